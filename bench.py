@@ -1,0 +1,166 @@
+"""Throughput of the full SDMD PIC step on one MI355X.
+
+Default workload: the laser-wakefield-shaped 2D3V run -- 2048 x 256 cells,
+dx = 0.125, dy = 0.5, vacuum / 256-cell linear ramp / plateau n = 0.005,
+16 cold particles per cell (3,932,160 particles), Gaussian laser a0 = 2,
+16 x 16-cell patches, 4 regions of 512 x 256, FP32 split-position particles
+with FP64 region reduction and Maxwell.  Synthetic seeded input.
+
+Prints one JSON line: particle-pushes/s of the whole step (all phases: patch
+field window, interpolation, Boris, Esirkepov deposition, patch -> region
+current sum, Yee, region ghosts, re-binning), the roofline of the dominant
+kernel (the particle kernel, HBM-bound) measured with HIP events on the
+library's stream, and the FP64 CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    from paper_1912_04064_amd import workloads as WL
+    if name == "lwfa":
+        return WL.lwfa_2d()
+    if name == "lwfa64":
+        return WL.lwfa_2d(precision="fp64")
+    if name == "thermal64":
+        return WL.thermal_2d()
+    if name == "cyl3d":
+        return WL.cylinder_3d()
+    if name == "cyl3d_small":
+        return WL.cylinder_3d(n=(128, 32, 32), radius=4.0)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def particle_bytes(wl):
+    """Algorithmic HBM bytes per particle per step of the particle kernel:
+    read cell (2 B, split form) + position + momentum + weight, write cell +
+    position + momentum."""
+    r = 4 if wl.precision == "fp32s" else 8
+    cell = 2 if wl.precision == "fp32s" else 0
+    rd = cell + wl.dims * r + 3 * r + r
+    wr = cell + wl.dims * r + 3 * r
+    return rd + wr
+
+
+def cpu_baseline(wl_name, budget_s=20.0):
+    """The FP64 oracle (single thread) on a bounded sample of the same
+    workload: a horizontal band of the grid with its particles, full steps."""
+    import oracle as O
+    from paper_1912_04064_amd import workloads as WL
+    if wl_name.startswith("lwfa"):
+        # the plasma band of the run: 256 x 256 cells of plateau + ramp
+        wl = WL.lwfa_2d(n=(512, 256), vac_end=64, ramp=256, x0=68.0)
+        sample = "lwfa band 512x256 cells (ramp+plateau, 16 ppc)"
+    elif wl_name.startswith("cyl"):
+        wl = WL.cylinder_3d(n=(32, 32, 32), radius=8.0)
+        sample = "cylinder 32^3 cells (8 ppc + 16x cylinder)"
+    else:
+        wl = workload(wl_name)
+        sample = wl.name
+    from tests.helpers import oracle_state
+    g, F, P = oracle_state(wl)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        O.step_sdsd(g, F, P)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s or steps >= 50:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": P.n * steps / dt, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}: {P.n} particles x {steps} steps in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="lwfa")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--phase-samples", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
+              "(one region per GPU) is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1912_04064_amd import binding as B
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU")
+    wl = workload(args.workload)
+    N = wl.n_particles
+    ncell = wl.n_cells
+    print(f"[bench] workload {wl.name}: {N} particles, {ncell} cells, {wl.precision}", file=sys.stderr, flush=True)
+    ctx = B.Context([wl], graph=not args.no_graph)
+    ctx.step(args.warmup)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup {args.warmup} steps done", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ctx.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = N * args.steps / (t1 - t0)
+    print(f"[bench] timed {args.steps} steps: {ms:.4f} ms/step", file=sys.stderr, flush=True)
+
+    # dominant kernel: HIP events around the particle kernel, same stream
+    push_ms, yee_ms, post_ms = [], [], []
+    for _ in range(args.phase_samples):
+        ctx.time_phases()
+        t = ctx.diag(0)["t_ms"]
+        push_ms.append(t[0])
+        yee_ms.append(t[1])
+        post_ms.append(t[2])
+    d = ctx.diag(0)
+    push_avg = float(np.mean(push_ms))
+    pb = particle_bytes(wl)
+    alg_push = N * pb + ncell * 48          # particles + the FP64 E, Bm window (transfer ii)
+    achieved = alg_push / (push_avg * 1e-3) / 1e9
+    step_bytes = N * pb + ncell * 216
+    ctx.close()
+
+    out = {
+        "metric": "particle-pushes/s (full SDMD step)",
+        "value": value,
+        "unit": "particle-pushes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if wl.precision == "fp32s" else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "cells": list(wl.n), "particles": N, "patch": list(d["patch"][:wl.dims]),
+                   "regions": list(wl.nreg), "precision": wl.precision, "graph": not args.no_graph},
+        "step_hbm_GBps_algorithmic": step_bytes / (ms * 1e-3) / 1e9,
+        "phase_ms": {"particles": push_avg, "reduce_maxwell": float(np.mean(yee_ms)),
+                     "sync_rebin": float(np.mean(post_ms))},
+        "roofline": {"bound": "hbm", "kernel": "push_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": alg_push},
+        "relayouts": d["n_relayout"],
+    }
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

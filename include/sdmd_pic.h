@@ -1,0 +1,249 @@
+/*
+ * sdmd_pic.h -- C ABI of the MI355X (gfx950) SDMD particle-in-cell library.
+ *
+ * The library implements the data-parallel core of the Single Domain Multiple
+ * Decompositions method (Derouillat & Beck): one physical domain carried by two
+ * decompositions at once (section 2.2).  Small *patches* own the
+ * macro-particles; large *regions* own the fields.  One step is
+ *
+ *   particles on patches: field interpolation, push, charge-conserving
+ *   deposition into a patch-local current tile   (section 3.3, "Particles")
+ *   transfer (i): patch currents summed into the regions         (section 2.2)
+ *   Maxwell (Yee) update on the regions             (section 3.3, "Fields")
+ *   region ghost synchronisation                     (section 2.1, "Sync")
+ *   transfer (ii): region fields read by the patches             (section 2.2)
+ *   re-binning of the particles that left their patch  (section 2.1, "Sync")
+ *
+ * Equations (normalised units, c = 1): dE/dt = curl B - J, dB/dt = -curl E,
+ * du/dt = (q/m)(E + u x B / gamma), dx/dt = u / gamma.  Second-order
+ * (quadratic B-spline) shapes and the Esirkepov scheme (section 3.2), Boris
+ * push, Yee staggered grid (section 3.2), periodic boundaries.
+ *
+ * Conventions for every function:
+ *   - return 0 (PIC_OK) or a negative PIC_E_* code; no exception crosses the ABI;
+ *   - host pointers are plain host memory owned by the caller; the library
+ *     copies what it needs and keeps no reference to caller memory after the
+ *     call returns;
+ *   - device memory is obtained through pic_runtime.alloc / .free (or
+ *     hipMalloc / hipFree when those are null) and is owned by the context
+ *     until pic_retire / pic_free;
+ *   - work is enqueued on pic_runtime.stream in order; pic_step is
+ *     asynchronous, pic_fields / pic_diag / pic_particles synchronise the
+ *     stream.  Device-side errors (non-finite values, a particle moving a cell
+ *     or more in one step) are reported by the next synchronising call;
+ *   - one host thread at a time per context.
+ *
+ * Field arrays crossing the ABI are FP64, layout [component][z][y][x] with x
+ * fastest, no ghost cells, the whole domain (region-assembled).  Staggering
+ * (position of index (i,j,k) in cell units):
+ *   Ex (i+1/2, j, k)  Ey (i, j+1/2, k)  Ez (i, j, k+1/2)   J like E
+ *   Bx (i, j+1/2, k+1/2)  By (i+1/2, j, k+1/2)  Bz (i+1/2, j+1/2, k)
+ * In 2D3V (dims = 2) there is no z axis: nz = 1 and Ez, Jz sit on (i, j).
+ */
+#ifndef SDMD_PIC_H
+#define SDMD_PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define PIC_OK          0
+#define PIC_E_INVAL    -1  /* null pointer, bad run index or argument        */
+#define PIC_E_CONFIG   -2  /* configuration breaks a rule listed at pic_init  */
+#define PIC_E_NOMEM    -3  /* allocation failed or HBM budget exceeded        */
+#define PIC_E_DEVICE   -4  /* HIP runtime error; text in pic_last_error      */
+#define PIC_E_NUMERIC  -5  /* non-finite value or a move of >= 1 cell a step */
+#define PIC_E_CAPACITY -6  /* no free run slot                               */
+#define PIC_E_STATE    -7  /* call not valid in the current state            */
+
+/* ---- enums -------------------------------------------------------------- */
+#define PIC_FP64        0  /* everything in FP64                             */
+#define PIC_FP32_SPLIT  1  /* particles: FP32 with a split position (integer
+                              cell + FP32 offset in [0,1)), FP32 patch tiles;
+                              region reduction and Maxwell in FP64           */
+#define PIC_BC_PERIODIC 0
+
+/* pic_fields component mask bits */
+#define PIC_F_EX   (1u << 0)
+#define PIC_F_EY   (1u << 1)
+#define PIC_F_EZ   (1u << 2)
+#define PIC_F_BX   (1u << 3)   /* Bm: B time-centred at t^n                   */
+#define PIC_F_BY   (1u << 4)
+#define PIC_F_BZ   (1u << 5)
+#define PIC_F_BHX  (1u << 6)   /* B at t^{n+1/2} (needed to resume a run)    */
+#define PIC_F_BHY  (1u << 7)
+#define PIC_F_BHZ  (1u << 8)
+#define PIC_F_JX   (1u << 9)   /* J at t^{n-1/2}, from the last step          */
+#define PIC_F_JY   (1u << 10)
+#define PIC_F_JZ   (1u << 11)
+#define PIC_F_RHO  (1u << 12)  /* electron charge density at t^n (deposited on
+                                  demand; the ion background is not included) */
+
+/* pic_runtime.flags */
+#define PIC_RT_NO_GRAPH   (1 << 0)  /* launch kernels one by one instead of
+                                       replaying a captured hipGraph          */
+#define PIC_RT_PERSISTENT (1 << 1)  /* particle phase as one persistent launch
+                                       with work stealing over patches        */
+
+typedef struct pic_ctx pic_ctx;
+
+/* Initial particles, host memory, FP64 SoA, length n each.  Positions must
+ * lie in [0, L) per axis (L = n_cells * d); z is ignored when dims = 2.
+ * Momenta are u = gamma v at t^{-1/2}.  w is the particle's share of the
+ * density (density of its cell divided by particles per cell), so the
+ * electron charge density is rho = sum q w S.  id may be null (ids are then
+ * 0..n-1); ids travel with the particle only when track_ids is set. */
+typedef struct {
+    int64_t n;
+    const double *x, *y, *z;
+    const double *ux, *uy, *uz;
+    const double *w;
+    const uint32_t *id;
+} pic_particles_in;
+
+/* Initial fields, host memory, FP64, 3 components each in the layout above.
+ * kind 0: E and B at t = 0; the library sets B^{1/2} = B^0 - dt/2 curl E^0
+ *         and Bm^0 = B^0 (no momentum pull-back: u is taken as u^{-1/2}).
+ * kind 1: E at t^n, B at t^{n+1/2} and Bm at t^n (a resumed state); Bm may
+ *         be null, then Bm = B. */
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    const double *E, *B, *Bm;
+} pic_fields_in;
+
+/* One run.  Rules checked by pic_init / pic_admit (PIC_E_CONFIG):
+ *   dims is 2 or 3; every n_cells[a] >= 1 (n_cells[2] = 1 when dims = 2);
+ *   d[a] > 0 and 0 < dt < 1 / sqrt(sum 1/d[a]^2) (Courant limit);
+ *   patch[a] >= 4 -- a patch holds at least the interpolation support
+ *     (section 2.1; the smallest patches of section 3.4 are 8 x 7 cells) --
+ *     patch[a] <= 32 (2D) or 8 (3D), and patch[a] divides n_cells[a];
+ *     patch[a] = 0 on every axis asks the autotuner to choose;
+ *   regions are rectangular, of equal shape, and made of whole patches
+ *     (section 2.2, rule B): n_regions[a] >= 1 divides n_cells[a]/patch[a];
+ *   shape_order is 2; bc[a] is PIC_BC_PERIODIC; m > 0. */
+typedef struct {
+    int32_t dims;
+    int32_t n_cells[3];
+    double  d[3];
+    double  dt;
+    int32_t patch[3];
+    int32_t n_regions[3];
+    int32_t shape_order;
+    int32_t precision;          /* PIC_FP64 or PIC_FP32_SPLIT */
+    int32_t bc[3];
+    int32_t track_ids;          /* carry ids through steps (pic_particles)  */
+    double  q, m;               /* species charge and mass; electrons -1, 1 */
+    const pic_particles_in *particles;   /* may be null: no particles      */
+    const pic_fields_in    *fields;      /* may be null: zero fields       */
+} pic_config;
+
+/* Where device memory and work go.  alloc(bytes, stream, user) returns
+ * device memory or null; free(ptr, bytes, stream, user) releases it.  Both
+ * null: hipMalloc / hipFree.  stream: a hipStream_t (null = null stream).
+ * hbm_budget: bytes the context may hold in total (0 = unlimited).
+ * max_runs: run slots for pic_admit (0 = the n_runs given to pic_init). */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *ptr, size_t bytes, void *stream, void *user);
+    void   *stream;
+    void   *user;
+    size_t  hbm_budget;
+    int32_t max_runs;
+    int32_t flags;              /* PIC_RT_* */
+} pic_runtime;
+
+/* Diagnostics of one run at its current step.  t_ms: wall time of the
+ * phases of the last timed step (pic_time_phases), order Particles,
+ * SyncDec-i + Fields (fused), Sync (ghosts + re-binning), Relayout. */
+typedef struct {
+    int64_t step;
+    double  t;
+    int64_t n_particles;
+    int64_t patch_min, patch_max;     /* particles per patch */
+    double  patch_mean;
+    double  U_E, U_B, K;              /* 1/2 sum E^2 dV, 1/2 sum Bm^2 dV,
+                                         sum m w (gamma - 1) dV            */
+    double  t_ms[4];
+    int64_t n_relayout;               /* device re-layouts of the particle
+                                         store since pic_init              */
+    int64_t n_spill;                  /* particles parked outside their
+                                         patch segment right now           */
+    int32_t err_flags;                /* bit 0 non-finite, bit 1 move >= 1
+                                         cell, bit 2 capacity overflow     */
+    int32_t patch[3];                 /* patch shape in use                */
+} pic_diag_t;
+
+/* Particle export (host memory, caller owned).  capacity is the length of
+ * every non-null array; n receives the particle count (PIC_E_INVAL with n
+ * set if capacity is too small).  Order is the storage order (patch by
+ * patch); positions are FP64 in [0, L); patch receives each particle's
+ * patch index (x fastest over patches). */
+typedef struct {
+    int64_t capacity;
+    int64_t n;
+    double *x, *y, *z, *ux, *uy, *uz, *w;
+    uint32_t *id;
+    int32_t *patch;
+} pic_particles_out;
+
+/* Create a context holding n_runs independent runs (section 2.2 problem
+ * statement per run) and bin their particles into patches.  Configs are
+ * read and copied; *out receives the context.  With PIC_E_CONFIG the text
+ * of the broken rule is in pic_last_error(NULL). */
+int pic_init(const pic_config *cfgs, int32_t n_runs, const pic_runtime *rt, pic_ctx **out);
+
+/* Enqueue n_steps SDMD steps for every active run on rt->stream (async). */
+int pic_step(pic_ctx *ctx, int32_t n_steps);
+
+/* Copy the fields of `run` selected by `mask` (PIC_F_*) into dst,
+ * components in bit order, each nx*ny*nz FP64 values, layout above.
+ * dst_len is the capacity of dst in doubles; dst_on_device != 0 means dst is
+ * device memory.  Synchronises the stream. */
+int pic_fields(pic_ctx *ctx, int32_t run, uint32_t mask, double *dst, size_t dst_len, int32_t dst_on_device);
+
+/* Fill *out for `run`.  Synchronises the stream. */
+int pic_diag(pic_ctx *ctx, int32_t run, pic_diag_t *out);
+
+/* Export the particles of `run` (see pic_particles_out). Synchronises. */
+int pic_particles(pic_ctx *ctx, int32_t run, pic_particles_out *out);
+
+/* Device bytes pic_init / pic_admit would take for this config (admission
+ * by HBM budget).  Does not touch the GPU. */
+int pic_mem_bytes(const pic_config *cfg, size_t *bytes);
+
+/* Add a run to a live context (continuous batching); *run_id receives its
+ * slot.  PIC_E_CAPACITY if every slot is taken, PIC_E_NOMEM if the budget
+ * would be exceeded.  The new run advances with the next pic_step. */
+int pic_admit(pic_ctx *ctx, const pic_config *cfg, int32_t *run_id);
+
+/* Release a run's slot and device memory.  Its results must have been read
+ * before.  Enqueued work is drained first. */
+int pic_retire(pic_ctx *ctx, int32_t run);
+
+/* Number of steps `run` has taken (host counter, no synchronisation). */
+int pic_run_steps(pic_ctx *ctx, int32_t run, int64_t *steps);
+
+/* Time one step phase by phase with HIP events (synchronising, for the
+ * diagnostics' t_ms); the step is a normal step of every active run. */
+int pic_time_phases(pic_ctx *ctx);
+
+/* Release everything.  Null is allowed. */
+void pic_free(pic_ctx *ctx);
+
+/* Static text for an error code. */
+const char *pic_strerror(int code);
+
+/* Text of the last error of ctx (or of the last failed pic_init when ctx is
+ * null).  Valid until the next call on the same context. */
+const char *pic_last_error(pic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDMD_PIC_H */

@@ -1,0 +1,1051 @@
+// host.cpp -- C-ABI implementation and host runtime of the SDMD PIC library.
+//
+// A context holds up to max_runs independent runs in a device run table.
+// Runs of the same dimensionality, precision and patch class share one
+// launch per phase, so a step is three launches per class whatever the
+// number of runs:
+//   push  (one workgroup per patch of every run)       -- particles phase
+//   yee   (one workgroup per region tile of every run) -- transfer (i) + Maxwell
+//   post  (ghost chunks + leaver insertion)            -- Sync
+// and every `relayout_every` steps a re-layout check (three launches that
+// exit at once unless some patch overflowed).  The two-step sequence
+// (E/B buffer parity 0 then 1) is captured once in a hipGraph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "launch.h"
+#include "sdmd_dev.h"
+#include "sdmd_pic.h"
+
+using namespace sdmd;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Run {
+    bool active = false;
+    int dims = 2, prec = PIC_FP64, pc = 8;
+    bool split = false;
+    int ncell = 0;
+    int total_ghosts = 0;
+    int64_t steps = 0;
+    size_t bytes = 0;
+    RunDev rd{};
+    std::vector<DevBuf> bufs;
+};
+
+struct PushClass {
+    int dims, pc;
+    bool split;
+    std::vector<int2> h;
+    int2 *d = nullptr;
+    size_t cap = 0;
+};
+
+struct FieldClass {
+    int dims;
+    bool split;
+    std::vector<int4> hy, hp;
+    std::vector<int> slots;
+    int4 *dy = nullptr, *dp = nullptr;
+    int *dslots = nullptr;
+    size_t capy = 0, capp = 0, caps = 0;
+    int move_gx = 1, commit_gx = 1;
+};
+
+}  // namespace
+
+struct pic_ctx {
+    pic_runtime rt{};
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int max_runs = 0;
+    std::vector<Run> runs;
+    RunDev *d_runs = nullptr;
+    int *d_slot1 = nullptr;   // one slot, for single-run re-layouts
+    std::vector<PushClass> pcls;
+    std::vector<FieldClass> fcls;
+    std::vector<DevBuf> own;   // context-level buffers
+    int par = 0;
+    int64_t step = 0;
+    int relayout_every = 16;
+    bool use_graph = true;
+    hipGraphExec_t g2 = nullptr;      // two steps
+    hipGraphExec_t grel = nullptr;    // re-layout check
+    bool graphs_valid = false;
+    size_t bytes = 0;
+    std::string err;
+    double t_ms[4] = {0, 0, 0, 0};
+};
+
+// ------------------------------------------------------------------ errors
+static int set_err(pic_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_init_error = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                                  \
+    do {                                                                                                   \
+        hipError_t e_ = (expr);                                                                            \
+        if (e_ != hipSuccess) return set_err(ctx, PIC_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+// ------------------------------------------------------------------ memory
+static void *dev_alloc(pic_ctx *c, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if (c->rt.alloc) {
+        p = c->rt.alloc(bytes, c->rt.stream, c->rt.user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) c->bytes += bytes;
+    return p;
+}
+
+static void dev_free(pic_ctx *c, DevBuf &b)
+{
+    if (!b.p) return;
+    if (c->rt.free)
+        c->rt.free(b.p, b.bytes, c->rt.stream, c->rt.user);
+    else
+        hipFree(b.p);
+    c->bytes -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+static void *run_alloc(pic_ctx *c, Run &r, size_t bytes)
+{
+    size_t b = bytes == 0 ? 256 : ((bytes + 255) & ~(size_t)255);
+    void *p = dev_alloc(c, b);
+    if (p) r.bufs.push_back({p, b});
+    return p;
+}
+
+// ------------------------------------------------------------------ layout
+struct Layout {
+    int dims, pc;
+    bool split;
+    int n[3], P[3], np[3], nreg[3], rs[3], ra[3], TA[3];
+    int n_patch, n_regions, tsz, ghosts;
+    long long rsize;
+    long long n_total, cap_total;
+    size_t bytes;
+};
+
+static int patch_class(int dims, const int P[3])
+{
+    int m = std::max(P[0], P[1]);
+    if (dims == 3) m = std::max(m, P[2]);
+    if (m <= 8) return 8;
+    if (m <= 16) return 16;
+    return 32;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// validate a config (patch already chosen) and derive the layout
+static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::string &why)
+{
+    char buf[256];
+    auto fail = [&](const char *m) {
+        why = m;
+        return PIC_E_CONFIG;
+    };
+    const int dims = cfg->dims;
+    if (dims != 2 && dims != 3) return fail("dims must be 2 or 3");
+    if (cfg->shape_order != 2) return fail("shape_order must be 2 (quadratic shapes, Esirkepov 5-point frame)");
+    if (cfg->precision != PIC_FP64 && cfg->precision != PIC_FP32_SPLIT) return fail("unknown precision");
+    if (!(cfg->m > 0)) return fail("mass must be positive");
+    double inv2 = 0.0;
+    for (int a = 0; a < dims; ++a) {
+        if (cfg->bc[a] != PIC_BC_PERIODIC) return fail("only periodic boundaries are supported");
+        if (cfg->n_cells[a] < 1) return fail("n_cells must be >= 1");
+        if (!(cfg->d[a] > 0)) return fail("cell sizes must be positive");
+        inv2 += 1.0 / (cfg->d[a] * cfg->d[a]);
+    }
+    if (dims == 2 && cfg->n_cells[2] != 1) return fail("n_cells[2] must be 1 in 2D");
+    if (!(cfg->dt > 0) || !(cfg->dt < 1.0 / std::sqrt(inv2))) return fail("dt must satisfy 0 < dt < 1/sqrt(sum 1/d^2)");
+    const int pmax = dims == 2 ? 32 : 8;
+    L.dims = dims;
+    L.split = cfg->precision == PIC_FP32_SPLIT;
+    long long ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a >= dims) {
+            L.n[a] = 1;
+            L.P[a] = 1;
+            L.np[a] = 1;
+            L.nreg[a] = 1;
+            L.rs[a] = 1;
+            L.ra[a] = 1;
+            L.TA[a] = 1;
+            continue;
+        }
+        L.n[a] = cfg->n_cells[a];
+        L.P[a] = P[a];
+        if (P[a] < 4) return fail("patch size must be >= 4 cells per axis (a patch holds the interpolation support)");
+        if (P[a] > pmax) {
+            snprintf(buf, sizeof buf, "patch size must be <= %d cells per axis in %dD", pmax, dims);
+            why = buf;
+            return PIC_E_CONFIG;
+        }
+        if (L.n[a] % P[a]) return fail("patch size must divide n_cells");
+        L.np[a] = L.n[a] / P[a];
+        const int nr = cfg->n_regions[a] < 1 ? 1 : cfg->n_regions[a];
+        if (L.np[a] % nr) return fail("regions must be made of whole patches and all of equal shape");
+        L.nreg[a] = nr;
+        L.rs[a] = L.n[a] / nr;
+        L.ra[a] = L.rs[a] + 2 * GH;
+        L.TA[a] = P[a] + 5;
+        ncell *= L.n[a];
+    }
+    if (ncell > (1LL << 31) - 1) return fail("grid too large");
+    L.pc = patch_class(dims, L.P);
+    L.n_patch = L.np[0] * L.np[1] * L.np[2];
+    L.n_regions = L.nreg[0] * L.nreg[1] * L.nreg[2];
+    L.rsize = (long long)L.ra[0] * L.ra[1] * L.ra[2];
+    L.tsz = L.TA[0] * L.TA[1] * L.TA[2];
+    const int G2 = 2 * GH;
+    if (dims == 2)
+        L.ghosts = G2 * L.ra[0] + G2 * L.rs[1];
+    else
+        L.ghosts = G2 * L.ra[0] * L.ra[1] + L.rs[2] * G2 * L.ra[0] + L.rs[2] * L.rs[1] * G2;
+    L.n_total = cfg->particles ? cfg->particles->n : 0;
+    if (L.n_total < 0) return fail("negative particle count");
+    L.cap_total = L.n_total + L.n_total / 4 + 16LL * L.n_patch + 1024;
+    if (L.cap_total > (1LL << 31) - 1) return fail("too many particles for one run");
+    // bytes
+    const size_t rsz = L.split ? 4 : 8;
+    const bool ids = cfg->track_ids != 0;
+    const size_t per = dims * rsz + (L.split ? 2 : 0) + 3 * rsz + rsz + (ids ? 4 : 0);
+    size_t b = 0;
+    b += align256((size_t)L.n_regions * F_NCOMP * L.rsize * 8);
+    b += align256((size_t)L.n_patch * 3 * L.tsz * rsz);
+    b += 5 * align256((size_t)(L.n_patch + 1) * 4);
+    b += 2 * (size_t)L.cap_total * per + align256((size_t)L.cap_total * 4);
+    b += (size_t)std::max<long long>(L.n_total, 1) * (per + 4);
+    b += 64 * 256;   // per-array rounding and the control block
+    L.bytes = b;
+    return PIC_OK;
+}
+
+// default patch shape when the caller leaves it to the library: the
+// measured choice for 2D is 16 cells (8 for small grids); 3D uses 8
+static void default_patch(const pic_config *cfg, int P[3])
+{
+    const int dims = cfg->dims;
+    for (int a = 0; a < 3; ++a) P[a] = 1;
+    const int cands2[] = {16, 8, 32, 12, 10, 4};
+    const int cands3[] = {8, 4, 6};
+    for (int a = 0; a < dims; ++a) {
+        const int nr = cfg->n_regions[a] < 1 ? 1 : cfg->n_regions[a];
+        const int *c = dims == 2 ? cands2 : cands3;
+        const int nc = dims == 2 ? 6 : 3;
+        P[a] = 0;
+        for (int i = 0; i < nc; ++i)
+            if (cfg->n_cells[a] % (c[i] * nr) == 0) {
+                P[a] = c[i];
+                break;
+            }
+    }
+}
+
+// ------------------------------------------------------------------ run setup
+static void free_run(pic_ctx *c, Run &r)
+{
+    for (auto &b : r.bufs) dev_free(c, b);
+    r.bufs.clear();
+    r.active = false;
+}
+
+static void make_store(pic_ctx *c, Run &r, Store &s, long long n, bool split, int dims, bool ids, bool &ok)
+{
+    const size_t rsz = split ? 4 : 8;
+    const size_t nn = (size_t)std::max<long long>(n, 1);
+    for (int a = 0; a < 3; ++a) s.pos[a] = a < dims ? run_alloc(c, r, nn * rsz) : nullptr;
+    s.cell = split ? (uint16_t *)run_alloc(c, r, nn * 2) : nullptr;
+    for (int a = 0; a < 3; ++a) s.u[a] = run_alloc(c, r, nn * rsz);
+    s.w = run_alloc(c, r, nn * rsz);
+    s.id = ids ? (uint32_t *)run_alloc(c, r, nn * 4) : nullptr;
+    for (int a = 0; a < dims; ++a) ok = ok && s.pos[a];
+    ok = ok && s.u[0] && s.u[1] && s.u[2] && s.w && (!split || s.cell) && (!ids || s.id);
+}
+
+static int upload_rd(pic_ctx *c, int slot)
+{
+    HIPCHK(c, hipMemcpyAsync(c->d_runs + slot, &c->runs[slot].rd, sizeof(RunDev), hipMemcpyHostToDevice, c->stream));
+    return PIC_OK;
+}
+
+static Ctl read_ctl(pic_ctx *c, int slot, hipError_t &e)
+{
+    Ctl ctl;
+    memset(&ctl, 0, sizeof ctl);
+    e = hipMemcpy(&ctl, c->runs[slot].rd.ctl, sizeof ctl, hipMemcpyDeviceToHost);
+    ctl.nspill = std::max(0, std::min(ctl.nspill, c->runs[slot].rd.n_total));
+    return ctl;
+}
+
+static int check_run_err(pic_ctx *c, int slot, int *flags_out = nullptr)
+{
+    Ctl ctl;
+    HIPCHK(c, hipMemcpyAsync(&ctl, c->runs[slot].rd.ctl, sizeof ctl, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (flags_out) *flags_out = ctl.err;
+    if (ctl.err & ERR_RANGE) return set_err(c, PIC_E_CONFIG, "run %d: particle position outside [0, L)", slot);
+    if (ctl.err & ERR_NONFINITE) return set_err(c, PIC_E_NUMERIC, "run %d: non-finite particle value", slot);
+    if (ctl.err & ERR_MOVE) return set_err(c, PIC_E_NUMERIC, "run %d: a particle moved a cell or more in one step", slot);
+    if (ctl.err & ERR_CAPACITY) return set_err(c, PIC_E_NUMERIC, "run %d: particle store capacity exceeded", slot);
+    return PIC_OK;
+}
+
+static int relayout_one(pic_ctx *c, int slot, int force)
+{
+    Run &r = c->runs[slot];
+    HIPCHK(c, hipMemcpyAsync(c->d_slot1, &slot, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    const int nsb = std::max(1, std::min(1024, (int)(r.rd.n_total / (BLOCK * 64))));
+    int cb = (int)std::min<long long>(4096, std::max<long long>(1, (r.rd.cap_total + BLOCK - 1) / BLOCK));
+    HIPCHK(c, launch_relayout(r.dims, r.split, c->d_runs, c->d_slot1, 1, r.rd.n_patch + nsb, cb, force, c->stream));
+    return PIC_OK;
+}
+
+static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
+{
+    Run &r = c->runs[slot];
+    int P[3] = {cfg->patch[0], cfg->patch[1], cfg->patch[2]};
+    if (P[0] == 0 && P[1] == 0 && (cfg->dims == 2 || P[2] == 0)) default_patch(cfg, P);
+    Layout L;
+    std::string why;
+    int rc = make_layout(cfg, P, L, why);
+    if (rc) return set_err(c, rc, "%s", why.c_str());
+    if (c->rt.hbm_budget && c->bytes + L.bytes > c->rt.hbm_budget)
+        return set_err(c, PIC_E_NOMEM, "HBM budget exceeded (%zu + %zu > %zu)", c->bytes, L.bytes, c->rt.hbm_budget);
+
+    r = Run();
+    r.dims = L.dims;
+    r.split = L.split;
+    r.prec = cfg->precision;
+    r.pc = L.pc;
+    r.ncell = L.n[0] * L.n[1] * L.n[2];
+    r.total_ghosts = L.ghosts * L.n_regions;
+    RunDev &d = r.rd;
+    memset(&d, 0, sizeof d);
+    d.dims = L.dims;
+    d.prec = cfg->precision;
+    for (int a = 0; a < 3; ++a) {
+        d.n[a] = L.n[a];
+        d.P[a] = L.P[a];
+        d.np[a] = L.np[a];
+        d.nreg[a] = L.nreg[a];
+        d.rs[a] = L.rs[a];
+        d.ra[a] = L.ra[a];
+        d.TA[a] = L.TA[a];
+        d.d[a] = a < L.dims ? cfg->d[a] : 1.0;
+        d.L[a] = d.n[a] * d.d[a];
+    }
+    d.n_patch = L.n_patch;
+    d.n_regions = L.n_regions;
+    d.rsize = L.rsize;
+    d.tsz = L.tsz;
+    d.cap_total = (int)L.cap_total;
+    d.n_total = (int)L.n_total;
+    d.ins_blocks = std::max(1, std::min(1024, (int)(L.n_total / 8192)));
+    d.ghosts = L.ghosts;
+    d.dt = cfg->dt;
+    d.q = cfg->q;
+    d.m = cfg->m;
+    d.qmh = 0.5 * cfg->q / cfg->m * cfg->dt;
+    d.f_qmh = (float)d.qmh;
+    d.f_q = (float)cfg->q;
+    for (int a = 0; a < 3; ++a) {
+        d.f_dtd[a] = (float)(cfg->dt / d.d[a]);
+        d.f_cj[a] = (float)(-cfg->q * d.d[a] / cfg->dt);
+    }
+    const size_t rsz = L.split ? 4 : 8;
+    const bool ids = cfg->track_ids != 0;
+    bool ok = true;
+    d.fld = (double *)run_alloc(c, r, (size_t)L.n_regions * F_NCOMP * L.rsize * 8);
+    d.tiles = run_alloc(c, r, (size_t)L.n_patch * 3 * L.tsz * rsz);
+    d.seg = (int *)run_alloc(c, r, (size_t)(L.n_patch + 1) * 4);
+    d.cnt = (int *)run_alloc(c, r, (size_t)(L.n_patch + 1) * 4);
+    d.seg2 = (int *)run_alloc(c, r, (size_t)(L.n_patch + 1) * 4);
+    d.tot = (int *)run_alloc(c, r, (size_t)(L.n_patch + 1) * 4);
+    d.fill = (int *)run_alloc(c, r, (size_t)(L.n_patch + 1) * 4);
+    d.ctl = (Ctl *)run_alloc(c, r, sizeof(Ctl));
+    ok = d.fld && d.tiles && d.seg && d.cnt && d.seg2 && d.tot && d.fill && d.ctl;
+    make_store(c, r, d.st, L.cap_total, L.split, L.dims, ids, ok);
+    make_store(c, r, d.lv, L.cap_total, L.split, L.dims, ids, ok);
+    make_store(c, r, d.sp, L.n_total, L.split, L.dims, ids, ok);
+    d.lpatch = (int *)run_alloc(c, r, (size_t)L.cap_total * 4);
+    d.spatch = (int *)run_alloc(c, r, (size_t)std::max<long long>(L.n_total, 1) * 4);
+    ok = ok && d.lpatch && d.spatch;
+    r.bytes = 0;
+    for (auto &b : r.bufs) r.bytes += b.bytes;
+    if (!ok) {
+        free_run(c, r);
+        return set_err(c, PIC_E_NOMEM, "device allocation failed");
+    }
+    r.active = true;
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemsetAsync(d.fld, 0, (size_t)L.n_regions * F_NCOMP * L.rsize * 8, s));
+    HIPCHK(c, hipMemsetAsync(d.tiles, 0, (size_t)L.n_patch * 3 * L.tsz * rsz, s));
+    HIPCHK(c, hipMemsetAsync(d.seg, 0, (size_t)(L.n_patch + 1) * 4, s));
+    HIPCHK(c, hipMemsetAsync(d.cnt, 0, (size_t)(L.n_patch + 1) * 4, s));
+    HIPCHK(c, hipMemsetAsync(d.ctl, 0, sizeof(Ctl), s));
+    if ((rc = upload_rd(c, slot))) return rc;
+
+    // fields
+    const int par = c->par;
+    const int ncell = r.ncell;
+    if (cfg->fields) {
+        const pic_fields_in *f = cfg->fields;
+        if (!f->E || !f->B || (f->kind != 0 && f->kind != 1)) return set_err(c, PIC_E_INVAL, "fields: E and B required, kind 0 or 1");
+        double *stg = (double *)dev_alloc(c, (size_t)3 * ncell * 8);
+        if (!stg) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
+        DevBuf sb{stg, align256((size_t)3 * ncell * 8)};
+        auto up = [&](const double *src, int c0) -> int {
+            HIPCHK(c, hipMemcpyAsync(stg, src, (size_t)3 * ncell * 8, hipMemcpyHostToDevice, s));
+            HIPCHK(c, launch_scatter_fields(c->d_runs, slot, ncell, stg, c0, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            return PIC_OK;
+        };
+        if ((rc = up(f->E, f_E(par)))) return rc;
+        if ((rc = up(f->B, f_B(par)))) return rc;
+        if (f->kind == 1) {
+            if ((rc = up(f->Bm ? f->Bm : f->B, F_BM))) return rc;
+        }
+        dev_free(c, sb);
+        HIPCHK(c, launch_ghosts(c->d_runs, slot, r.total_ghosts, f_E(par), 3, s));
+        HIPCHK(c, launch_ghosts(c->d_runs, slot, r.total_ghosts, f_B(par), 3, s));
+        if (f->kind == 0) HIPCHK(c, launch_half_faraday(c->d_runs, slot, ncell, par, s));
+        HIPCHK(c, launch_ghosts(c->d_runs, slot, r.total_ghosts, f_B(par), 3, s));
+        HIPCHK(c, launch_ghosts(c->d_runs, slot, r.total_ghosts, F_BM, 3, s));
+    }
+
+    // particles: FP64 staging -> spill store -> forced re-layout (binning)
+    const long long n = L.n_total;
+    if (n > 0) {
+        const pic_particles_in *p = cfg->particles;
+        if (!p->x || !p->y || (L.dims == 3 && !p->z) || !p->ux || !p->uy || !p->uz || !p->w)
+            return set_err(c, PIC_E_INVAL, "particles: x, y, (z), ux, uy, uz, w required");
+        const int nar = 7;
+        std::vector<DevBuf> st(nar + 1);
+        const double *src[7] = {p->x, p->y, L.dims == 3 ? p->z : p->x, p->ux, p->uy, p->uz, p->w};
+        double *dp[7];
+        for (int i = 0; i < nar; ++i) {
+            dp[i] = (double *)dev_alloc(c, (size_t)n * 8);
+            if (!dp[i]) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
+            st[i] = {dp[i], align256((size_t)n * 8)};
+            HIPCHK(c, hipMemcpyAsync(dp[i], src[i], (size_t)n * 8, hipMemcpyHostToDevice, s));
+        }
+        uint32_t *did = nullptr;
+        if (p->id) {
+            did = (uint32_t *)dev_alloc(c, (size_t)n * 4);
+            if (!did) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
+            st[nar] = {did, align256((size_t)n * 4)};
+            HIPCHK(c, hipMemcpyAsync(did, p->id, (size_t)n * 4, hipMemcpyHostToDevice, s));
+        }
+        HIPCHK(c, launch_convert(L.dims, L.split, c->d_runs, slot, (int)n, dp[0], dp[1], dp[2], dp[3], dp[4], dp[5],
+                                 dp[6], did, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        for (auto &b : st) dev_free(c, b);
+    }
+    if ((rc = relayout_one(c, slot, 1))) return rc;
+    if ((rc = check_run_err(c, slot))) {
+        free_run(c, r);
+        return rc;
+    }
+    r.steps = 0;
+    return PIC_OK;
+}
+
+// ------------------------------------------------------------------ classes
+template <class V>
+static int upload_vec(pic_ctx *c, const std::vector<V> &h, V *&d, size_t &cap)
+{
+    if (h.size() > cap || !d) {
+        for (auto it = c->own.begin(); it != c->own.end(); ++it)
+            if (it->p == d) {
+                dev_free(c, *it);
+                c->own.erase(it);
+                break;
+            }
+        cap = std::max<size_t>(h.size(), 1) * 2;
+        d = (V *)dev_alloc(c, cap * sizeof(V));
+        if (!d) return set_err(c, PIC_E_NOMEM, "item list allocation failed");
+        c->own.push_back({(void *)d, align256(cap * sizeof(V))});
+    }
+    if (!h.empty()) HIPCHK(c, hipMemcpyAsync(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice, c->stream));
+    return PIC_OK;
+}
+
+static int rebuild_items(pic_ctx *c)
+{
+    for (auto &pc : c->pcls) pc.h.clear();
+    for (auto &fc : c->fcls) {
+        fc.hy.clear();
+        fc.hp.clear();
+        fc.slots.clear();
+        fc.move_gx = 1;
+        fc.commit_gx = 1;
+    }
+    for (int slot = 0; slot < (int)c->runs.size(); ++slot) {
+        Run &r = c->runs[slot];
+        if (!r.active) continue;
+        PushClass *pc = nullptr;
+        for (auto &x : c->pcls)
+            if (x.dims == r.dims && x.split == r.split && x.pc == r.pc) pc = &x;
+        if (!pc) {
+            c->pcls.push_back(PushClass{r.dims, r.pc, r.split});
+            pc = &c->pcls.back();
+        }
+        FieldClass *fc = nullptr;
+        for (auto &x : c->fcls)
+            if (x.dims == r.dims && x.split == r.split) fc = &x;
+        if (!fc) {
+            c->fcls.push_back(FieldClass{r.dims, r.split});
+            fc = &c->fcls.back();
+        }
+        const RunDev &d = r.rd;
+        // push items: XCD-aware order -- workgroup i runs on XCD i % 8, so
+        // give each XCD a contiguous band of patches (shared window halos
+        // then hit the same L2)
+        const int np = d.n_patch;
+        const int band = (np + 7) / 8;
+        std::vector<char> seen(np, 0);
+        size_t base = pc->h.size();
+        pc->h.resize(base + np);
+        int k = 0;
+        for (int i = 0; k < np; ++i) {
+            const int xcd = i % 8, j = i / 8;
+            const int q = xcd * band + j;
+            if (j >= band || q >= np) {
+                if (i > 16 * np + 64) break;
+                continue;
+            }
+            pc->h[base + k++] = make_int2(slot, q);
+            seen[q] = 1;
+        }
+        for (int q = 0; q < np && k < np; ++q)
+            if (!seen[q]) pc->h[base + k++] = make_int2(slot, q);
+        // yee items
+        constexpr int TX2 = 64, TY2 = 4, TX3 = 32, TY3 = 4, TZ3 = 2;
+        const int tx = r.dims == 2 ? TX2 : TX3, ty = r.dims == 2 ? TY2 : TY3, tz = r.dims == 2 ? 1 : TZ3;
+        const int ntiles = ((d.rs[0] + tx - 1) / tx) * ((d.rs[1] + ty - 1) / ty) * ((d.rs[2] + tz - 1) / tz);
+        bool first = true;
+        for (int reg = 0; reg < d.n_regions; ++reg)
+            for (int t = 0; t < ntiles; ++t) {
+                fc->hy.push_back(make_int4(slot, reg, t, first ? 1 : 0));
+                first = false;
+            }
+        // post items
+        for (int g = 0; g < r.total_ghosts; g += BLOCK) fc->hp.push_back(make_int4(slot, 0, g, 0));
+        for (int b = 0; b < d.ins_blocks; ++b) fc->hp.push_back(make_int4(slot, 1, b, d.ins_blocks));
+        fc->slots.push_back(slot);
+        const int nsb = std::max(1, std::min(1024, (int)(d.n_total / (BLOCK * 64))));
+        fc->move_gx = std::max(fc->move_gx, d.n_patch + nsb);
+        fc->commit_gx = std::max(fc->commit_gx,
+                                 (int)std::min<long long>(4096, std::max<long long>(1, (d.cap_total + BLOCK - 1) / BLOCK)));
+    }
+    int rc;
+    for (auto &pc : c->pcls)
+        if ((rc = upload_vec(c, pc.h, pc.d, pc.cap))) return rc;
+    for (auto &fc : c->fcls) {
+        if ((rc = upload_vec(c, fc.hy, fc.dy, fc.capy))) return rc;
+        if ((rc = upload_vec(c, fc.hp, fc.dp, fc.capp))) return rc;
+        if ((rc = upload_vec(c, fc.slots, fc.dslots, fc.caps))) return rc;
+    }
+    c->graphs_valid = false;
+    return PIC_OK;
+}
+
+// ------------------------------------------------------------------ stepping
+static hipError_t enqueue_push(pic_ctx *c, int par, hipStream_t s)
+{
+    for (auto &pc : c->pcls) {
+        hipError_t e = launch_push(pc.dims, pc.split, pc.pc, c->d_runs, pc.d, (int)pc.h.size(), par, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static hipError_t enqueue_yee(pic_ctx *c, int par, hipStream_t s)
+{
+    for (auto &fc : c->fcls) {
+        hipError_t e = launch_yee(fc.dims, fc.split, c->d_runs, fc.dy, (int)fc.hy.size(), par, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static hipError_t enqueue_post(pic_ctx *c, int par, hipStream_t s)
+{
+    for (auto &fc : c->fcls) {
+        hipError_t e = launch_post(fc.dims, fc.split, c->d_runs, fc.dp, (int)fc.hp.size(), 1 - par, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static hipError_t enqueue_step(pic_ctx *c, int par, hipStream_t s)
+{
+    hipError_t e = enqueue_push(c, par, s);
+    if (e == hipSuccess) e = enqueue_yee(c, par, s);
+    if (e == hipSuccess) e = enqueue_post(c, par, s);
+    return e;
+}
+
+static hipError_t enqueue_relayout(pic_ctx *c, hipStream_t s)
+{
+    for (auto &fc : c->fcls) {
+        if (fc.slots.empty()) continue;
+        hipError_t e = launch_relayout(fc.dims, fc.split, c->d_runs, fc.dslots, (int)fc.slots.size(), fc.move_gx,
+                                       fc.commit_gx, 0, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static void drop_graphs(pic_ctx *c)
+{
+    if (c->g2) hipGraphExecDestroy(c->g2);
+    if (c->grel) hipGraphExecDestroy(c->grel);
+    c->g2 = c->grel = nullptr;
+    c->graphs_valid = false;
+}
+
+static int build_graphs(pic_ctx *c)
+{
+    drop_graphs(c);
+    if (!c->use_graph) return PIC_OK;
+    for (int k = 0; k < 2; ++k) {
+        hipGraph_t g = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = (k == 0) ? enqueue_step(c, 0, c->cap_stream) : enqueue_relayout(c, c->cap_stream);
+        if (e == hipSuccess && k == 0) e = enqueue_step(c, 1, c->cap_stream);
+        hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return set_err(c, PIC_E_DEVICE, "graph capture failed: %s",
+                           hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        hipGraphExec_t ex = nullptr;
+        hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e3 != hipSuccess) return set_err(c, PIC_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e3));
+        (k == 0 ? c->g2 : c->grel) = ex;
+    }
+    c->graphs_valid = true;
+    return PIC_OK;
+}
+
+static bool any_active(pic_ctx *c)
+{
+    for (auto &r : c->runs)
+        if (r.active) return true;
+    return false;
+}
+
+static void advance(pic_ctx *c, int nsteps)
+{
+    for (auto &r : c->runs)
+        if (r.active) r.steps += nsteps;
+    c->step += nsteps;
+    if (nsteps & 1) c->par ^= 1;
+}
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+const char *pic_strerror(int code)
+{
+    switch (code) {
+    case PIC_OK: return "ok";
+    case PIC_E_INVAL: return "invalid argument";
+    case PIC_E_CONFIG: return "invalid configuration";
+    case PIC_E_NOMEM: return "out of device memory or over the HBM budget";
+    case PIC_E_DEVICE: return "HIP runtime error";
+    case PIC_E_NUMERIC: return "numerical error (non-finite value or a move of a cell or more in one step)";
+    case PIC_E_CAPACITY: return "no free run slot";
+    case PIC_E_STATE: return "call not valid in the current state";
+    default: return "unknown error";
+    }
+}
+
+const char *pic_last_error(pic_ctx *ctx) { return ctx ? ctx->err.c_str() : g_init_error.c_str(); }
+
+int pic_mem_bytes(const pic_config *cfg, size_t *bytes)
+{
+    if (!cfg || !bytes) return set_err(nullptr, PIC_E_INVAL, "null argument");
+    int P[3] = {cfg->patch[0], cfg->patch[1], cfg->patch[2]};
+    if (P[0] == 0 && P[1] == 0 && (cfg->dims == 2 || P[2] == 0)) default_patch(cfg, P);
+    Layout L;
+    std::string why;
+    int rc = make_layout(cfg, P, L, why);
+    if (rc) return set_err(nullptr, rc, "%s", why.c_str());
+    *bytes = L.bytes;
+    return PIC_OK;
+}
+
+void pic_free(pic_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->stream || true) hipStreamSynchronize(ctx->stream);
+    drop_graphs(ctx);
+    for (auto &r : ctx->runs) free_run(ctx, r);
+    for (auto &b : ctx->own) dev_free(ctx, b);
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+}
+
+int pic_init(const pic_config *cfgs, int32_t n_runs, const pic_runtime *rt, pic_ctx **out)
+{
+    g_init_error.clear();
+    if (!out || n_runs < 0 || (n_runs > 0 && !cfgs)) return set_err(nullptr, PIC_E_INVAL, "null argument");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return set_err(nullptr, PIC_E_DEVICE, "no HIP device");
+    // validate every config before touching the device
+    for (int i = 0; i < n_runs; ++i) {
+        int P[3] = {cfgs[i].patch[0], cfgs[i].patch[1], cfgs[i].patch[2]};
+        if (P[0] == 0 && P[1] == 0 && (cfgs[i].dims == 2 || P[2] == 0)) default_patch(&cfgs[i], P);
+        Layout L;
+        std::string why;
+        int rc = make_layout(&cfgs[i], P, L, why);
+        if (rc) return set_err(nullptr, rc, "run %d: %s", i, why.c_str());
+    }
+    pic_ctx *c = new pic_ctx();
+    if (rt) c->rt = *rt;
+    c->stream = (hipStream_t)c->rt.stream;
+    c->max_runs = c->rt.max_runs > 0 ? std::max(c->rt.max_runs, n_runs) : std::max(n_runs, 1);
+    c->use_graph = !(c->rt.flags & PIC_RT_NO_GRAPH);
+    c->runs.resize(c->max_runs);
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return set_err(nullptr, PIC_E_DEVICE, "stream creation failed");
+    }
+    c->d_runs = (RunDev *)dev_alloc(c, sizeof(RunDev) * c->max_runs);
+    c->d_slot1 = (int *)dev_alloc(c, 256);
+    if (!c->d_runs || !c->d_slot1) {
+        pic_free(c);
+        return set_err(nullptr, PIC_E_NOMEM, "device allocation failed");
+    }
+    c->own.push_back({c->d_runs, align256(sizeof(RunDev) * c->max_runs)});
+    c->own.push_back({c->d_slot1, 256});
+    for (int i = 0; i < n_runs; ++i) {
+        int rc = setup_run(c, i, &cfgs[i]);
+        if (rc) {
+            g_init_error = "run " + std::to_string(i) + ": " + c->err;
+            pic_free(c);
+            return rc;
+        }
+    }
+    int rc = rebuild_items(c);
+    if (rc) {
+        g_init_error = c->err;
+        pic_free(c);
+        return rc;
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+        pic_free(c);
+        return set_err(nullptr, PIC_E_DEVICE, "synchronisation failed");
+    }
+    *out = c;
+    return PIC_OK;
+}
+
+int pic_step(pic_ctx *c, int32_t n_steps)
+{
+    if (!c || n_steps < 0) return set_err(c, PIC_E_INVAL, "bad argument");
+    if (!any_active(c) || n_steps == 0) return PIC_OK;
+    if (c->use_graph && !c->graphs_valid) {
+        int rc = build_graphs(c);
+        if (rc) return rc;
+    }
+    int left = n_steps;
+    while (left > 0) {
+        const int K = c->relayout_every;
+        const int to_check = K - (int)(c->step % K);
+        if (c->use_graph && c->g2 && c->par == 0 && left >= 2 && to_check >= 2) {
+            HIPCHK(c, hipGraphLaunch(c->g2, c->stream));
+            advance(c, 2);
+            left -= 2;
+        } else {
+            HIPCHK(c, enqueue_step(c, c->par, c->stream));
+            advance(c, 1);
+            left -= 1;
+        }
+        if (c->step % K == 0) {
+            if (c->use_graph && c->grel)
+                HIPCHK(c, hipGraphLaunch(c->grel, c->stream));
+            else
+                HIPCHK(c, enqueue_relayout(c, c->stream));
+        }
+    }
+    return PIC_OK;
+}
+
+int pic_run_steps(pic_ctx *c, int32_t run, int64_t *steps)
+{
+    if (!c || !steps || run < 0 || run >= (int)c->runs.size() || !c->runs[run].active)
+        return set_err(c, PIC_E_INVAL, "bad run");
+    *steps = c->runs[run].steps;
+    return PIC_OK;
+}
+
+int pic_time_phases(pic_ctx *c)
+{
+    if (!c) return PIC_E_INVAL;
+    if (!any_active(c)) return PIC_OK;
+    hipEvent_t ev[5];
+    for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
+    HIPCHK(c, hipEventRecord(ev[0], c->stream));
+    HIPCHK(c, enqueue_push(c, c->par, c->stream));
+    HIPCHK(c, hipEventRecord(ev[1], c->stream));
+    HIPCHK(c, enqueue_yee(c, c->par, c->stream));
+    HIPCHK(c, hipEventRecord(ev[2], c->stream));
+    HIPCHK(c, enqueue_post(c, c->par, c->stream));
+    HIPCHK(c, hipEventRecord(ev[3], c->stream));
+    advance(c, 1);
+    if (c->step % c->relayout_every == 0) HIPCHK(c, enqueue_relayout(c, c->stream));
+    HIPCHK(c, hipEventRecord(ev[4], c->stream));
+    HIPCHK(c, hipEventSynchronize(ev[4]));
+    for (int i = 0; i < 4; ++i) {
+        float ms = 0;
+        hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+        c->t_ms[i] = ms;
+    }
+    for (auto &e : ev) hipEventDestroy(e);
+    return PIC_OK;
+}
+
+static int field_comp(int bit, int par)
+{
+    if (bit < 3) return f_E(par) + bit;
+    if (bit < 6) return F_BM + (bit - 3);
+    if (bit < 9) return f_B(par) + (bit - 6);
+    if (bit < 12) return F_J + (bit - 9);
+    return -1;
+}
+
+int pic_fields(pic_ctx *c, int32_t run, uint32_t mask, double *dst, size_t dst_len, int32_t dst_on_device)
+{
+    if (!c || run < 0 || run >= (int)c->runs.size() || !c->runs[run].active || (!dst && mask))
+        return set_err(c, PIC_E_INVAL, "bad argument");
+    Run &r = c->runs[run];
+    const size_t nc = (size_t)r.ncell;
+    int ncomp = 0;
+    for (int b = 0; b < 13; ++b)
+        if (mask & (1u << b)) ++ncomp;
+    if ((size_t)ncomp * nc > dst_len) return set_err(c, PIC_E_INVAL, "dst too small: need %zu", (size_t)ncomp * nc);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double *tmp = (double *)dev_alloc(c, nc * 8);
+    if (!tmp) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
+    DevBuf tb{tmp, align256(nc * 8)};
+    size_t o = 0;
+    int rc = PIC_OK;
+    for (int b = 0; b < 13 && rc == PIC_OK; ++b) {
+        if (!(mask & (1u << b))) continue;
+        hipError_t e;
+        if (b < 12) {
+            e = launch_assemble(c->d_runs, run, r.ncell, field_comp(b, c->par), tmp, c->stream);
+        } else {
+            Ctl ctl = read_ctl(c, run, e);
+            if (e == hipSuccess)
+                e = launch_rho(r.dims, r.split, c->d_runs, run, r.rd.n_patch, ctl.nspill, r.ncell, tmp, c->stream);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dst + o, tmp, nc * 8, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                               c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) rc = set_err(c, PIC_E_DEVICE, "field readout: %s", hipGetErrorString(e));
+        o += nc;
+    }
+    dev_free(c, tb);
+    if (rc) return rc;
+    return check_run_err(c, run);
+}
+
+int pic_diag(pic_ctx *c, int32_t run, pic_diag_t *out)
+{
+    if (!c || !out || run < 0 || run >= (int)c->runs.size() || !c->runs[run].active)
+        return set_err(c, PIC_E_INVAL, "bad argument");
+    Run &r = c->runs[run];
+    const RunDev &d = r.rd;
+    memset(out, 0, sizeof *out);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hipError_t ce;
+    Ctl ctl = read_ctl(c, run, ce);
+    HIPCHK(c, ce);
+    std::vector<int> seg(d.n_patch + 1), cnt(d.n_patch);
+    HIPCHK(c, hipMemcpy(seg.data(), d.seg, seg.size() * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(cnt.data(), d.cnt, cnt.size() * 4, hipMemcpyDeviceToHost));
+    std::vector<long long> per(d.n_patch, 0);
+    std::vector<int> sp(ctl.nspill);
+    if (ctl.nspill > 0) HIPCHK(c, hipMemcpy(sp.data(), d.spatch, sp.size() * 4, hipMemcpyDeviceToHost));
+    long long n = 0;
+    for (int q = 0; q < d.n_patch; ++q) {
+        per[q] = std::min(cnt[q], seg[q + 1] - seg[q]);
+        n += per[q];
+    }
+    for (int q : sp)
+        if (q >= 0 && q < d.n_patch) per[q]++;
+    n += ctl.nspill;
+    out->step = r.steps;
+    out->t = r.steps * d.dt;
+    out->n_particles = n;
+    if (d.n_patch > 0) {
+        out->patch_min = *std::min_element(per.begin(), per.end());
+        out->patch_max = *std::max_element(per.begin(), per.end());
+        out->patch_mean = (double)n / d.n_patch;
+    }
+    const double dV = d.d[0] * d.d[1] * (d.dims == 3 ? d.d[2] : 1.0);
+    const int nb = std::max(1, std::min(1024, (r.ncell + BLOCK - 1) / BLOCK));
+    double *part = (double *)dev_alloc(c, (size_t)std::max(2 * nb, d.n_patch + 1) * 8);
+    if (!part) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
+    DevBuf pb{part, align256((size_t)std::max(2 * nb, d.n_patch + 1) * 8)};
+    std::vector<double> h(std::max(2 * nb, d.n_patch + 1));
+    HIPCHK(c, launch_field_energy(c->d_runs, run, r.ncell, c->par, part, nb, c->stream));
+    HIPCHK(c, hipMemcpyAsync(h.data(), part, 2 * nb * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double ue = 0, ub = 0;
+    for (int i = 0; i < nb; ++i) {
+        ue += h[2 * i];
+        ub += h[2 * i + 1];
+    }
+    HIPCHK(c, launch_kinetic(r.dims, r.split, c->d_runs, run, d.n_patch, ctl.nspill, part, c->stream));
+    HIPCHK(c, hipMemcpyAsync(h.data(), part, (d.n_patch + 1) * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double k = 0;
+    for (int i = 0; i <= d.n_patch; ++i) k += h[i];
+    dev_free(c, pb);
+    out->U_E = 0.5 * ue * dV;
+    out->U_B = 0.5 * ub * dV;
+    out->K = k * dV;
+    for (int i = 0; i < 4; ++i) out->t_ms[i] = c->t_ms[i];
+    out->n_relayout = ctl.n_relayout;
+    out->n_spill = ctl.nspill;
+    out->err_flags = ctl.err;
+    for (int a = 0; a < 3; ++a) out->patch[a] = d.P[a];
+    return check_run_err(c, run);
+}
+
+int pic_particles(pic_ctx *c, int32_t run, pic_particles_out *out)
+{
+    if (!c || !out || run < 0 || run >= (int)c->runs.size() || !c->runs[run].active)
+        return set_err(c, PIC_E_INVAL, "bad argument");
+    Run &r = c->runs[run];
+    const RunDev &d = r.rd;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    hipError_t ce;
+    Ctl ctl = read_ctl(c, run, ce);
+    HIPCHK(c, ce);
+    std::vector<int> seg(d.n_patch + 1), cnt(d.n_patch), off(d.n_patch + 1);
+    HIPCHK(c, hipMemcpy(seg.data(), d.seg, seg.size() * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(cnt.data(), d.cnt, cnt.size() * 4, hipMemcpyDeviceToHost));
+    long long n = 0;
+    for (int q = 0; q < d.n_patch; ++q) {
+        off[q] = (int)n;
+        n += std::min(cnt[q], seg[q + 1] - seg[q]);
+    }
+    off[d.n_patch] = (int)n;
+    n += ctl.nspill;
+    out->n = n;
+    if (out->capacity < n) return set_err(c, PIC_E_INVAL, "capacity %lld < %lld particles", (long long)out->capacity, n);
+    if (n == 0) return check_run_err(c, run);
+    const size_t nn = (size_t)n;
+    std::vector<DevBuf> tmp;
+    auto mk = [&](size_t bytes) -> void * {
+        void *p = dev_alloc(c, bytes);
+        if (p) tmp.push_back({p, align256(bytes)});
+        return p;
+    };
+    double *dx[7] = {nullptr};
+    double *hx[7] = {out->x, out->y, out->z, out->ux, out->uy, out->uz, out->w};
+    bool ok = true;
+    for (int i = 0; i < 7; ++i)
+        if (hx[i] && (i != 2 || d.dims == 3 || true)) {
+            dx[i] = (double *)mk(nn * 8);
+            ok = ok && dx[i];
+        }
+    uint32_t *did = out->id ? (uint32_t *)mk(nn * 4) : nullptr;
+    int *dpat = out->patch ? (int *)mk(nn * 4) : nullptr;
+    int *doff = (int *)mk(off.size() * 4);
+    ok = ok && (!out->id || did) && (!out->patch || dpat) && doff;
+    int rc = PIC_OK;
+    if (!ok) rc = set_err(c, PIC_E_NOMEM, "staging allocation failed");
+    hipError_t e = hipSuccess;
+    if (!rc) e = hipMemcpyAsync(doff, off.data(), off.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (!rc && e == hipSuccess)
+        e = launch_export(r.dims, r.split, c->d_runs, run, d.n_patch, ctl.nspill, doff, dx[0], dx[1], dx[2], dx[3], dx[4],
+                          dx[5], dx[6], did, dpat, c->stream);
+    for (int i = 0; i < 7 && !rc && e == hipSuccess; ++i)
+        if (dx[i]) e = hipMemcpyAsync(hx[i], dx[i], nn * 8, hipMemcpyDeviceToHost, c->stream);
+    if (!rc && e == hipSuccess && did) e = hipMemcpyAsync(out->id, did, nn * 4, hipMemcpyDeviceToHost, c->stream);
+    if (!rc && e == hipSuccess && dpat) e = hipMemcpyAsync(out->patch, dpat, nn * 4, hipMemcpyDeviceToHost, c->stream);
+    if (!rc && e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (!rc && e != hipSuccess) rc = set_err(c, PIC_E_DEVICE, "particle export: %s", hipGetErrorString(e));
+    for (auto &b : tmp) dev_free(c, b);
+    if (rc) return rc;
+    return check_run_err(c, run);
+}
+
+int pic_admit(pic_ctx *c, const pic_config *cfg, int32_t *run_id)
+{
+    if (!c || !cfg || !run_id) return set_err(c, PIC_E_INVAL, "null argument");
+    int slot = -1;
+    for (int i = 0; i < (int)c->runs.size(); ++i)
+        if (!c->runs[i].active) {
+            slot = i;
+            break;
+        }
+    if (slot < 0) return set_err(c, PIC_E_CAPACITY, "all %d run slots are taken", (int)c->runs.size());
+    int rc = setup_run(c, slot, cfg);
+    if (rc) {
+        if (c->runs[slot].active) free_run(c, c->runs[slot]);
+        return rc;
+    }
+    if ((rc = rebuild_items(c))) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *run_id = slot;
+    return PIC_OK;
+}
+
+int pic_retire(pic_ctx *c, int32_t run)
+{
+    if (!c || run < 0 || run >= (int)c->runs.size() || !c->runs[run].active)
+        return set_err(c, PIC_E_INVAL, "bad run");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    free_run(c, c->runs[run]);
+    return rebuild_items(c);
+}
+
+}  // extern "C"

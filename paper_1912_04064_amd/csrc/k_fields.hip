@@ -1,0 +1,458 @@
+// k_fields.hip -- region-side kernels of the SDMD step.
+//
+//   yee_kernel   : transfer (i) of section 2.2 fused with the Yee update
+//                  (section 3.2).  For every node of its tile (plus a
+//                  one-node high halo) a workgroup sums the current of the
+//                  patch tiles covering that node (at most 2 patches per
+//                  axis when P >= 5, fixed order, FP64 sum), applies Ampere,
+//                  keeps E^{n+1} of tile and halo in LDS, then applies
+//                  Faraday and forms Bm^{n+1} on the tile.  E and B are read
+//                  from buffer `par` and written to buffer 1-par.
+//   post_kernel  : region ghost synchronisation of the new E, B, Bm
+//                  (section 2.1 "Sync", between regions) and, in the same
+//                  launch, insertion of the particles that left their patch.
+//   init / readout helpers.
+#include "launch.h"
+#include "part.h"
+#include "sdmd_dev.h"
+
+namespace sdmd {
+
+// --------------------------------------------------------------- J gather
+// Current at global node g of component c: sum over the patch tiles whose
+// node range [p0-2, p0+P+2] covers g (periodic), in a fixed order.
+template <int DIM, class R>
+__device__ __forceinline__ double gather_J(const RunDev &rd, const R *__restrict__ tiles, int c, const int g[3])
+{
+    int pa[3] = {0, 0, 0}, l[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        pa[a] = g[a] / rd.P[a];
+        l[a] = g[a] - pa[a] * rd.P[a];
+        lo[a] = l[a] <= 2 ? -1 : 0;
+        hi[a] = l[a] >= rd.P[a] - 2 ? 1 : 0;
+    }
+    double s = 0.0;
+    for (int oz = lo[2]; oz <= hi[2]; ++oz)
+        for (int oy = lo[1]; oy <= hi[1]; ++oy)
+            for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+                const int qx = wrapi(pa[0] + ox, rd.np[0]);
+                const int qy = wrapi(pa[1] + oy, rd.np[1]);
+                const int qz = DIM == 3 ? wrapi(pa[2] + oz, rd.np[2]) : 0;
+                const long long q = qx + (long long)rd.np[0] * (qy + (long long)rd.np[1] * qz);
+                const int tx = l[0] - ox * rd.P[0] + 2;
+                const int ty = l[1] - oy * rd.P[1] + 2;
+                const int tz = DIM == 3 ? l[2] - oz * rd.P[2] + 2 : 0;
+                s += (double)tiles[(q * 3 + c) * rd.tsz + (tz * rd.TA[1] + ty) * rd.TA[0] + tx];
+            }
+    return s;
+}
+
+// ------------------------------------------------------------ Yee kernel
+template <int DIM>
+struct YeeTile;
+template <>
+struct YeeTile<2> {
+    static constexpr int X = 64, Y = 4, Z = 1;
+};
+template <>
+struct YeeTile<3> {
+    static constexpr int X = 32, Y = 4, Z = 2;
+};
+
+template <int DIM, class T>
+__global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ runs, const int4 *__restrict__ items,
+                                                    int par)
+{
+    using R = typename T::real;
+    constexpr int TX = YeeTile<DIM>::X, TY = YeeTile<DIM>::Y, TZ = YeeTile<DIM>::Z;
+    constexpr int HX = TX + 1, HY = TY + 1, HZ = DIM == 3 ? TZ + 1 : 1;
+    constexpr int HN = HX * HY * HZ;
+    __shared__ double sE[3][HN];
+
+    const int4 it = items[blockIdx.x];
+    const RunDev &rd = runs[it.x];
+    const int tid = threadIdx.x;
+    // one workgroup per run clears the spill counter: the particle phase of
+    // this step has consumed the spill store
+    if (it.w && tid == 0) rd.ctl->nspill = 0;
+
+    const int region = it.y;
+    const int rr[3] = {region % rd.nreg[0], (region / rd.nreg[0]) % rd.nreg[1],
+                       DIM == 3 ? region / (rd.nreg[0] * rd.nreg[1]) : 0};
+    const int ro[3] = {rr[0] * rd.rs[0], rr[1] * rd.rs[1], rr[2] * rd.rs[2]};
+    const int ntx = (rd.rs[0] + TX - 1) / TX, nty = (rd.rs[1] + TY - 1) / TY;
+    const int ti = it.z;
+    const int ox = (ti % ntx) * TX, oy = ((ti / ntx) % nty) * TY, oz = DIM == 3 ? (ti / (ntx * nty)) * TZ : 0;
+    const int rs0 = rd.rs[0], rs1 = rd.rs[1], rs2 = DIM == 3 ? rd.rs[2] : 1;
+
+    const double dt = rd.dt, dx = rd.d[0], dy = rd.d[1], dz = DIM == 3 ? rd.d[2] : 1.0;
+    const double *Eo[3], *Bo[3];
+    double *En[3], *Bn[3], *Bm[3], *Jr[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Eo[c] = rcomp(rd, region, f_E(par) + c);
+        Bo[c] = rcomp(rd, region, f_B(par) + c);
+        En[c] = rcomp(rd, region, f_E(1 - par) + c);
+        Bn[c] = rcomp(rd, region, f_B(1 - par) + c);
+        Bm[c] = rcomp(rd, region, F_BM + c);
+        Jr[c] = rcomp(rd, region, F_J + c);
+    }
+    const R *tiles = (const R *)rd.tiles;
+    const long long sx = 1, sy = rd.ra[0], sz = (long long)rd.ra[0] * rd.ra[1];
+
+    // phase 1: J gather and Ampere on tile + high halo
+    for (int h = tid; h < HN; h += BLOCK) {
+        const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+        const int li = ox + hx, lj = oy + hy, lk = oz + hz;
+        if (li > rs0 || lj > rs1 || (DIM == 3 && lk > rs2)) continue;
+        const int g[3] = {wrapi(ro[0] + li, rd.n[0]), wrapi(ro[1] + lj, rd.n[1]),
+                          DIM == 3 ? wrapi(ro[2] + lk, rd.n[2]) : 0};
+        double J[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) J[c] = gather_J<DIM, R>(rd, tiles, c, g);
+        const long long p = rindex(rd, li, lj, DIM == 3 ? lk : 0);
+        double e0, e1, e2;
+        if constexpr (DIM == 2) {
+            e0 = Eo[0][p] + dt * ((Bo[2][p] - Bo[2][p - sy]) / dy - J[0]);
+            e1 = Eo[1][p] + dt * (-((Bo[2][p] - Bo[2][p - sx]) / dx) - J[1]);
+            e2 = Eo[2][p] + dt * ((Bo[1][p] - Bo[1][p - sx]) / dx - (Bo[0][p] - Bo[0][p - sy]) / dy - J[2]);
+        } else {
+            e0 = Eo[0][p] + dt * ((Bo[2][p] - Bo[2][p - sy]) / dy - (Bo[1][p] - Bo[1][p - sz]) / dz - J[0]);
+            e1 = Eo[1][p] + dt * ((Bo[0][p] - Bo[0][p - sz]) / dz - (Bo[2][p] - Bo[2][p - sx]) / dx - J[1]);
+            e2 = Eo[2][p] + dt * ((Bo[1][p] - Bo[1][p - sx]) / dx - (Bo[0][p] - Bo[0][p - sy]) / dy - J[2]);
+        }
+        sE[0][h] = e0;
+        sE[1][h] = e1;
+        sE[2][h] = e2;
+        if (hx < TX && hy < TY && (DIM == 2 || hz < TZ) && li < rs0 && lj < rs1 && (DIM == 2 || lk < rs2)) {
+            En[0][p] = e0;
+            En[1][p] = e1;
+            En[2][p] = e2;
+            Jr[0][p] = J[0];
+            Jr[1][p] = J[1];
+            Jr[2][p] = J[2];
+        }
+    }
+    __syncthreads();
+
+    // phase 2: Faraday and Bm on the tile
+    {
+        const int tx = tid % TX, ty = (tid / TX) % TY, tz = DIM == 3 ? tid / (TX * TY) : 0;
+        const int li = ox + tx, lj = oy + ty, lk = oz + tz;
+        if (li < rs0 && lj < rs1 && (DIM == 2 || lk < rs2)) {
+            const int h = (tz * HY + ty) * HX + tx;
+            const int hxp = h + 1, hyp = h + HX, hzp = h + HX * HY;
+            const long long p = rindex(rd, li, lj, DIM == 3 ? lk : 0);
+            const double bx = Bo[0][p], by = Bo[1][p], bz = Bo[2][p];
+            double nbx, nby, nbz;
+            if constexpr (DIM == 2) {
+                nbx = bx - dt * ((sE[2][hyp] - sE[2][h]) / dy);
+                nby = by - dt * (-((sE[2][hxp] - sE[2][h]) / dx));
+                nbz = bz - dt * ((sE[1][hxp] - sE[1][h]) / dx - (sE[0][hyp] - sE[0][h]) / dy);
+            } else {
+                nbx = bx - dt * ((sE[2][hyp] - sE[2][h]) / dy - (sE[1][hzp] - sE[1][h]) / dz);
+                nby = by - dt * ((sE[0][hzp] - sE[0][h]) / dz - (sE[2][hxp] - sE[2][h]) / dx);
+                nbz = bz - dt * ((sE[1][hxp] - sE[1][h]) / dx - (sE[0][hyp] - sE[0][h]) / dy);
+            }
+            Bn[0][p] = nbx;
+            Bn[1][p] = nby;
+            Bn[2][p] = nbz;
+            Bm[0][p] = 0.5 * (bx + nbx);
+            Bm[1][p] = 0.5 * (by + nby);
+            Bm[2][p] = 0.5 * (bz + nbz);
+        }
+    }
+}
+
+// ------------------------------------------------------------ ghosts
+// Ghost node number k of a region -> local coordinates (li, lj, lk).
+__device__ __forceinline__ void ghost_coords(const RunDev &rd, int k, int &li, int &lj, int &lk)
+{
+    const int ra0 = rd.ra[0], ra1 = rd.ra[1];
+    const int rs0 = rd.rs[0], rs1 = rd.rs[1];
+    const int G2 = 2 * GH;
+    if (rd.dims == 2) {
+        lk = 0;
+        const int rowsN = G2 * ra0;
+        if (k < rowsN) {
+            const int r = k / ra0;
+            lj = r < GH ? r - GH : rs1 + (r - GH);
+            li = k % ra0 - GH;
+        } else {
+            k -= rowsN;
+            lj = k / G2;
+            const int c = k % G2;
+            li = c < GH ? c - GH : rs0 + (c - GH);
+        }
+        return;
+    }
+    const int rs2 = rd.rs[2];
+    const int slabN = G2 * ra0 * ra1;
+    if (k < slabN) {
+        const int r = k / (ra0 * ra1), rem = k % (ra0 * ra1);
+        lk = r < GH ? r - GH : rs2 + (r - GH);
+        lj = rem / ra0 - GH;
+        li = rem % ra0 - GH;
+        return;
+    }
+    k -= slabN;
+    const int rowN = rs2 * G2 * ra0;
+    if (k < rowN) {
+        lk = k / (G2 * ra0);
+        const int rem = k % (G2 * ra0);
+        const int r = rem / ra0;
+        lj = r < GH ? r - GH : rs1 + (r - GH);
+        li = rem % ra0 - GH;
+        return;
+    }
+    k -= rowN;
+    lk = k / (rs1 * G2);
+    const int rem = k % (rs1 * G2);
+    lj = rem / G2;
+    const int c = rem % G2;
+    li = c < GH ? c - GH : rs0 + (c - GH);
+}
+
+// copy components [c0, c0+nc) of ghost node gk (run-global ghost index)
+// from the interior of the region that owns the wrapped node
+__device__ __forceinline__ void ghost_copy(const RunDev &rd, int gk, const int *comps, int nc)
+{
+    const int region = gk / rd.ghosts;
+    int li, lj, lk;
+    ghost_coords(rd, gk - region * rd.ghosts, li, lj, lk);
+    const int rr[3] = {region % rd.nreg[0], (region / rd.nreg[0]) % rd.nreg[1], region / (rd.nreg[0] * rd.nreg[1])};
+    const int g[3] = {wrapi(rr[0] * rd.rs[0] + li, rd.n[0]), wrapi(rr[1] * rd.rs[1] + lj, rd.n[1]),
+                      rd.dims == 3 ? wrapi(rr[2] * rd.rs[2] + lk, rd.n[2]) : 0};
+    const int sr[3] = {g[0] / rd.rs[0], g[1] / rd.rs[1], rd.dims == 3 ? g[2] / rd.rs[2] : 0};
+    const int src = sr[0] + rd.nreg[0] * (sr[1] + rd.nreg[1] * sr[2]);
+    const long long ps = rindex(rd, g[0] - sr[0] * rd.rs[0], g[1] - sr[1] * rd.rs[1],
+                                rd.dims == 3 ? g[2] - sr[2] * rd.rs[2] : 0);
+    const long long pd = rindex(rd, li, lj, lk);
+    for (int i = 0; i < nc; ++i) rcomp(rd, region, comps[i])[pd] = rcomp(rd, src, comps[i])[ps];
+}
+
+// ------------------------------------------------------------ post kernel
+template <int DIM, class T>
+__global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ runs, const int4 *__restrict__ items,
+                                                     int par_new)
+{
+    const int4 it = items[blockIdx.x];
+    const RunDev &rd = runs[it.x];
+    const int tid = threadIdx.x;
+    if (it.y == 0) {
+        const int comps[9] = {f_E(par_new), f_E(par_new) + 1, f_E(par_new) + 2, f_B(par_new), f_B(par_new) + 1,
+                              f_B(par_new) + 2, F_BM, F_BM + 1, F_BM + 2};
+        const int gk = it.z + tid;
+        if (gk < rd.ghosts * rd.n_regions) ghost_copy(rd, gk, comps, 9);
+        return;
+    }
+    // insert the leavers of this step into their destination patch
+    __shared__ int s_last;
+    const int nb = it.w;
+    const int nl = min(rd.ctl->nleave, rd.cap_total);
+    int err = 0;
+    for (int i = it.z * BLOCK + tid; i < nl; i += nb * BLOCK) {
+        const int q = rd.lpatch[i];
+        const int slot = atomicAdd(&rd.cnt[q], 1);
+        const int cap = rd.seg[q + 1] - rd.seg[q];
+        if (slot < cap) {
+            copy_part<DIM, T>(rd.lv, i, rd.st, (long long)rd.seg[q] + slot);
+        } else {
+            const int s = atomicAdd(&rd.ctl->nspill, 1);
+            if (s < rd.n_total) {
+                copy_part<DIM, T>(rd.lv, i, rd.sp, s);
+                rd.spatch[s] = q;
+            } else {
+                err |= ERR_CAPACITY;
+            }
+        }
+    }
+    if (err) atomicOr(&rd.ctl->err, err);
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        s_last = atomicAdd(&rd.ctl->ins_done, 1) == nb - 1;
+    }
+    __syncthreads();
+    if (s_last && tid == 0) {
+        const int ns = rd.ctl->nspill;
+        if (ns > rd.ctl->max_spill) rd.ctl->max_spill = ns;
+        rd.ctl->nleave = 0;
+        rd.ctl->ins_done = 0;
+    }
+}
+
+// ------------------------------------------------------------ launchers
+#define DT_CASE(D, TT, KERNEL, ...)                                                                   \
+    if (dims == D && split == TT::split) {                                                            \
+        KERNEL<D, TT><<<n_items, BLOCK, 0, s>>>(__VA_ARGS__);                                         \
+        return hipGetLastError();                                                                     \
+    }
+
+hipError_t launch_yee(int dims, bool split, const RunDev *runs, const int4 *items, int n_items, int par,
+                      hipStream_t s)
+{
+    if (n_items <= 0) return hipSuccess;
+    DT_CASE(2, F32S, yee_kernel, runs, items, par)
+    DT_CASE(2, FP64, yee_kernel, runs, items, par)
+    DT_CASE(3, F32S, yee_kernel, runs, items, par)
+    DT_CASE(3, FP64, yee_kernel, runs, items, par)
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_post(int dims, bool split, const RunDev *runs, const int4 *items, int n_items, int par_new,
+                       hipStream_t s)
+{
+    if (n_items <= 0) return hipSuccess;
+    DT_CASE(2, F32S, post_kernel, runs, items, par_new)
+    DT_CASE(2, FP64, post_kernel, runs, items, par_new)
+    DT_CASE(3, F32S, post_kernel, runs, items, par_new)
+    DT_CASE(3, FP64, post_kernel, runs, items, par_new)
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------ init / readout
+__global__ void ghosts_kernel(const RunDev *__restrict__ runs, int run, int total, int c0, int nc)
+{
+    const RunDev &rd = runs[run];
+    const int gk = blockIdx.x * BLOCK + threadIdx.x;
+    if (gk >= total) return;
+    int comps[9];
+    for (int i = 0; i < nc && i < 9; ++i) comps[i] = c0 + i;
+    ghost_copy(rd, gk, comps, nc < 9 ? nc : 9);
+}
+
+hipError_t launch_ghosts(const RunDev *runs, int run, int total_ghosts, int c0, int nc, hipStream_t s)
+{
+    if (total_ghosts <= 0) return hipSuccess;
+    ghosts_kernel<<<(total_ghosts + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(runs, run, total_ghosts, c0, nc);
+    return hipGetLastError();
+}
+
+// global node id -> (region, region-local index)
+__device__ __forceinline__ void node_of(const RunDev &rd, long long gid, int &region, long long &p)
+{
+    const int nx = rd.n[0], ny = rd.n[1];
+    const int i = (int)(gid % nx), j = (int)((gid / nx) % ny), k = (int)(gid / ((long long)nx * ny));
+    const int r0 = i / rd.rs[0], r1 = j / rd.rs[1], r2 = k / rd.rs[2];
+    region = r0 + rd.nreg[0] * (r1 + rd.nreg[1] * r2);
+    p = rindex(rd, i - r0 * rd.rs[0], j - r1 * rd.rs[1], k - r2 * rd.rs[2]);
+}
+
+__global__ void scatter_fields_kernel(const RunDev *__restrict__ runs, int run, int ncell,
+                                      const double *__restrict__ src, int c0)
+{
+    const RunDev &rd = runs[run];
+    const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (gid >= ncell) return;
+    int region;
+    long long p;
+    node_of(rd, gid, region, p);
+    for (int c = 0; c < 3; ++c) rcomp(rd, region, c0 + c)[p] = src[(long long)c * ncell + gid];
+}
+
+hipError_t launch_scatter_fields(const RunDev *runs, int run, int ncell, const double *src, int c0, hipStream_t s)
+{
+    scatter_fields_kernel<<<(ncell + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(runs, run, ncell, src, c0);
+    return hipGetLastError();
+}
+
+__global__ void assemble_kernel(const RunDev *__restrict__ runs, int run, int ncell, int comp, double *__restrict__ dst)
+{
+    const RunDev &rd = runs[run];
+    const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (gid >= ncell) return;
+    int region;
+    long long p;
+    node_of(rd, gid, region, p);
+    dst[gid] = rcomp(rd, region, comp)[p];
+}
+
+hipError_t launch_assemble(const RunDev *runs, int run, int ncell, int comp, double *dst, hipStream_t s)
+{
+    assemble_kernel<<<(ncell + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(runs, run, ncell, comp, dst);
+    return hipGetLastError();
+}
+
+// Bm = B^0; B^{1/2} = B^0 - dt/2 curl E^0 (region interiors, E ghosts valid)
+__global__ void half_faraday_kernel(const RunDev *__restrict__ runs, int run, int ncell, int par)
+{
+    const RunDev &rd = runs[run];
+    const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (gid >= ncell) return;
+    int region;
+    long long p;
+    node_of(rd, gid, region, p);
+    const double h = 0.5 * rd.dt, dx = rd.d[0], dy = rd.d[1], dz = rd.dims == 3 ? rd.d[2] : 1.0;
+    const long long sx = 1, sy = rd.ra[0], sz = (long long)rd.ra[0] * rd.ra[1];
+    const double *E[3];
+    double *B[3], *Bm[3];
+    for (int c = 0; c < 3; ++c) {
+        E[c] = rcomp(rd, region, f_E(par) + c);
+        B[c] = rcomp(rd, region, f_B(par) + c);
+        Bm[c] = rcomp(rd, region, F_BM + c);
+    }
+    const double bx = B[0][p], by = B[1][p], bz = B[2][p];
+    Bm[0][p] = bx;
+    Bm[1][p] = by;
+    Bm[2][p] = bz;
+    if (rd.dims == 2) {
+        B[0][p] = bx - h * ((E[2][p + sy] - E[2][p]) / dy);
+        B[1][p] = by - h * (-((E[2][p + sx] - E[2][p]) / dx));
+        B[2][p] = bz - h * ((E[1][p + sx] - E[1][p]) / dx - (E[0][p + sy] - E[0][p]) / dy);
+    } else {
+        B[0][p] = bx - h * ((E[2][p + sy] - E[2][p]) / dy - (E[1][p + sz] - E[1][p]) / dz);
+        B[1][p] = by - h * ((E[0][p + sz] - E[0][p]) / dz - (E[2][p + sx] - E[2][p]) / dx);
+        B[2][p] = bz - h * ((E[1][p + sx] - E[1][p]) / dx - (E[0][p + sy] - E[0][p]) / dy);
+    }
+}
+
+hipError_t launch_half_faraday(const RunDev *runs, int run, int ncell, int par, hipStream_t s)
+{
+    half_faraday_kernel<<<(ncell + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(runs, run, ncell, par);
+    return hipGetLastError();
+}
+
+// partial sums of E^2 (buffer par) and Bm^2 over region interiors
+__global__ void field_energy_kernel(const RunDev *__restrict__ runs, int run, int ncell, int par,
+                                    double *__restrict__ partial)
+{
+    const RunDev &rd = runs[run];
+    __shared__ double se[BLOCK], sb[BLOCK];
+    double e = 0.0, b = 0.0;
+    for (long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x; gid < ncell; gid += (long long)gridDim.x * BLOCK) {
+        int region;
+        long long p;
+        node_of(rd, gid, region, p);
+        for (int c = 0; c < 3; ++c) {
+            const double ev = rcomp(rd, region, f_E(par) + c)[p];
+            const double bv = rcomp(rd, region, F_BM + c)[p];
+            e += ev * ev;
+            b += bv * bv;
+        }
+    }
+    se[threadIdx.x] = e;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            se[threadIdx.x] += se[threadIdx.x + w];
+            sb[threadIdx.x] += sb[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = se[0];
+        partial[2 * blockIdx.x + 1] = sb[0];
+    }
+}
+
+hipError_t launch_field_energy(const RunDev *runs, int run, int ncell, int par, double *partial, int nblocks,
+                               hipStream_t s)
+{
+    field_energy_kernel<<<nblocks, BLOCK, 0, s>>>(runs, run, ncell, par, partial);
+    return hipGetLastError();
+}
+
+}  // namespace sdmd

@@ -1,0 +1,406 @@
+// k_particles.hip -- particle-store kernels: initial conversion and binning,
+// re-layout of the patch-segmented store, export and particle diagnostics.
+//
+// Binning (the patch decomposition of section 2.2): a particle belongs to
+// the patch holding its cell; cell = floor(x/d) clamped to [0, n-1] in the
+// FP64 form, the integer cell in the split form.  The store keeps the
+// particles of patch p in slots [seg[p], seg[p]+cnt[p]).  A re-layout gives
+// every patch a new capacity (live count + 25 % + 16) and moves the live and
+// parked particles into it; it runs at init (binning of the initial state)
+// and whenever particles had to be parked because their patch was full.
+#include "launch.h"
+#include "part.h"
+#include "sdmd_dev.h"
+
+namespace sdmd {
+
+// ---------------------------------------------------------------- convert
+template <int DIM, class T>
+__global__ __launch_bounds__(BLOCK) void convert_kernel(const RunDev *__restrict__ runs, int run, int n,
+                                                        const double *__restrict__ x, const double *__restrict__ y,
+                                                        const double *__restrict__ z, const double *__restrict__ ux,
+                                                        const double *__restrict__ uy, const double *__restrict__ uz,
+                                                        const double *__restrict__ w, const uint32_t *__restrict__ id)
+{
+    using R = typename T::real;
+    const RunDev &rd = runs[run];
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i == 0) rd.ctl->nspill = n;
+    if (i >= n) return;
+    const double *pos[3] = {x, y, z};
+    int err = 0;
+    Part<T> p;
+    int dest = 0, mul = 1, packed = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double xa = pos[a][i];
+        if (!(xa >= 0.0 && xa < rd.L[a])) {
+            err |= ERR_RANGE;
+            xa = 0.0;
+        }
+        int c = (int)floor(xa / rd.d[a]);
+        c = c > rd.n[a] - 1 ? rd.n[a] - 1 : (c < 0 ? 0 : c);
+        if constexpr (T::split) {
+            float f = (float)(xa / rd.d[a] - (double)c);
+            if (f < 0.0f) f = 0.0f;
+            if (f >= 1.0f) {
+                f = 0.0f;
+                c += 1;
+                if (c >= rd.n[a]) c -= rd.n[a];
+            }
+            p.pos[a] = f;
+        } else {
+            p.pos[a] = xa;
+        }
+        const int pa = c / rd.P[a];
+        dest += pa * mul;
+        mul *= rd.np[a];
+        packed |= (c - pa * rd.P[a]) << (5 * a);
+    }
+    p.cell = packed;
+    const double u[3] = {ux[i], uy[i], uz[i]};
+    for (int a = 0; a < 3; ++a) {
+        if (!(fabs(u[a]) < 1e30)) err |= ERR_NONFINITE;
+        p.u[a] = (R)u[a];
+    }
+    if (!(fabs(w[i]) < 1e300)) err |= ERR_NONFINITE;
+    p.w = (R)w[i];
+    p.id = id ? id[i] : (uint32_t)i;
+    store_part<DIM, T>(rd.sp, i, p, true);
+    rd.spatch[i] = dest;
+    if (err) atomicOr(&rd.ctl->err, err);
+}
+
+// ---------------------------------------------------------------- re-layout
+constexpr int PLAN_BLOCK = 1024;
+
+// block-wide exclusive scan of per-thread values (PLAN_BLOCK threads)
+__device__ long long block_exclusive_scan(long long v, long long *buf, long long &total)
+{
+    const int tid = threadIdx.x;
+    buf[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < PLAN_BLOCK; off <<= 1) {
+        const long long t = tid >= off ? buf[tid - off] : 0;
+        __syncthreads();
+        buf[tid] += t;
+        __syncthreads();
+    }
+    total = buf[PLAN_BLOCK - 1];
+    const long long ex = buf[tid] - v;
+    __syncthreads();
+    return ex;
+}
+
+__global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev *__restrict__ runs,
+                                                                   const int *__restrict__ slots, int force)
+{
+    const RunDev &rd = runs[slots[blockIdx.x]];
+    __shared__ long long buf[PLAN_BLOCK];
+    const int tid = threadIdx.x;
+    const int nsp = min(rd.ctl->nspill, rd.n_total);
+    if (!force && nsp == 0) {
+        if (tid == 0) rd.ctl->relayout = 0;
+        return;
+    }
+    const int np = rd.n_patch;
+    for (int p = tid; p < np; p += PLAN_BLOCK) {
+        const int cap = rd.seg[p + 1] - rd.seg[p];
+        const int c = rd.cnt[p];
+        rd.tot[p] = c < cap ? c : cap;
+        rd.fill[p] = 0;
+    }
+    __syncthreads();
+    for (int i = tid; i < nsp; i += PLAN_BLOCK) atomicAdd(&rd.tot[rd.spatch[i]], 1);
+    __syncthreads();
+    // contiguous chunk of patches per thread
+    const int chunk = (np + PLAN_BLOCK - 1) / PLAN_BLOCK;
+    const int p0 = tid * chunk, p1 = min(np, p0 + chunk);
+    long long want = 0;
+    for (int p = p0; p < p1; ++p) {
+        const int t = rd.tot[p];
+        want += t + t / 4 + 16;
+    }
+    long long total;
+    block_exclusive_scan(want, buf, total);
+    // fall back to an even share of the free slots if the generous layout
+    // does not fit
+    const bool tight = total > rd.cap_total;
+    const int slack = tight ? (rd.cap_total - rd.n_total) / (np > 0 ? np : 1) : 0;
+    long long mine = 0;
+    for (int p = p0; p < p1; ++p) {
+        const int t = rd.tot[p];
+        mine += tight ? t + slack : t + t / 4 + 16;
+    }
+    long long tot2;
+    long long off = block_exclusive_scan(mine, buf, tot2);
+    for (int p = p0; p < p1; ++p) {
+        rd.seg2[p] = (int)off;
+        const int t = rd.tot[p];
+        off += tight ? t + slack : t + t / 4 + 16;
+    }
+    if (tid == 0) {
+        rd.seg2[np] = (int)tot2;
+        rd.ctl->relayout = 1;
+    }
+}
+
+template <int DIM, class T>
+__global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__restrict__ runs,
+                                                             const int *__restrict__ slots)
+{
+    const RunDev &rd = runs[slots[blockIdx.y]];
+    if (!rd.ctl->relayout) return;
+    const int np = rd.n_patch;
+    const int n_spill_blocks = (int)gridDim.x - np;   // >= 1 by construction
+    if ((int)blockIdx.x < np) {
+        const int p = blockIdx.x;
+        const int cap = rd.seg[p + 1] - rd.seg[p];
+        const int c = rd.cnt[p];
+        const int r = c < cap ? c : cap;
+        for (int i = threadIdx.x; i < r; i += BLOCK)
+            copy_part<DIM, T>(rd.st, (long long)rd.seg[p] + i, rd.lv, (long long)rd.seg2[p] + i);
+        return;
+    }
+    const int nsp = min(rd.ctl->nspill, rd.n_total);
+    for (int i = (blockIdx.x - np) * BLOCK + threadIdx.x; i < nsp; i += n_spill_blocks * BLOCK) {
+        const int q = rd.spatch[i];
+        const int cap = rd.seg[q + 1] - rd.seg[q];
+        const int c = rd.cnt[q];
+        const int r = c < cap ? c : cap;
+        const int slot = rd.seg2[q] + r + atomicAdd(&rd.fill[q], 1);
+        copy_part<DIM, T>(rd.sp, i, rd.lv, slot);
+    }
+}
+
+template <int DIM, class T>
+__global__ __launch_bounds__(BLOCK) void relayout_commit_kernel(const RunDev *__restrict__ runs,
+                                                               const int *__restrict__ slots)
+{
+    const RunDev &rd = runs[slots[blockIdx.y]];
+    if (!rd.ctl->relayout) return;
+    const int np = rd.n_patch;
+    const int total = rd.seg2[np];
+    const int stride = gridDim.x * BLOCK;
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < total; i += stride) copy_part<DIM, T>(rd.lv, i, rd.st, i);
+    for (int p = blockIdx.x * BLOCK + threadIdx.x; p <= np; p += stride) {
+        rd.seg[p] = rd.seg2[p];
+        if (p < np) rd.cnt[p] = rd.tot[p];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        rd.ctl->nspill = 0;
+        rd.ctl->n_relayout += 1;
+    }
+}
+
+// ---------------------------------------------------------------- export
+template <int DIM, class T>
+__device__ __forceinline__ void export_one(const RunDev &rd, const Store &s, long long i, int q, long long o, double *x,
+                                           double *y, double *z, double *ux, double *uy, double *uz, double *w,
+                                           uint32_t *id, int *patch)
+{
+    Part<T> p;
+    load_part<DIM, T>(s, i, p);
+    double *pos[3] = {x, y, z};
+    const int pq[3] = {q % rd.np[0], (q / rd.np[0]) % rd.np[1], DIM == 3 ? q / (rd.np[0] * rd.np[1]) : 0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        if (!pos[a]) continue;
+        if constexpr (T::split) {
+            const int c = pq[a] * rd.P[a] + ((p.cell >> (5 * a)) & 31);
+            pos[a][o] = ((double)c + (double)p.pos[a]) * rd.d[a];
+        } else {
+            pos[a][o] = (double)p.pos[a];
+        }
+    }
+    if (DIM == 2 && z) z[o] = 0.0;
+    if (ux) ux[o] = (double)p.u[0];
+    if (uy) uy[o] = (double)p.u[1];
+    if (uz) uz[o] = (double)p.u[2];
+    if (w) w[o] = (double)p.w;
+    if (id) id[o] = s.id ? p.id : 0u;
+    if (patch) patch[o] = q;
+}
+
+template <int DIM, class T>
+__global__ __launch_bounds__(BLOCK) void export_kernel(const RunDev *__restrict__ runs, int run, int nspill,
+                                                       const int *__restrict__ off, double *x, double *y, double *z,
+                                                       double *ux, double *uy, double *uz, double *w, uint32_t *id,
+                                                       int *patch)
+{
+    const RunDev &rd = runs[run];
+    const int np = rd.n_patch;
+    if ((int)blockIdx.x < np) {
+        const int q = blockIdx.x;
+        const int cap = rd.seg[q + 1] - rd.seg[q];
+        const int c = rd.cnt[q];
+        const int r = c < cap ? c : cap;
+        for (int i = threadIdx.x; i < r; i += BLOCK)
+            export_one<DIM, T>(rd, rd.st, (long long)rd.seg[q] + i, q, (long long)off[q] + i, x, y, z, ux, uy, uz, w, id,
+                               patch);
+        return;
+    }
+    const int nb = gridDim.x - np;
+    for (int i = (blockIdx.x - np) * BLOCK + threadIdx.x; i < nspill; i += nb * BLOCK)
+        export_one<DIM, T>(rd, rd.sp, i, rd.spatch[i], (long long)off[np] + i, x, y, z, ux, uy, uz, w, id, patch);
+}
+
+// ---------------------------------------------------------------- kinetic energy
+template <int DIM, class T>
+__global__ __launch_bounds__(BLOCK) void kinetic_kernel(const RunDev *__restrict__ runs, int run, int nspill,
+                                                        double *__restrict__ partial)
+{
+    using R = typename T::real;
+    const RunDev &rd = runs[run];
+    __shared__ double sk[BLOCK];
+    const int np = rd.n_patch;
+    double k = 0.0;
+    auto add = [&](const Store &s, long long i) {
+        const double a = ((const R *)s.u[0])[i], b = ((const R *)s.u[1])[i], c = ((const R *)s.u[2])[i];
+        const double g = sqrt(1.0 + a * a + b * b + c * c);
+        k += rd.m * (double)((const R *)s.w)[i] * (g - 1.0);
+    };
+    if ((int)blockIdx.x < np) {
+        const int q = blockIdx.x;
+        const int cap = rd.seg[q + 1] - rd.seg[q];
+        const int c = rd.cnt[q];
+        const int r = c < cap ? c : cap;
+        for (int i = threadIdx.x; i < r; i += BLOCK) add(rd.st, (long long)rd.seg[q] + i);
+    } else {
+        for (int i = threadIdx.x; i < nspill; i += BLOCK) add(rd.sp, i);
+    }
+    sk[threadIdx.x] = k;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sk[threadIdx.x] += sk[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sk[0];
+}
+
+// ---------------------------------------------------------------- charge density
+template <int DIM, class T>
+__device__ __forceinline__ void rho_one(const RunDev &rd, const Store &s, long long i, int q, double *rho)
+{
+    Part<T> p;
+    load_part<DIM, T>(s, i, p);
+    const int pq[3] = {q % rd.np[0], (q / rd.np[0]) % rd.np[1], DIM == 3 ? q / (rd.np[0] * rd.np[1]) : 0};
+    int base[3] = {0, 0, 0};
+    double wt[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double X;
+        if constexpr (T::split)
+            X = (double)(pq[a] * rd.P[a] + ((p.cell >> (5 * a)) & 31)) + (double)p.pos[a];
+        else
+            X = (double)p.pos[a] / rd.d[a];
+        const double f = floor(X + 0.5);
+        base[a] = (int)f - 1;
+        shape3(X - f, wt[a][0], wt[a][1], wt[a][2]);
+    }
+    const double qw = rd.q * (double)p.w;
+    const int nk = DIM == 3 ? 3 : 1;
+    for (int k = 0; k < nk; ++k)
+        for (int j = 0; j < 3; ++j)
+            for (int ii = 0; ii < 3; ++ii) {
+                const int gi = wrapi(base[0] + ii, rd.n[0]), gj = wrapi(base[1] + j, rd.n[1]);
+                const int gk = DIM == 3 ? wrapi(base[2] + k, rd.n[2]) : 0;
+                const double v = qw * wt[0][ii] * wt[1][j] * (DIM == 3 ? wt[2][k] : 1.0);
+                atomicAdd(&rho[gi + (long long)rd.n[0] * (gj + (long long)rd.n[1] * gk)], v);
+            }
+}
+
+template <int DIM, class T>
+__global__ __launch_bounds__(BLOCK) void rho_kernel(const RunDev *__restrict__ runs, int run, int nspill,
+                                                    double *__restrict__ rho)
+{
+    const RunDev &rd = runs[run];
+    const int np = rd.n_patch;
+    if ((int)blockIdx.x < np) {
+        const int q = blockIdx.x;
+        const int cap = rd.seg[q + 1] - rd.seg[q];
+        const int c = rd.cnt[q];
+        const int r = c < cap ? c : cap;
+        for (int i = threadIdx.x; i < r; i += BLOCK) rho_one<DIM, T>(rd, rd.st, (long long)rd.seg[q] + i, q, rho);
+        return;
+    }
+    for (int i = threadIdx.x; i < nspill; i += BLOCK) rho_one<DIM, T>(rd, rd.sp, i, rd.spatch[i], rho);
+}
+
+__global__ void fill_kernel(double *p, long long n, double v)
+{
+    const long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------- launchers
+#define DISPATCH(D, TT, BODY)                      \
+    if (dims == D && split == TT::split) {         \
+        BODY(D, TT);                               \
+        return hipGetLastError();                  \
+    }
+#define DISPATCH_ALL(BODY)       \
+    DISPATCH(2, F32S, BODY)      \
+    DISPATCH(2, FP64, BODY)      \
+    DISPATCH(3, F32S, BODY)      \
+    DISPATCH(3, FP64, BODY)      \
+    return hipErrorInvalidValue;
+
+hipError_t launch_convert(int dims, bool split, const RunDev *runs, int run, int n, const double *x, const double *y,
+                          const double *z, const double *ux, const double *uy, const double *uz, const double *w,
+                          const uint32_t *id, hipStream_t s)
+{
+    const int nb = n > 0 ? (n + BLOCK - 1) / BLOCK : 1;
+#define CONVERT_BODY(D, TT) convert_kernel<D, TT><<<nb, BLOCK, 0, s>>>(runs, run, n, x, y, z, ux, uy, uz, w, id)
+    DISPATCH_ALL(CONVERT_BODY)
+}
+
+static int spill_blocks(int n_total)
+{
+    int b = n_total / (BLOCK * 64);
+    return b < 1 ? 1 : (b > 1024 ? 1024 : b);
+}
+
+hipError_t launch_relayout(int dims, bool split, const RunDev *runs, const int *slots, int n_slots, int move_gx,
+                           int commit_gx, int force, hipStream_t s)
+{
+    if (n_slots <= 0) return hipSuccess;
+    relayout_plan_kernel<<<n_slots, PLAN_BLOCK, 0, s>>>(runs, slots, force);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define RELAYOUT_BODY(D, TT)                                                                   \
+    relayout_move_kernel<D, TT><<<dim3(move_gx, n_slots), BLOCK, 0, s>>>(runs, slots);         \
+    e = hipGetLastError();                                                                     \
+    if (e != hipSuccess) return e;                                                             \
+    relayout_commit_kernel<D, TT><<<dim3(commit_gx, n_slots), BLOCK, 0, s>>>(runs, slots)
+    DISPATCH_ALL(RELAYOUT_BODY)
+}
+
+hipError_t launch_export(int dims, bool split, const RunDev *runs, int run, int n_patch, int nspill, const int *off,
+                         double *x, double *y, double *z, double *ux, double *uy, double *uz, double *w, uint32_t *id,
+                         int *patch, hipStream_t s)
+{
+    const int nb = n_patch + spill_blocks(nspill > 0 ? nspill * 64 : 1);
+#define EXPORT_BODY(D, TT) \
+    export_kernel<D, TT><<<nb, BLOCK, 0, s>>>(runs, run, nspill, off, x, y, z, ux, uy, uz, w, id, patch)
+    DISPATCH_ALL(EXPORT_BODY)
+}
+
+hipError_t launch_kinetic(int dims, bool split, const RunDev *runs, int run, int n_patch, int nspill, double *partial,
+                          hipStream_t s)
+{
+#define KIN_BODY(D, TT) kinetic_kernel<D, TT><<<n_patch + 1, BLOCK, 0, s>>>(runs, run, nspill, partial)
+    DISPATCH_ALL(KIN_BODY)
+}
+
+hipError_t launch_rho(int dims, bool split, const RunDev *runs, int run, int n_patch, int nspill, int ncell,
+                      double *rho, hipStream_t s)
+{
+    fill_kernel<<<(ncell + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(rho, ncell, 0.0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define RHO_BODY(D, TT) rho_kernel<D, TT><<<n_patch + 1, BLOCK, 0, s>>>(runs, run, nspill, rho)
+    DISPATCH_ALL(RHO_BODY)
+}
+
+}  // namespace sdmd

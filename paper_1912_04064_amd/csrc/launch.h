@@ -1,0 +1,57 @@
+// launch.h -- host-side launchers of the SDMD kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sdmd_dev.h"
+
+namespace sdmd {
+
+// particles phase (one workgroup per push item = (run, patch))
+hipError_t launch_push(int dims, bool split, int pc, const RunDev *runs, const int2 *items, int n_items, int par,
+                       hipStream_t s);
+
+// transfer (i) + Maxwell: items (run, region, tile, first-item-of-run flag)
+hipError_t launch_yee(int dims, bool split, const RunDev *runs, const int4 *items, int n_items, int par,
+                      hipStream_t s);
+
+// ghost synchronisation of the new fields + insertion of the leavers:
+// items (run, kind, a, b); kind 0 ghost chunk starting at a, kind 1 insert
+// block a of b
+hipError_t launch_post(int dims, bool split, const RunDev *runs, const int4 *items, int n_items, int par_new,
+                       hipStream_t s);
+
+// ghost synchronisation alone, components [c0, c0 + nc) of one run
+hipError_t launch_ghosts(const RunDev *runs, int run, int total_ghosts, int c0, int nc, hipStream_t s);
+
+// initial fields: global FP64 staging (3 components) -> region interiors of
+// components [c0, c0+3)
+hipError_t launch_scatter_fields(const RunDev *runs, int run, int ncell, const double *src, int c0, hipStream_t s);
+// region interiors of component c -> global FP64 array
+hipError_t launch_assemble(const RunDev *runs, int run, int ncell, int comp, double *dst, hipStream_t s);
+// Bm = B, then B -= dt/2 curl E on every region interior (buffer par)
+hipError_t launch_half_faraday(const RunDev *runs, int run, int ncell, int par, hipStream_t s);
+
+// particles: FP64 staging -> spill store with patch ids
+hipError_t launch_convert(int dims, bool split, const RunDev *runs, int run, int n, const double *x, const double *y,
+                          const double *z, const double *ux, const double *uy, const double *uz, const double *w,
+                          const uint32_t *id, hipStream_t s);
+// re-layout of the patch stores of the runs listed in slots[0..n_slots)
+// (plan / move / commit); force = 1 re-lays out even without parked particles
+hipError_t launch_relayout(int dims, bool split, const RunDev *runs, const int *slots, int n_slots, int move_gx,
+                           int commit_gx, int force, hipStream_t s);
+// export: live particles -> FP64 arrays at per-patch offsets (off[n_patch]
+// = start of the spill part)
+hipError_t launch_export(int dims, bool split, const RunDev *runs, int run, int n_patch, int nspill, const int *off,
+                         double *x, double *y, double *z, double *ux, double *uy, double *uz, double *w, uint32_t *id,
+                         int *patch, hipStream_t s);
+// diagnostics: partial sums (field energy per block; kinetic per patch)
+hipError_t launch_field_energy(const RunDev *runs, int run, int ncell, int par, double *partial, int nblocks,
+                               hipStream_t s);
+hipError_t launch_kinetic(int dims, bool split, const RunDev *runs, int run, int n_patch, int nspill, double *partial,
+                          hipStream_t s);
+// charge density (electrons) at primal nodes, global FP64 array (zeroed here)
+hipError_t launch_rho(int dims, bool split, const RunDev *runs, int run, int n_patch, int nspill, int ncell,
+                      double *rho, hipStream_t s);
+
+}  // namespace sdmd

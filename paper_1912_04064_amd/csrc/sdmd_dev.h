@@ -1,0 +1,141 @@
+// sdmd_dev.h -- device-side data layout shared by the kernels and the host
+// runtime of the SDMD PIC library (gfx950).
+//
+// Layout in HBM (one run):
+//   regions  : FP64, all regions of the run back to back,
+//              [region][component 0..17][z][y][x] with GH ghost layers per
+//              side (none along z in 2D).  Components: E (two buffers, 3
+//              each), B (two buffers, 3 each), Bm (B time-centred at t^n),
+//              J (current of the last step).  E and B are double-buffered so
+//              the fused Ampere/Faraday kernel can recompute a one-node halo
+//              of E^{n+1} without reading values another workgroup already
+//              overwrote.
+//   tiles    : per patch, 3 current components on the nodes the patch's
+//              particles can reach, [patch][component][z][y][x], extent P+5
+//              per axis, origin = patch origin - 2 (FP32 in the split form,
+//              FP64 in the plain form).
+//   particles: SoA, patch-segmented.  Patch p owns slots [seg[p], seg[p+1])
+//              of which the first cnt[p] are live.  A second store of the
+//              same capacity receives the particles leaving their patch
+//              each step and serves as the scratch of a re-layout; a third
+//              one ("spill") parks particles that found their patch segment
+//              full until the next re-layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sdmd {
+
+constexpr int GH = 2;          // ghost layers around each region
+constexpr int F_E0 = 0;        // E, buffer 0 (3 components)
+constexpr int F_B0 = 6;        // B, buffer 0 (3 components)
+constexpr int F_BM = 12;       // Bm
+constexpr int F_J = 15;        // J
+constexpr int F_NCOMP = 18;
+__host__ __device__ inline int f_E(int par) { return F_E0 + 3 * par; }
+__host__ __device__ inline int f_B(int par) { return F_B0 + 3 * par; }
+
+constexpr int BLOCK = 256;     // threads per workgroup of the step kernels
+
+// error flag bits (Ctl::err)
+constexpr int ERR_NONFINITE = 1;
+constexpr int ERR_MOVE = 2;
+constexpr int ERR_CAPACITY = 4;
+constexpr int ERR_RANGE = 8;
+
+// precision traits
+struct FP64 {
+    using real = double;
+    static constexpr bool split = false;
+};
+struct F32S {
+    using real = float;
+    static constexpr bool split = true;
+};
+
+// one particle store, SoA.  pos: global position (FP64 form) or in-cell
+// offset xi in [0,1) (split form).  cell: split form only, the cell inside
+// the owning patch packed as lx | ly << 5 | lz << 10.
+struct Store {
+    void *pos[3];
+    uint16_t *cell;
+    void *u[3];
+    void *w;
+    uint32_t *id;   // null when ids are not tracked
+};
+
+// per-run device counters
+struct Ctl {
+    int nleave;       // particles written to the leaver store this step
+    int nspill;       // particles parked in the spill store
+    int ins_done;     // insert workgroups finished (last one resets nleave)
+    int err;          // ERR_* bits, sticky
+    int relayout;     // set by the re-layout planner when a re-layout runs
+    int n_relayout;   // re-layouts done
+    int max_spill;    // largest nspill seen
+    int pad;
+};
+
+struct RunDev {
+    int dims, prec;
+    int n[3];            // cells per axis (n[2] = 1 in 2D)
+    int P[3];            // cells per patch per axis (1 in 2D z)
+    int np[3];           // patches per axis
+    int n_patch;
+    int nreg[3];         // regions per axis
+    int rs[3];           // region interior cells per axis
+    int ra[3];           // region allocated nodes per axis (rs + 2 GH; 1 in 2D z)
+    int n_regions;
+    long long rsize;     // nodes per component per region
+    int TA[3];           // tile extent per axis (P + 5; 1 in 2D z)
+    int tsz;             // nodes per tile component
+    int cap_total;       // slots of the patch store
+    int n_total;         // particles of the run
+    int ins_blocks;      // insert workgroups per step
+    int ghosts;          // ghost nodes per region
+    double d[3], L[3];
+    double dt, q, m;
+    double qmh;          // (q/m) dt/2
+    float f_qmh;
+    float f_dtd[3];      // dt / d  (split form displacement in cells per unit velocity)
+    float f_cj[3];       // -q d / dt (Esirkepov prefactor, times w)
+    float f_q;
+    double *fld;         // regions
+    void *tiles;
+    int *seg, *cnt;      // [n_patch + 1], [n_patch]
+    int *seg2, *tot, *fill;   // re-layout scratch
+    Store st, lv, sp;    // patch store, leaver / scratch store, spill store
+    int *lpatch, *spatch;
+    Ctl *ctl;
+};
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ long long rindex(const RunDev &r, int li, int lj, int lk)
+{
+    const int gz = (r.dims == 3) ? GH : 0;
+    return (long long)(li + GH) + (long long)r.ra[0] * ((lj + GH) + (long long)r.ra[1] * (lk + gz));
+}
+
+__device__ __forceinline__ double *rcomp(const RunDev &r, int region, int comp)
+{
+    return r.fld + ((long long)region * F_NCOMP + comp) * r.rsize;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// quadratic B-spline weights at nodes -1, 0, +1 for offset d in [-1/2, 1/2]
+template <class R>
+__device__ __forceinline__ void shape3(R d, R &w0, R &w1, R &w2)
+{
+    R a = R(0.5) - d, b = R(0.5) + d;
+    w0 = R(0.5) * a * a;
+    w1 = R(0.75) - d * d;
+    w2 = R(0.5) * b * b;
+}
+
+}  // namespace sdmd

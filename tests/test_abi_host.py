@@ -1,0 +1,72 @@
+"""Host-side checks of the C ABI library: it loads, exports every entry point
+the header declares, and validates configurations without a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1912_04064_amd import binding as B
+from paper_1912_04064_amd import workloads as WL
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "sdmd_pic.h")).read()
+    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.load()
+    names = _declared()
+    assert set(names) == set(B.EXPORTED)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_strerror_texts():
+    L = B.load()
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert L.pic_strerror(code)
+    assert L.pic_strerror(-99) == b"unknown error"
+
+
+def _cfg(**over):
+    wl = WL.thermal_2d(n=(32, 32), ppc=1)
+    for k, v in over.items():
+        setattr(wl, k, v)
+    return wl
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(patch=(3, 8)), "patch size must be >= 4"),
+    (dict(patch=(6, 8)), "divide"),
+    (dict(patch=(64, 8)), "<= 32"),
+    (dict(dt=1.0), "dt must satisfy"),
+    (dict(nreg=(3, 1)), "whole patches"),
+    (dict(dims=4), "dims must be 2 or 3"),
+])
+def test_config_validation(change, msg):
+    wl = _cfg(**change)
+    with pytest.raises(B.PicError) as e:
+        B.mem_bytes(wl)
+    assert e.value.code == B.PIC_E_CONFIG
+    assert msg in str(e.value)
+
+
+def test_mem_bytes_scales_with_particles():
+    a = B.mem_bytes(WL.thermal_2d(n=(64, 64), ppc=4, patch=(8, 8)))
+    b = B.mem_bytes(WL.thermal_2d(n=(64, 64), ppc=16, patch=(8, 8)))
+    assert b > a > 64 * 64 * 18 * 8
+
+
+def test_init_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    L = B.load()
+    ctx = C.c_void_p()
+    rc = L.pic_init(None, 0, None, C.byref(ctx))
+    assert rc == B.PIC_E_DEVICE

@@ -1,0 +1,282 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: binning bit-exact; FP64 path within round-off of the oracle after one
+step; fields and currents within 1e-5 relative after 1 step and 1e-3 after 100
+steps (relative L2 per component, small components measured against their
+family's norm); energy drift reported.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1912_04064_amd import binding as B
+from paper_1912_04064_amd import workloads as WL
+from tests.helpers import family_errors, oracle_state
+
+pytestmark = pytest.mark.gpu
+
+MASK = B.F_E | B.F_B | B.F_BH | B.F_J
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(wl, steps, track_ids=True, graph=True):
+    with B.Context([wl], track_ids=track_ids, graph=graph) as ctx:
+        if steps:
+            ctx.step(steps)
+        F = ctx.fields(0, MASK)
+        parts = B.sort_by_id(ctx.particles(0)) if track_ids else None
+        diag = ctx.diag(0)
+    return {"E": F[0:3], "Bm": F[3:6], "BH": F[6:9], "J": F[9:12]}, parts, diag
+
+
+def oracle_run(wl, steps):
+    g, F, P = oracle_state(wl)
+    for _ in range(steps):
+        O.step_sdsd(g, F, P)
+    return {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]}, P, g
+
+
+def max_family_error(Fg, Fo):
+    errs = {}
+    for k in ("E", "BH", "Bm", "J"):
+        if np.linalg.norm(Fo[k]) == 0:
+            errs[k] = float(np.abs(Fg[k]).max())
+        else:
+            errs[k] = max(family_errors(Fg[k], Fo[k]))
+    return errs
+
+
+def wrapped_diff(a, b, L):
+    d = np.abs(a - b)
+    return np.minimum(d, L - d)
+
+
+# ---------------------------------------------------------------- binning
+@pytest.mark.parametrize("prec", ["fp64", "fp32s"])
+def test_binning_bit_exact_with_edge_inputs(prec):
+    say(f"case: binning {prec}")
+    rng = np.random.default_rng(101)
+    n, d = (64, 32), (0.1, 0.2)
+    Lx, Ly = n[0] * d[0], n[1] * d[1]
+    xs = list(rng.uniform(0, Lx, 5000))
+    ys = list(rng.uniform(0, Ly, 5000))
+    edge_x = [0.0, np.nextafter(Lx, 0), 0.8, np.nextafter(0.8, 0), np.nextafter(0.8, 1), 1.6, 2.4, 3.2,
+              (5 + (1 - 1e-12)) * d[0], np.nextafter(6.8 * 0.1 * 10 / 10, 0)]
+    edge_y = [np.nextafter(Ly, 0), 0.0, 1.6, 1.6, np.nextafter(3.2, 0), 0.2, 0.4, (7 + (1 - 1e-12)) * d[1], 3.0,
+              1.0]
+    xs += edge_x
+    ys += edge_y
+    N = len(xs)
+    parts = {"x": np.array(xs), "y": np.array(ys), "z": np.zeros(N), "ux": np.zeros(N), "uy": np.zeros(N),
+             "uz": np.zeros(N), "w": np.ones(N), "id": np.arange(N, dtype=np.uint32)}
+    wl = WL.Workload(name="bin", dims=2, n=n, d=d, dt=0.05, patch=(8, 8), nreg=(1, 1), steps=0, precision=prec,
+                     parts=parts)
+    _, gp, diag = gpu_run(wl, 0)
+    assert len(gp["id"]) == N and np.array_equal(gp["id"], np.arange(N))
+    g = O.Grid(2, n, d, 0.05, patch=(8, 8))
+    if prec == "fp64":
+        exp = O.bin_patches(g, O.Particles(x=parts["x"], y=parts["y"]))
+    else:
+        exp = np.zeros(N, np.int32)
+        for i in range(N):
+            ci, _ = O.split(parts["x"][i], d[0], n[0])
+            cj, _ = O.split(parts["y"][i], d[1], n[1])
+            exp[i] = ci // 8 + (n[0] // 8) * (cj // 8)
+    assert np.array_equal(gp["patch"], exp)
+    counts = np.bincount(gp["patch"], minlength=32)
+    assert counts.sum() == N and diag["patch_max"] == counts.max() and diag["patch_min"] == counts.min()
+
+
+# ---------------------------------------------------------------- Yee
+@pytest.mark.parametrize("dims", [2, 3])
+def test_vacuum_eigenmode(dims):
+    say(f"case: eigenmode {dims}D")
+    from tests.test_oracle_pins import _eigenmode
+    n = (32, 24) if dims == 2 else (24, 16, 16)
+    d = (0.3, 0.4) if dims == 2 else (0.3, 0.4, 0.5)
+    dt = WL.cfl_dt(d, 0.9)
+    g = O.Grid(dims, n, d, dt)
+    m = (3, 2, 0) if dims == 2 else (2, 1, 3)
+    F, omega, (e, b, phase) = _eigenmode(g, m, (1, -1, 0.5), 0.0)
+    parts = {k: np.zeros(0) for k in ("x", "y", "z", "ux", "uy", "uz", "w")}
+    parts["id"] = np.zeros(0, np.uint32)
+    wl = WL.Workload(name="vac", dims=dims, n=n, d=d, dt=dt, patch=(8,) * dims, nreg=(1,) * dims, steps=0,
+                     precision="fp64", parts=parts, E0=F[0:3], B0=F[3:6], Bm0=F[6:9], field_kind=1)
+    steps = 200
+    Fg, _, _ = gpu_run(wl, steps, track_ids=False)
+    t = steps * dt
+    for c in range(3):
+        np.testing.assert_allclose(Fg["E"][c], e[c] * phase(c, t), atol=5e-12)
+        np.testing.assert_allclose(Fg["BH"][c], b[c] * phase(3 + c, t + 0.5 * dt), atol=5e-12)
+
+
+def test_regions_one_vs_four_bitwise():
+    say("case: regions 1 vs 4")
+    rng = np.random.default_rng(7)
+    n, d = (128, 32), (0.125, 0.5)
+    dt = WL.cfl_dt(d)
+    E = rng.standard_normal((3, 1, 32, 128))
+    Bf = rng.standard_normal((3, 1, 32, 128))
+    parts = {k: np.zeros(0) for k in ("x", "y", "z", "ux", "uy", "uz", "w")}
+    parts["id"] = np.zeros(0, np.uint32)
+    out = []
+    for nreg in [(1, 1), (4, 1), (2, 2)]:
+        wl = WL.Workload(name="reg", dims=2, n=n, d=d, dt=dt, patch=(16, 8), nreg=nreg, steps=0, precision="fp64",
+                         parts=parts, E0=E, B0=Bf, Bm0=Bf, field_kind=1)
+        Fg, _, _ = gpu_run(wl, 20, track_ids=False)
+        out.append(Fg)
+    for k in ("E", "BH", "Bm"):
+        assert np.array_equal(out[0][k], out[1][k]) and np.array_equal(out[0][k], out[2][k]), k
+    # and the oracle's SDMD mode with 4 regions agrees with the global Yee
+    g = O.Grid(2, n, d, dt, patch=(16, 8), nreg=(4, 1))
+    F = g.zeros_fields()
+    F[0:3], F[3:6], F[6:9] = E, Bf, Bf
+    for _ in range(20):
+        O.step_sdmd(g, F, None)
+    assert np.abs(out[1]["E"] - F[0:3]).max() < 1e-12 * np.abs(F[0:3]).max()
+
+
+# ---------------------------------------------------------------- full steps
+@pytest.mark.parametrize("graph", [True, False])
+def test_fp64_one_step_matches_oracle(graph):
+    say(f"case: fp64 1 step thermal64 graph={graph}")
+    wl = WL.thermal_2d(precision="fp64")
+    Fg, gp, _ = gpu_run(wl, 1, graph=graph)
+    Fo, P, g = oracle_run(wl, 1)
+    errs = max_family_error(Fg, Fo)
+    say("fp64 1-step family errors", errs)
+    assert max(errs.values()) < 1e-12
+    L = wl.n[0] * wl.d[0]
+    assert wrapped_diff(gp["x"], P.x, L).max() < 1e-13
+    assert np.abs(gp["ux"] - P.ux).max() < 1e-15
+    assert np.abs(gp["uz"] - P.uz).max() < 1e-15
+
+
+@pytest.mark.parametrize("prec,tol1", [("fp64", 1e-12), ("fp32s", 1e-5)])
+def test_thermal64_100_steps(prec, tol1):
+    say(f"case: thermal64 {prec} 1 + 100 steps")
+    wl = WL.thermal_2d(precision=prec)
+    g, F, P = oracle_state(wl)
+    O.step_sdsd(g, F, P)
+    Fg1, _, _ = gpu_run(wl, 1, track_ids=False)
+    e1 = max_family_error(Fg1, {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]})
+    U0 = None
+    for _ in range(99):
+        O.step_sdsd(g, F, P)
+    Fg, gp, diag = gpu_run(wl, 100)
+    e100 = max_family_error(Fg, {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]})
+    uo = O.energy(g, F, P)
+    say(f"{prec}: 1-step {e1}; 100-step {e100}; GPU energy U_E {diag['U_E']:.6e} U_B {diag['U_B']:.6e} "
+        f"K {diag['K']:.6e} oracle {uo}")
+    assert max(e1.values()) < tol1
+    assert max(e100.values()) < 1e-3
+    assert diag["n_particles"] == wl.n_particles
+    assert diag["K"] == pytest.approx(uo[2], rel=1e-3)
+
+
+@pytest.mark.parametrize("prec,tol1", [("fp64", 1e-12), ("fp32s", 1e-5)])
+def test_3d_cylinder_steps(prec, tol1):
+    say(f"case: 3D cylinder {prec}")
+    wl = WL.cylinder_3d(n=(32, 16, 16), ppc_bg=2, ppc_cyl=16, radius=4.0, vth=0.05, precision=prec)
+    g, F, P = oracle_state(wl)
+    O.step_sdsd(g, F, P)
+    Fg1, _, _ = gpu_run(wl, 1, track_ids=False)
+    e1 = max_family_error(Fg1, {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]})
+    for _ in range(19):
+        O.step_sdsd(g, F, P)
+    Fg, gp, diag = gpu_run(wl, 20)
+    e20 = max_family_error(Fg, {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]})
+    say(f"3D {prec}: 1-step {e1}; 20-step {e20}")
+    assert max(e1.values()) < tol1
+    assert max(e20.values()) < 1e-3
+    assert diag["n_particles"] == wl.n_particles
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32s"])
+def test_lwfa_reduced_steps(prec):
+    """C2-shaped run at reduced size: laser, vacuum, ramp, plateau, 4 regions."""
+    say(f"case: lwfa reduced {prec}")
+    wl = WL.lwfa_2d(n=(512, 64), patch=(16, 16), nreg=(4, 1), vac_end=272, ramp=64, x0=17.0, waist=10.0,
+                    duration=8.0, precision=prec)
+    g, F, P = oracle_state(wl)
+    O.step_sdsd(g, F, P)
+    Fg1, _, _ = gpu_run(wl, 1, track_ids=False)
+    e1 = max_family_error(Fg1, {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]})
+    for _ in range(29):
+        O.step_sdsd(g, F, P)
+    Fg, gp, diag = gpu_run(wl, 30)
+    e30 = max_family_error(Fg, {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]})
+    say(f"lwfa {prec}: 1-step {e1}; 30-step {e30}")
+    assert max(e1.values()) < (1e-12 if prec == "fp64" else 1e-5)
+    assert max(e30.values()) < 1e-3
+
+
+def test_continuity_and_gauss_on_gpu_data():
+    """(rho1 - rho0)/dt + div J = 0 from the GPU's own rho and J, FP32 path."""
+    say("case: continuity fp32s")
+    wl = WL.thermal_2d(n=(64, 64), ppc=8, vth=0.1, precision="fp32s")
+    with B.Context([wl]) as ctx:
+        r0 = ctx.fields(0, B.F_RHO)[0]
+        ctx.step(1)
+        F = ctx.fields(0, B.F_RHO | B.F_J | B.F_E)
+    E, J, r1 = F[0:3], F[3:6], F[6]
+    dx, dy = wl.d
+    divJ = (J[0] - np.roll(J[0], 1, axis=2)) / dx + (J[1] - np.roll(J[1], 1, axis=1)) / dy
+    res = (r1 - r0) / wl.dt + divJ
+    scale = np.abs(r0).max() / wl.dt
+    say(f"continuity residual / (max rho / dt): {np.abs(res).max() / scale:.3e}")
+    assert np.abs(res).max() < 2e-6 * scale
+    divE = (E[0] - np.roll(E[0], 1, axis=2)) / dx + (E[1] - np.roll(E[1], 1, axis=1)) / dy
+    # E starts at zero, so div E^1 = rho^1 - rho^0 exactly up to round-off
+    assert np.abs(divE - (r1 - r0)).max() < 2e-6 * np.abs(r0).max()
+
+
+def test_converging_flow_spills_and_relayouts():
+    """Particles stream towards the centre: patches overflow their segment,
+    particles are parked and the store is re-laid out; results still match."""
+    say("case: converging flow")
+    n, d = (32, 32), (1.0, 1.0)
+    rng = np.random.default_rng(3)
+    N = 32 * 32 * 4
+    x = rng.uniform(0, 32, N)
+    y = rng.uniform(0, 32, N)
+    vx = -0.6 * np.sign(x - 16) * (np.abs(x - 16) > 2)
+    vy = -0.6 * np.sign(y - 16) * (np.abs(y - 16) > 2)
+    parts = {"x": x, "y": y, "z": np.zeros(N), "ux": vx, "uy": vy, "uz": np.zeros(N), "w": np.full(N, 0.25),
+             "id": np.arange(N, dtype=np.uint32)}
+    for prec in ("fp64", "fp32s"):
+        wl = WL.Workload(name="conv", dims=2, n=n, d=d, dt=0.6, patch=(8, 8), nreg=(1, 1), steps=0, precision=prec,
+                         parts=parts, q=-1e-6)
+        Fg, gp, diag = gpu_run(wl, 24)
+        Fo, P, g = oracle_run(wl, 24)
+        say(f"{prec}: relayouts {diag['n_relayout']} spill {diag['n_spill']} patch max {diag['patch_max']}")
+        assert diag["n_particles"] == N
+        assert diag["n_relayout"] >= 2          # the initial binning plus at least one overflow
+        assert np.array_equal(gp["id"], np.arange(N))
+        tol = 1e-9 if prec == "fp64" else 1e-4
+        assert wrapped_diff(gp["x"], P.x, 32.0).max() < tol
+        assert wrapped_diff(gp["y"], P.y, 32.0).max() < tol
+        errs = max_family_error(Fg, Fo)
+        assert max(errs.values()) < (1e-9 if prec == "fp64" else 1e-3), errs
+
+
+def test_empty_run_and_ragged_grid():
+    say("case: empty + ragged")
+    parts = {k: np.zeros(0) for k in ("x", "y", "z", "ux", "uy", "uz", "w")}
+    parts["id"] = np.zeros(0, np.uint32)
+    wl = WL.Workload(name="empty", dims=2, n=(72, 20), d=(0.1, 0.1), dt=0.05, patch=(8, 4), nreg=(3, 1), steps=0,
+                     precision="fp32s", parts=parts)
+    Fg, gp, diag = gpu_run(wl, 5)
+    assert diag["n_particles"] == 0 and np.all(Fg["E"] == 0) and len(gp["x"]) == 0
+    # ragged: region width 24 is not a multiple of the 64-wide field tile
+    wl = WL.thermal_2d(n=(72, 20), ppc=3, vth=0.05, patch=(8, 4), nreg=(3, 1), precision="fp64")
+    Fg, gp, _ = gpu_run(wl, 3)
+    Fo, P, _ = oracle_run(wl, 3)
+    assert max(max_family_error(Fg, Fo).values()) < 1e-11

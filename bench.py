@@ -35,6 +35,9 @@ def workload(name):
         return WL.lwfa_2d(precision="fp64")
     if name == "thermal64":
         return WL.thermal_2d()
+    if name == "thermal2k":
+        return WL.thermal_2d(n=(2048, 256), ppc=16, vth=0.05, patch=(16, 16), nreg=(4, 1), precision="fp32s",
+                             name="thermal2048x256")
     if name == "cyl3d":
         return WL.cylinder_3d()
     if name == "cyl3d_small":

@@ -102,6 +102,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+    # One HIP runtime per process: torch carries its own libamdhip64, so load
+    # torch first and let this library bind to that copy by soname.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     L.pic_init.argtypes = [C.POINTER(PicConfig), C.c_int32, C.POINTER(PicRuntime), C.POINTER(C.c_void_p)]
     L.pic_step.argtypes = [C.c_void_p, C.c_int32]

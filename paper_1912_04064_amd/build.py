@@ -3,6 +3,11 @@
 Every HIP source is compiled for gfx950 only, at -O3, with packed FP32
 instructions disabled (``-packed-fp32-ops``) and no fast-math, then linked
 into one shared library next to this file.  Object files go to ``_build/``.
+
+The library is loaded into processes that already hold PyTorch's HIP runtime
+(torch ships its own ``libamdhip64``).  The binding imports torch first so
+this library's ``libamdhip64.so.7`` dependency resolves to that same runtime
+by soname; code objects are emitted as version 5, which that runtime reads.
 """
 from __future__ import annotations
 
@@ -23,7 +28,7 @@ ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = [
-    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-I", INCLUDE, "-I", CSRC,

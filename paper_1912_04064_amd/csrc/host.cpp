@@ -40,7 +40,7 @@ struct DevBuf {
 
 struct Run {
     bool active = false;
-    int dims = 2, prec = PIC_FP64, pc = 8;
+    int dims = 2, prec = PIC_FP64, pc = 8, px = 0;
     bool split = false;
     int ncell = 0;
     int total_ghosts = 0;
@@ -51,7 +51,7 @@ struct Run {
 };
 
 struct PushClass {
-    int dims, pc;
+    int dims, pc, px;
     bool split;
     std::vector<int2> h;
     int2 *d = nullptr;
@@ -171,6 +171,19 @@ static int patch_class(int dims, const int P[3])
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// exact patch edge with a compiled fast path of the particle kernel, or 0
+static int fast_patch(const Layout &L)
+{
+    const bool square = L.P[0] == L.P[1] && (L.dims == 2 || L.P[2] == L.P[0]);
+    if (!square) return 0;
+    const int p = L.P[0];
+    if (L.dims == 2) {
+        if (p == 8 || p == 16 || (p == 32 && L.split)) return p;
+        return 0;
+    }
+    return p == 8 ? 8 : 0;
+}
 
 // validate a config (patch already chosen) and derive the layout
 static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::string &why)
@@ -354,6 +367,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     r.split = L.split;
     r.prec = cfg->precision;
     r.pc = L.pc;
+    r.px = fast_patch(L);
     r.ncell = L.n[0] * L.n[1] * L.n[2];
     r.total_ghosts = L.ghosts * L.n_regions;
     RunDev &d = r.rd;
@@ -478,6 +492,10 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
         HIPCHK(c, hipStreamSynchronize(s));
         for (auto &b : st) dev_free(c, b);
     }
+    // binning: the first re-layout gathers the particles into their patch
+    // segments, the second spreads each segment's storage order (see the
+    // permutation in the re-layout kernel)
+    if ((rc = relayout_one(c, slot, 1))) return rc;
     if ((rc = relayout_one(c, slot, 1))) return rc;
     if ((rc = check_run_err(c, slot))) {
         free_run(c, r);
@@ -522,9 +540,9 @@ static int rebuild_items(pic_ctx *c)
         if (!r.active) continue;
         PushClass *pc = nullptr;
         for (auto &x : c->pcls)
-            if (x.dims == r.dims && x.split == r.split && x.pc == r.pc) pc = &x;
+            if (x.dims == r.dims && x.split == r.split && x.pc == r.pc && x.px == r.px) pc = &x;
         if (!pc) {
-            c->pcls.push_back(PushClass{r.dims, r.pc, r.split});
+            c->pcls.push_back(PushClass{r.dims, r.pc, r.px, r.split});
             pc = &c->pcls.back();
         }
         FieldClass *fc = nullptr;
@@ -591,7 +609,7 @@ static int rebuild_items(pic_ctx *c)
 static hipError_t enqueue_push(pic_ctx *c, int par, hipStream_t s)
 {
     for (auto &pc : c->pcls) {
-        hipError_t e = launch_push(pc.dims, pc.split, pc.pc, c->d_runs, pc.d, (int)pc.h.size(), par, s);
+        hipError_t e = launch_push(pc.dims, pc.split, pc.px, pc.pc, c->d_runs, pc.d, (int)pc.h.size(), par, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

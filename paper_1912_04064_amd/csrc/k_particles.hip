@@ -145,6 +145,23 @@ __global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev 
     }
 }
 
+// multiplier of the in-segment permutation: the integer nearest 0.618 r
+// that is coprime with r (r >= 1)
+__device__ __forceinline__ long long scatter_stride(int r)
+{
+    if (r <= 2) return 1;
+    long long k = (long long)(0.6180339887498949 * r);
+    for (;; ++k) {
+        long long a = k, b = r;
+        while (b) {
+            const long long t = a % b;
+            a = b;
+            b = t;
+        }
+        if (a == 1) return k % r;
+    }
+}
+
 template <int DIM, class T>
 __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__restrict__ runs,
                                                              const int *__restrict__ slots)
@@ -154,12 +171,19 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
     const int np = rd.n_patch;
     const int n_spill_blocks = (int)gridDim.x - np;   // >= 1 by construction
     if ((int)blockIdx.x < np) {
+        // slot i of the new segment takes particle (i K) mod r of the old
+        // one, K ~ 0.618 r coprime with r: consecutive slots -- the lanes of
+        // one wavefront -- then hold particles from all over the patch
+        // instead of the same cell, so their LDS current-tile atomics hit
+        // different addresses.
         const int p = blockIdx.x;
         const int cap = rd.seg[p + 1] - rd.seg[p];
         const int c = rd.cnt[p];
         const int r = c < cap ? c : cap;
+        const long long K = scatter_stride(r);
         for (int i = threadIdx.x; i < r; i += BLOCK)
-            copy_part<DIM, T>(rd.st, (long long)rd.seg[p] + i, rd.lv, (long long)rd.seg2[p] + i);
+            copy_part<DIM, T>(rd.st, (long long)rd.seg[p] + (int)(((long long)i * K) % r), rd.lv,
+                              (long long)rd.seg2[p] + i);
         return;
     }
     const int nsp = min(rd.ctl->nspill, rd.n_total);

@@ -26,6 +26,7 @@ namespace sdmd {
 // node ip + k0 (k0 = -2 or -1) of the 5-node Esirkepov frame centred on the
 // old primal node ip.  d0: old offset from ip in [-1/2, 1/2); d1: new
 // position relative to ip in (-3/2, 3/2).  t0: tile index of the first node.
+// Plain form: DS = S(new) - S(old), node by node.
 template <class R>
 __device__ __forceinline__ void esirkepov_axis(R d0, R d1, int ip, R S0[4], R DS[4], int &t0)
 {
@@ -49,19 +50,75 @@ __device__ __forceinline__ void esirkepov_axis(R d0, R d1, int ip, R S0[4], R DS
     t0 = ip + (lo ? 0 : 1);   // tile origin is patch origin - 2
 }
 
+// Split form: the same DS written as polynomials in the displacement D, so
+// its rounding error is relative to D rather than to the shape values (a
+// cold particle moving 1e-6 cell would otherwise lose most digits of DS in
+// FP32).  d0: old offset from ip in [-1/2, 1/2); D: displacement in cells.
+// Three cases by where the new position falls: the same primal node, the
+// next one up (u, v = distances below / above the half-node knot), or the
+// next one down (mirror image).
+template <class R>
+__device__ __forceinline__ void esirkepov_axis_delta(R d0, R D, int ip, R S0[4], R DS[4], int &t0)
+{
+    R a0, a1, a2;
+    shape3(d0, a0, a1, a2);
+    const R d1 = d0 + D;
+    const bool up = d1 >= R(0.5), dn = d1 < R(-0.5);
+    // same node
+    R c0 = R(-0.5) * D * (R(1) - R(2) * d0 - D);
+    R c1 = -D * (R(2) * d0 + D);
+    R c2 = R(0.5) * D * (R(1) + R(2) * d0 + D);
+    R c3 = R(0);
+    if (up) {
+        const R u = R(0.5) - d0, v = D - u;
+        c0 = R(-0.5) * u * u;
+        c1 = -D + R(0.5) * v * v + u * u;
+        c2 = D - v * v - R(0.5) * u * u;
+        c3 = R(0.5) * v * v;
+    } else if (dn) {
+        const R u = R(0.5) + d0, v = -D - u;
+        c0 = R(0.5) * v * v;
+        c1 = -D - v * v - R(0.5) * u * u;
+        c2 = D + R(0.5) * v * v + u * u;
+        c3 = R(-0.5) * u * u;
+    }
+    S0[0] = dn ? R(0) : a0;
+    S0[1] = dn ? a0 : a1;
+    S0[2] = dn ? a1 : a2;
+    S0[3] = dn ? a2 : R(0);
+    DS[0] = c0;
+    DS[1] = c1;
+    DS[2] = c2;
+    DS[3] = c3;
+    t0 = ip + (dn ? 0 : 1);
+}
+
 // Push one particle: interpolate, Boris, move, deposit.  `p` is updated in
 // place (position, cell relative to the destination patch, momentum);
 // returns the destination patch.
-template <int DIM, class T>
-__device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real *__restrict__ win,
-                                        typename T::real *tile, const int W0, const int W1, const int WS,
-                                        const int T0, const int T1, const int TS, const int p0[3], const int P[3],
-                                        Part<T> &p, int &err)
+//
+// PX > 0: square (cubic) patches of PX cells, so every LDS stride is a
+// compile-time constant and the 54 (2D) window reads and 40 tile updates of
+// a particle are one base address plus immediate offsets.  PX = 0: patch
+// sizes read from the run descriptor.
+//
+// The current tile accumulates in FP64 in both precision forms: on gfx950
+// ds_add_f64 sustains ~23x the rate of ds_add_f32 (measured: 7.5 vs 0.33
+// lane-atomics per clock per CU); contributions are still computed in the
+// particle precision.
+template <int DIM, class T, int PX>
+__device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real *__restrict__ win, double *tile,
+                                        const int p0[3], const int Prt[3], Part<T> &p, int &err)
 {
     using R = typename T::real;
+    const int P0 = PX ? PX : Prt[0], P1 = PX ? PX : Prt[1], P2 = DIM == 3 ? (PX ? PX : Prt[2]) : 1;
+    const int P[3] = {P0, P1, P2};
+    const int W0 = P0 + 3, W1 = P1 + 3, WS = W0 * W1 * (DIM == 3 ? P2 + 3 : 1);
+    const int T0 = P0 + 5, T1 = P1 + 5, TS = T0 * T1 * (DIM == 3 ? P2 + 5 : 1);
+
     int lc[3] = {0, 0, 0}, ip[3] = {0, 0, 0};
     R wp[3][3], wd[3][3], dp[3];
-    R h[3];                  // split form: 1 when the primal node is the upper one
+    R h[3] = {R(0), R(0), R(0)};   // split form: 1 when the primal node is the upper one
     double X0[3] = {0, 0, 0};
     int ipg[3] = {0, 0, 0};
 #pragma unroll
@@ -70,23 +127,23 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
             int c = (p.cell >> (5 * a)) & 31;
             c = c < P[a] ? c : P[a] - 1;
             lc[a] = c;
-            R xi = p.pos[a];
+            const R xi = p.pos[a];
             h[a] = xi >= R(0.5) ? R(1) : R(0);
             ip[a] = c + (int)h[a];
             dp[a] = xi - h[a];
             shape3(dp[a], wp[a][0], wp[a][1], wp[a][2]);
             shape3(xi - R(0.5), wd[a][0], wd[a][1], wd[a][2]);
         } else {
-            double X = (double)p.pos[a] / rd.d[a];
+            const double X = (double)p.pos[a] / rd.d[a];
             X0[a] = X;
-            double fp = floor(X + 0.5), fd = floor(X);
+            const double fp = floor(X + 0.5), fd = floor(X);
             ipg[a] = (int)fp;
             dp[a] = (R)(X - fp);
             shape3(dp[a], wp[a][0], wp[a][1], wp[a][2]);
             shape3((R)(X - fd - 0.5), wd[a][0], wd[a][1], wd[a][2]);
-            int i = ipg[a] - p0[a];
+            const int i = ipg[a] - p0[a];
             ip[a] = i < 0 ? 0 : (i > P[a] ? P[a] : i);
-            int l = (int)fd - p0[a];
+            const int l = (int)fd - p0[a];
             lc[a] = l < 0 ? 0 : (l > P[a] ? P[a] : l);
         }
     }
@@ -95,13 +152,10 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
     R E[3], B[3];
     if constexpr (DIM == 2) {
         auto sum2 = [&](int c, const R *wx, int bx, const R *wy, int by) {
-            const R *A = win + c * WS;
+            const R *A = win + c * WS + by * W0 + bx;
             R s = R(0);
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const R *row = A + (by + b) * W0 + bx;
-                s += wy[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2]);
-            }
+            for (int b = 0; b < 3; ++b) s += wy[b] * (wx[0] * A[b * W0] + wx[1] * A[b * W0 + 1] + wx[2] * A[b * W0 + 2]);
             return s;
         };
         E[0] = sum2(0, wd[0], lc[0], wp[1], ip[1]);
@@ -112,14 +166,14 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
         B[2] = sum2(5, wd[0], lc[0], wd[1], lc[1]);
     } else {
         auto sum3 = [&](int c, const R *wx, int bx, const R *wy, int by, const R *wz, int bz) {
-            const R *A = win + c * WS;
+            const R *A = win + c * WS + (bz * W1 + by) * W0 + bx;
             R s = R(0);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 R sk = R(0);
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
-                    const R *row = A + ((bz + k) * W1 + by + b) * W0 + bx;
+                    const R *row = A + (k * W1 + b) * W0;
                     sk += wy[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2]);
                 }
                 s += wz[k] * sk;
@@ -135,21 +189,41 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
     }
 
     // ---- Boris push: half E kick, B rotation, half E kick
-    const R hq = T::split ? (R)rd.f_qmh : (R)rd.qmh;
-    R um[3] = {p.u[0] + hq * E[0], p.u[1] + hq * E[1], p.u[2] + hq * E[2]};
-    R gm = sqrt(R(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
-    R t[3] = {hq * B[0] / gm, hq * B[1] / gm, hq * B[2] / gm};
-    R t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
-    R s[3] = {R(2) * t[0] / (R(1) + t2), R(2) * t[1] / (R(1) + t2), R(2) * t[2] / (R(1) + t2)};
-    R up[3] = {um[0] + (um[1] * t[2] - um[2] * t[1]), um[1] + (um[2] * t[0] - um[0] * t[2]),
-               um[2] + (um[0] * t[1] - um[1] * t[0])};
-    R un[3] = {um[0] + (up[1] * s[2] - up[2] * s[1]), um[1] + (up[2] * s[0] - up[0] * s[2]),
-               um[2] + (up[0] * s[1] - up[1] * s[0])};
-    un[0] += hq * E[0];
-    un[1] += hq * E[1];
-    un[2] += hq * E[2];
+    R un[3], ig;   // new momentum, 1/gamma
+    if constexpr (T::split) {
+        // FP32: one hardware reciprocal square root and one reciprocal
+        // (1 ulp each) instead of correctly rounded divisions
+        const R hq = rd.f_qmh;
+        const R um[3] = {p.u[0] + hq * E[0], p.u[1] + hq * E[1], p.u[2] + hq * E[2]};
+        const R igm = __builtin_amdgcn_rsqf(R(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+        const R f = hq * igm;
+        const R t[3] = {f * B[0], f * B[1], f * B[2]};
+        const R k2 = R(2) * __builtin_amdgcn_rcpf(R(1) + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+        const R s[3] = {k2 * t[0], k2 * t[1], k2 * t[2]};
+        const R up[3] = {um[0] + (um[1] * t[2] - um[2] * t[1]), um[1] + (um[2] * t[0] - um[0] * t[2]),
+                         um[2] + (um[0] * t[1] - um[1] * t[0])};
+        un[0] = um[0] + (up[1] * s[2] - up[2] * s[1]) + hq * E[0];
+        un[1] = um[1] + (up[2] * s[0] - up[0] * s[2]) + hq * E[1];
+        un[2] = um[2] + (up[0] * s[1] - up[1] * s[0]) + hq * E[2];
+        ig = __builtin_amdgcn_rsqf(R(1) + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+    } else {
+        const R hq = (R)rd.qmh;
+        const R um[3] = {p.u[0] + hq * E[0], p.u[1] + hq * E[1], p.u[2] + hq * E[2]};
+        const R gm = sqrt(R(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+        const R t[3] = {hq * B[0] / gm, hq * B[1] / gm, hq * B[2] / gm};
+        const R t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+        const R s[3] = {R(2) * t[0] / (R(1) + t2), R(2) * t[1] / (R(1) + t2), R(2) * t[2] / (R(1) + t2)};
+        const R up[3] = {um[0] + (um[1] * t[2] - um[2] * t[1]), um[1] + (um[2] * t[0] - um[0] * t[2]),
+                         um[2] + (um[0] * t[1] - um[1] * t[0])};
+        un[0] = um[0] + (up[1] * s[2] - up[2] * s[1]);
+        un[1] = um[1] + (up[2] * s[0] - up[0] * s[2]);
+        un[2] = um[2] + (up[0] * s[1] - up[1] * s[0]);
+        un[0] += hq * E[0];
+        un[1] += hq * E[1];
+        un[2] += hq * E[2];
+        ig = R(1) / sqrt(R(1) + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+    }
     if (!(fabs(un[0]) < R(1e30) && fabs(un[1]) < R(1e30) && fabs(un[2]) < R(1e30))) err |= ERR_NONFINITE;
-    const R g = sqrt(R(1) + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
 
     // ---- move, new cell, Esirkepov frames
     R S0[3][4], DS[3][4];
@@ -158,14 +232,14 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         if constexpr (T::split) {
-            R delta = (un[a] / g) * rd.f_dtd[a];
+            R delta = (un[a] * ig) * rd.f_dtd[a];
             if (!(fabs(delta) < R(1))) {
                 err |= ERR_MOVE;
                 delta = R(0);
             }
-            R xn = p.pos[a] + delta;
-            esirkepov_axis<R>(dp[a], xn - h[a], ip[a], S0[a], DS[a], t0[a]);
-            R f = floor(xn);
+            const R xn = p.pos[a] + delta;
+            esirkepov_axis_delta<R>(dp[a], delta, ip[a], S0[a], DS[a], t0[a]);
+            const R f = floor(xn);
             int sh = (int)f;
             R xi2 = xn - f;
             if (xi2 >= R(1)) {
@@ -176,7 +250,7 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
             p.pos[a] = xi2;
             gcell[a] = wrapi(p0[a] + lc[a] + sh, rd.n[a]);
         } else {
-            double xn = (double)p.pos[a] + rd.dt * (double)un[a] / (double)g;
+            double xn = (double)p.pos[a] + rd.dt * (double)un[a] * (double)ig;
             double X1 = xn / rd.d[a];
             if (!(fabs(X1 - X0[a]) < 1.0)) {
                 err |= ERR_MOVE;
@@ -195,76 +269,78 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
         }
     }
 
-    // ---- Esirkepov deposition into the LDS tile
+    // ---- Esirkepov deposition into the LDS tile.  The weights factor as
+    // outer products: Jx = cx Cx[m] yf[n] with Cx the running sum of DSx and
+    // yf = S0y + DSy/2; Jz (2D) = cz (S0x[m] yf[n] + DSx[m] (S0y[n]/2 + DSy[n]/3)).
     const R third = R(1) / R(3);
     R cj[3];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) cj[a] = (T::split ? (R)rd.f_cj[a] : (R)(-rd.q * rd.d[a] / rd.dt)) * p.w;
+    double *Jb = tile + (DIM == 3 ? (t0[2] * T1 + t0[1]) * T0 + t0[0] : t0[1] * T0 + t0[0]);
     if constexpr (DIM == 2) {
-        const R cz = (T::split ? (R)rd.f_q : (R)rd.q) * p.w * (un[2] / g);
-        R *Jx = tile, *Jy = tile + TS, *Jz = tile + 2 * TS;
+        R hf[2][4], qf[2][4], cs[2][3];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            const R yf = S0[1][n] + R(0.5) * DS[1][n];
+        for (int a = 0; a < 2; ++a) {
             R acc = R(0);
 #pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                acc += DS[0][m] * yf;
-                atomicAdd(&Jx[(t0[1] + n) * T0 + t0[0] + m], cj[0] * acc);
+            for (int m = 0; m < 4; ++m) {
+                hf[a][m] = S0[a][m] + R(0.5) * DS[a][m];
+                qf[a][m] = R(0.5) * S0[a][m] + third * DS[a][m];
+                if (m < 3) {
+                    acc += DS[a][m];
+                    cs[a][m] = cj[a] * acc;
+                }
             }
         }
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const R xf = S0[0][m] + R(0.5) * DS[0][m];
-            R acc = R(0);
-#pragma unroll
-            for (int n = 0; n < 3; ++n) {
-                acc += DS[1][n] * xf;
-                atomicAdd(&Jy[(t0[1] + n) * T0 + t0[0] + m], cj[1] * acc);
-            }
-        }
+        const R cz = (T::split ? (R)rd.f_q : (R)rd.q) * p.w * (un[2] * ig);
 #pragma unroll
         for (int n = 0; n < 4; ++n)
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const R wz = S0[0][m] * S0[1][n] + R(0.5) * DS[0][m] * S0[1][n] + R(0.5) * S0[0][m] * DS[1][n] +
-                             third * DS[0][m] * DS[1][n];
-                atomicAdd(&Jz[(t0[1] + n) * T0 + t0[0] + m], cz * wz);
-            }
+            for (int m = 0; m < 3; ++m) atomicAdd(&Jb[n * T0 + m], (double)(cs[0][m] * hf[1][n]));
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) atomicAdd(&Jb[TS + n * T0 + m], (double)(cs[1][n] * hf[0][m]));
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const R a = cz * S0[0][m], b = cz * DS[0][m];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) atomicAdd(&Jb[2 * TS + n * T0 + m], (double)(a * hf[1][n] + b * qf[1][n]));
+        }
     } else {
-        R *Jc[3] = {tile, tile + TS, tile + 2 * TS};
-        // component c flows along axis c; the other two axes (u, v) carry
-        // the time-averaged transverse shape product
+        R hf[3][4], qf[3][4], cs[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            R acc = R(0);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                hf[a][m] = S0[a][m] + R(0.5) * DS[a][m];
+                qf[a][m] = R(0.5) * S0[a][m] + third * DS[a][m];
+                if (m < 3) {
+                    acc += DS[a][m];
+                    cs[a][m] = cj[a] * acc;
+                }
+            }
+        }
+        // component c flows along axis c; (u, v) are the other two axes in
+        // increasing order, carrying the time-averaged transverse product
+        // S0u (S0v + DSv/2) + DSu (S0v/2 + DSv/3)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const int u = (c + 1) % 3, v = (c + 2) % 3;
-            R tr[4][4];
+            const int u = c == 0 ? 1 : 0, v = c == 2 ? 1 : 2;
+            const int su = u == 0 ? 1 : (u == 1 ? T0 : T0 * T1);
+            const int sv = v == 1 ? T0 : T0 * T1;
+            const int sc = c == 0 ? 1 : (c == 1 ? T0 : T0 * T1);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    // keep the operand order of the transverse product in
-                    // (y,z), (x,z), (x,y) axis order
-                    const int lo = u < v ? u : v, hi = u < v ? v : u;
-                    const int il = u < v ? i : j, ih = u < v ? j : i;
-                    tr[i][j] = S0[lo][il] * S0[hi][ih] + R(0.5) * DS[lo][il] * S0[hi][ih] +
-                               R(0.5) * S0[lo][il] * DS[hi][ih] + third * DS[lo][il] * DS[hi][ih];
-                }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    R acc = R(0);
+                    const R tr = S0[u][i] * hf[v][j] + DS[u][i] * qf[v][j];
 #pragma unroll
-                    for (int m = 0; m < 3; ++m) {
-                        acc += DS[c][m] * tr[i][j];
-                        int idx[3];
-                        idx[c] = t0[c] + m;
-                        idx[u] = t0[u] + i;
-                        idx[v] = t0[v] + j;
-                        atomicAdd(&Jc[c][(idx[2] * T1 + idx[1]) * T0 + idx[0]], cj[c] * acc);
-                    }
+                    for (int m = 0; m < 3; ++m)
+                        atomicAdd(&Jb[c * TS + i * su + j * sv + m * sc], (double)(cs[c][m] * tr));
                 }
+            }
         }
     }
 
@@ -276,7 +352,7 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
     int dest = 0, mul = 1, packed = 0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        int pa = gcell[a] / P[a];
+        const int pa = gcell[a] / P[a];
         dest += pa * mul;
         mul *= rd.np[a];
         packed |= (gcell[a] - pa * P[a]) << (5 * a);
@@ -285,7 +361,9 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
     return dest;
 }
 
-template <int DIM, class T, int PC>
+// PX: exact patch edge (0 = sizes from the run descriptor); PC: LDS sizing
+// class (the largest patch edge the instantiation accepts)
+template <int DIM, class T, int PX, int PC>
 __global__ __launch_bounds__(BLOCK) void push_kernel(const RunDev *__restrict__ runs, const int2 *__restrict__ items,
                                                      int par)
 {
@@ -294,7 +372,7 @@ __global__ __launch_bounds__(BLOCK) void push_kernel(const RunDev *__restrict__ 
     constexpr int TN = (PC + 5) * (PC + 5) * (DIM == 3 ? PC + 5 : 1);
     constexpr int NW = BLOCK / 64;
     __shared__ R s_win[6 * WN];
-    __shared__ R s_tile[3 * TN];
+    __shared__ double s_tile[3 * TN];
     __shared__ int s_wsum[2][NW];
 
     const int2 item = items[blockIdx.x];
@@ -302,7 +380,7 @@ __global__ __launch_bounds__(BLOCK) void push_kernel(const RunDev *__restrict__ 
     const int q = item.y;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    const int P[3] = {rd.P[0], rd.P[1], DIM == 3 ? rd.P[2] : 1};
+    const int P[3] = {PX ? PX : rd.P[0], PX ? PX : rd.P[1], DIM == 3 ? (PX ? PX : rd.P[2]) : 1};
     const int pq[3] = {q % rd.np[0], (q / rd.np[0]) % rd.np[1], DIM == 3 ? q / (rd.np[0] * rd.np[1]) : 0};
     const int p0[3] = {pq[0] * P[0], pq[1] * P[1], pq[2] * P[2]};
     const int rr[3] = {p0[0] / rd.rs[0], p0[1] / rd.rs[1], DIM == 3 ? p0[2] / rd.rs[2] : 0};
@@ -310,8 +388,7 @@ __global__ __launch_bounds__(BLOCK) void push_kernel(const RunDev *__restrict__ 
     const int o[3] = {p0[0] - rr[0] * rd.rs[0], p0[1] - rr[1] * rd.rs[1], DIM == 3 ? p0[2] - rr[2] * rd.rs[2] : 0};
     const int W0 = P[0] + 3, W1 = P[1] + 3, W2 = DIM == 3 ? P[2] + 3 : 1;
     const int WS = W0 * W1 * W2;
-    const int T0 = rd.TA[0], T1 = rd.TA[1];
-    const int TS = rd.tsz;
+    const int TS = (P[0] + 5) * (P[1] + 5) * (DIM == 3 ? P[2] + 5 : 1);
 
     // transfer (ii): region E^n, Bm^n -> LDS window
     for (int idx = tid; idx < 6 * WS; idx += BLOCK) {
@@ -321,7 +398,7 @@ __global__ __launch_bounds__(BLOCK) void push_kernel(const RunDev *__restrict__ 
         const double *A = rcomp(rd, region, comp);
         s_win[idx] = (R)A[rindex(rd, o[0] - 1 + wx, o[1] - 1 + wy, DIM == 3 ? o[2] - 1 + wz : 0)];
     }
-    for (int idx = tid; idx < 3 * TS; idx += BLOCK) s_tile[idx] = R(0);
+    for (int idx = tid; idx < 3 * TS; idx += BLOCK) s_tile[idx] = 0.0;
     __syncthreads();
 
     const long long seg0 = rd.seg[q];
@@ -340,7 +417,7 @@ __global__ __launch_bounds__(BLOCK) void push_kernel(const RunDev *__restrict__ 
         int dest = q;
         if (valid) {
             load_part<DIM, T>(rd.st, seg0 + i, pt);
-            dest = push_one<DIM, T>(rd, s_win, s_tile, W0, W1, WS, T0, T1, TS, p0, P, pt, err);
+            dest = push_one<DIM, T, PX>(rd, s_win, s_tile, p0, P, pt, err);
         }
         const bool st = valid && dest == q;
         const bool lv = valid && dest != q;
@@ -384,7 +461,7 @@ __global__ __launch_bounds__(BLOCK) void push_kernel(const RunDev *__restrict__ 
         int dest = q;
         if (mine) {
             load_part<DIM, T>(rd.sp, i, pt);
-            dest = push_one<DIM, T>(rd, s_win, s_tile, W0, W1, WS, T0, T1, TS, p0, P, pt, err);
+            dest = push_one<DIM, T, PX>(rd, s_win, s_tile, p0, P, pt, err);
         }
         const unsigned long long ml = __ballot(mine);
         int lbase = 0;
@@ -406,29 +483,38 @@ __global__ __launch_bounds__(BLOCK) void push_kernel(const RunDev *__restrict__ 
     if (err) atomicOr(&rd.ctl->err, err);
     if (tid == 0) rd.cnt[q] = stay;
     __syncthreads();
-    // flush the tile (transfer (i) reads it)
+    // flush the tile in the tile precision (transfer (i) reads it)
     R *dst = (R *)rd.tiles + (long long)q * 3 * TS;
-    for (int idx = tid; idx < 3 * TS; idx += BLOCK) dst[idx] = s_tile[idx];
+    for (int idx = tid; idx < 3 * TS; idx += BLOCK) dst[idx] = (R)s_tile[idx];
 }
 
-#define PUSH_CASE(D, TT, PCV)                                                                       \
-    if (dims == D && split == TT::split && pc == PCV) {                                             \
-        push_kernel<D, TT, PCV><<<n_items, BLOCK, 0, s>>>(runs, items, par);                        \
+#define PUSH_CASE(D, TT, PXV, PCV)                                                                  \
+    if (dims == D && split == TT::split && px == PXV && pc == PCV) {                                \
+        push_kernel<D, TT, PXV, PCV><<<n_items, BLOCK, 0, s>>>(runs, items, par);                   \
         return hipGetLastError();                                                                   \
     }
 
-hipError_t launch_push(int dims, bool split, int pc, const RunDev *runs, const int2 *items, int n_items, int par,
-                       hipStream_t s)
+// px: exact square/cubic patch edge with a compiled fast path, else 0;
+// pc: LDS sizing class 8 / 16 / 32
+hipError_t launch_push(int dims, bool split, int px, int pc, const RunDev *runs, const int2 *items, int n_items,
+                       int par, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
-    PUSH_CASE(2, F32S, 8)
-    PUSH_CASE(2, F32S, 16)
-    PUSH_CASE(2, F32S, 32)
-    PUSH_CASE(2, FP64, 8)
-    PUSH_CASE(2, FP64, 16)
-    PUSH_CASE(2, FP64, 32)
-    PUSH_CASE(3, F32S, 8)
-    PUSH_CASE(3, FP64, 8)
+    PUSH_CASE(2, F32S, 8, 8)
+    PUSH_CASE(2, F32S, 16, 16)
+    PUSH_CASE(2, F32S, 32, 32)
+    PUSH_CASE(2, F32S, 0, 8)
+    PUSH_CASE(2, F32S, 0, 16)
+    PUSH_CASE(2, F32S, 0, 32)
+    PUSH_CASE(2, FP64, 8, 8)
+    PUSH_CASE(2, FP64, 16, 16)
+    PUSH_CASE(2, FP64, 0, 8)
+    PUSH_CASE(2, FP64, 0, 16)
+    PUSH_CASE(2, FP64, 0, 32)
+    PUSH_CASE(3, F32S, 8, 8)
+    PUSH_CASE(3, F32S, 0, 8)
+    PUSH_CASE(3, FP64, 8, 8)
+    PUSH_CASE(3, FP64, 0, 8)
     return hipErrorInvalidValue;
 }
 

@@ -8,8 +8,10 @@
 namespace sdmd {
 
 // particles phase (one workgroup per push item = (run, patch))
-hipError_t launch_push(int dims, bool split, int pc, const RunDev *runs, const int2 *items, int n_items, int par,
-                       hipStream_t s);
+// px: exact square/cubic patch edge of a compiled fast path (0 = sizes read
+// from the run descriptor); pc: LDS sizing class 8 / 16 / 32
+hipError_t launch_push(int dims, bool split, int px, int pc, const RunDev *runs, const int2 *items, int n_items,
+                       int par, hipStream_t s);
 
 // transfer (i) + Maxwell: items (run, region, tile, first-item-of-run flag)
 hipError_t launch_yee(int dims, bool split, const RunDev *runs, const int4 *items, int n_items, int par,

@@ -214,7 +214,15 @@ def test_lwfa_reduced_steps(prec):
     Fg, gp, diag = gpu_run(wl, 30)
     e30 = max_family_error(Fg, {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]})
     say(f"lwfa {prec}: 1-step {e1}; 30-step {e30}")
-    assert max(e1.values()) < (1e-12 if prec == "fp64" else 1e-5)
+    # Cold plasma barely reached by the laser: J is the difference of the
+    # shape factors at the old and new positions, X ~ 300 cells apart from the
+    # origin, displacements ~1e-2 cell.  FP64 rounding of X (ulp ~ 6e-14)
+    # then bounds the agreement of two correct FP64 computations of J to
+    # ~6e-14 / 1e-2 ~ 1e-11 relative; E and B stay at round-off.
+    if prec == "fp64":
+        assert max(e1["E"], e1["BH"], e1["Bm"]) < 1e-12 and e1["J"] < 1e-10
+    else:
+        assert max(e1.values()) < 1e-5
     assert max(e30.values()) < 1e-3
 
 
@@ -258,7 +266,7 @@ def test_converging_flow_spills_and_relayouts():
         Fo, P, g = oracle_run(wl, 24)
         say(f"{prec}: relayouts {diag['n_relayout']} spill {diag['n_spill']} patch max {diag['patch_max']}")
         assert diag["n_particles"] == N
-        assert diag["n_relayout"] >= 2          # the initial binning plus at least one overflow
+        assert diag["n_relayout"] >= 3          # the two binning passes plus at least one overflow
         assert np.array_equal(gp["id"], np.arange(N))
         tol = 1e-9 if prec == "fp64" else 1e-4
         assert wrapped_diff(gp["x"], P.x, 32.0).max() < tol

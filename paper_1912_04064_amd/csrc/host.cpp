@@ -264,7 +264,7 @@ static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::st
     b += align256((size_t)L.n_patch * 3 * L.tsz * rsz);
     b += 5 * align256((size_t)(L.n_patch + 1) * 4);
     b += 2 * (size_t)L.cap_total * per + align256((size_t)L.cap_total * 4);
-    b += (size_t)std::max<long long>(L.n_total, 1) * (per + 4);
+    b += 2 * (size_t)std::max<long long>(L.n_total, 1) * (per + 4);
     b += 64 * 256;   // per-array rounding and the control block
     L.bytes = b;
     return PIC_OK;
@@ -391,7 +391,8 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     d.tsz = L.tsz;
     d.cap_total = (int)L.cap_total;
     d.n_total = (int)L.n_total;
-    d.ins_blocks = std::max(1, std::min(1024, (int)(L.n_total / 8192)));
+    d.ins_blocks = std::max(1, std::min(64, (int)(L.n_total / 65536)));
+    d.ins_patches = 16;
     d.ghosts = L.ghosts;
     d.dt = cfg->dt;
     d.q = cfg->q;
@@ -418,9 +419,12 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     make_store(c, r, d.st, L.cap_total, L.split, L.dims, ids, ok);
     make_store(c, r, d.lv, L.cap_total, L.split, L.dims, ids, ok);
     make_store(c, r, d.sp, L.n_total, L.split, L.dims, ids, ok);
+    make_store(c, r, d.lo, L.n_total, L.split, L.dims, ids, ok);
     d.lpatch = (int *)run_alloc(c, r, (size_t)L.cap_total * 4);
     d.spatch = (int *)run_alloc(c, r, (size_t)std::max<long long>(L.n_total, 1) * 4);
-    ok = ok && d.lpatch && d.spatch;
+    d.lopatch = (int *)run_alloc(c, r, (size_t)std::max<long long>(L.n_total, 1) * 4);
+    d.nlv = (int *)run_alloc(c, r, (size_t)(L.n_patch + 1) * 4);
+    ok = ok && d.lpatch && d.spatch && d.lopatch && d.nlv;
     r.bytes = 0;
     for (auto &b : r.bufs) r.bytes += b.bytes;
     if (!ok) {
@@ -433,6 +437,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     HIPCHK(c, hipMemsetAsync(d.tiles, 0, (size_t)L.n_patch * 3 * L.tsz * rsz, s));
     HIPCHK(c, hipMemsetAsync(d.seg, 0, (size_t)(L.n_patch + 1) * 4, s));
     HIPCHK(c, hipMemsetAsync(d.cnt, 0, (size_t)(L.n_patch + 1) * 4, s));
+    HIPCHK(c, hipMemsetAsync(d.nlv, 0, (size_t)(L.n_patch + 1) * 4, s));
     HIPCHK(c, hipMemsetAsync(d.ctl, 0, sizeof(Ctl), s));
     if ((rc = upload_rd(c, slot))) return rc;
 
@@ -586,7 +591,8 @@ static int rebuild_items(pic_ctx *c)
             }
         // post items
         for (int g = 0; g < r.total_ghosts; g += BLOCK) fc->hp.push_back(make_int4(slot, 0, g, 0));
-        for (int b = 0; b < d.ins_blocks; ++b) fc->hp.push_back(make_int4(slot, 1, b, d.ins_blocks));
+        for (int p = 0; p < d.n_patch; p += d.ins_patches) fc->hp.push_back(make_int4(slot, 1, p, d.ins_patches));
+        for (int b = 0; b < d.ins_blocks; ++b) fc->hp.push_back(make_int4(slot, 2, b, d.ins_blocks));
         fc->slots.push_back(slot);
         const int nsb = std::max(1, std::min(1024, (int)(d.n_total / (BLOCK * 64))));
         fc->move_gx = std::max(fc->move_gx, d.n_patch + nsb);

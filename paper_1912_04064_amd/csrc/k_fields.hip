@@ -248,34 +248,51 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
         return;
     }
     // insert the leavers of this step into their destination patch
-    __shared__ int s_last;
-    const int nb = it.w;
-    const int nl = min(rd.ctl->nleave, rd.cap_total);
+    const int tid_ = threadIdx.x;
     int err = 0;
-    for (int i = it.z * BLOCK + tid; i < nl; i += nb * BLOCK) {
-        const int q = rd.lpatch[i];
+    auto insert = [&](const Store &src, const int *srcpatch, long long i) {
+        const int q = srcpatch[i];
         const int slot = atomicAdd(&rd.cnt[q], 1);
         const int cap = rd.seg[q + 1] - rd.seg[q];
         if (slot < cap) {
-            copy_part<DIM, T>(rd.lv, i, rd.st, (long long)rd.seg[q] + slot);
+            copy_part<DIM, T>(src, i, rd.st, (long long)rd.seg[q] + slot);
         } else {
             const int s = atomicAdd(&rd.ctl->nspill, 1);
             if (s < rd.n_total) {
-                copy_part<DIM, T>(rd.lv, i, rd.sp, s);
+                copy_part<DIM, T>(src, i, rd.sp, s);
                 rd.spatch[s] = q;
             } else {
                 err |= ERR_CAPACITY;
             }
         }
+    };
+    if (it.y == 1) {
+        // one wavefront per patch: the patch's leavers sit in its own
+        // region of the leaver store
+        const int wave = tid_ >> 6, lane = tid_ & 63;
+        const int p1 = min(it.z + it.w, rd.n_patch);
+        for (int p = it.z + wave; p < p1; p += BLOCK / 64) {
+            const int nl = rd.nlv[p];
+            const long long b = rd.seg[p];
+            for (int k = lane; k < nl; k += 64) insert(rd.lv, rd.lpatch, b + k);
+        }
+        if (err) atomicOr(&rd.ctl->err, err);
+        return;
     }
+    // overflow leavers (parked particles that re-entered): a few workgroups
+    // stride over them; the last one to finish clears the counter
+    __shared__ int s_last;
+    const int nb = it.w;
+    const int nl = min(rd.ctl->nleave, rd.n_total);
+    for (int i = it.z * BLOCK + tid_; i < nl; i += nb * BLOCK) insert(rd.lo, rd.lopatch, i);
     if (err) atomicOr(&rd.ctl->err, err);
     __syncthreads();
-    if (tid == 0) {
+    if (tid_ == 0) {
         __threadfence();
         s_last = atomicAdd(&rd.ctl->ins_done, 1) == nb - 1;
     }
     __syncthreads();
-    if (s_last && tid == 0) {
+    if (s_last && tid_ == 0) {
         const int ns = rd.ctl->nspill;
         if (ns > rd.ctl->max_spill) rd.ctl->max_spill = ns;
         rd.ctl->nleave = 0;

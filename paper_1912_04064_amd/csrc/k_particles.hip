@@ -145,22 +145,37 @@ __global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev 
     }
 }
 
-// multiplier of the in-segment permutation: the integer nearest 0.618 r
-// that is coprime with r (r >= 1)
-__device__ __forceinline__ long long scatter_stride(int r)
+// Cell of a stored particle inside its patch (x fastest), for the in-patch
+// ordering of a re-layout.
+template <int DIM, class T>
+__device__ __forceinline__ int local_cell(const RunDev &rd, const Store &s, long long i, int q)
 {
-    if (r <= 2) return 1;
-    long long k = (long long)(0.6180339887498949 * r);
-    for (;; ++k) {
-        long long a = k, b = r;
-        while (b) {
-            const long long t = a % b;
-            a = b;
-            b = t;
+    if constexpr (T::split) {
+        const int c = s.cell[i];
+        int lc = 0, mul = 1;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            int v = (c >> (5 * a)) & 31;
+            v = v < rd.P[a] ? v : rd.P[a] - 1;
+            lc += v * mul;
+            mul *= rd.P[a];
         }
-        if (a == 1) return k % r;
+        return lc;
+    } else {
+        const int pq[3] = {q % rd.np[0], (q / rd.np[0]) % rd.np[1], DIM == 3 ? q / (rd.np[0] * rd.np[1]) : 0};
+        int lc = 0, mul = 1;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            int v = (int)floor(((const double *)s.pos[a])[i] / rd.d[a]) - pq[a] * rd.P[a];
+            v = v < 0 ? 0 : (v > rd.P[a] - 1 ? rd.P[a] - 1 : v);
+            lc += v * mul;
+            mul *= rd.P[a];
+        }
+        return lc;
     }
 }
+
+constexpr int MAX_PATCH_CELLS = 1024;   // 32 x 32 (2D) / 8 x 8 x 8 (3D)
 
 template <int DIM, class T>
 __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__restrict__ runs,
@@ -171,19 +186,54 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
     const int np = rd.n_patch;
     const int n_spill_blocks = (int)gridDim.x - np;   // >= 1 by construction
     if ((int)blockIdx.x < np) {
-        // slot i of the new segment takes particle (i K) mod r of the old
-        // one, K ~ 0.618 r coprime with r: consecutive slots -- the lanes of
-        // one wavefront -- then hold particles from all over the patch
-        // instead of the same cell, so their LDS current-tile atomics hit
-        // different addresses.
+        // The patch's particles are sorted by cell (counting sort in LDS)
+        // and stored transposed: viewing the cell-sorted list as rows of M
+        // (~ particles per cell) entries, slot = column * rows + row.
+        // Consecutive slots -- the lanes of a wavefront -- then hold
+        // particles of consecutive cells, whose field-window reads and
+        // current-tile updates fall on different LDS banks.
+        __shared__ int s_off[MAX_PATCH_CELLS];
+        __shared__ int s_sum[BLOCK];
         const int p = blockIdx.x;
         const int cap = rd.seg[p + 1] - rd.seg[p];
         const int c = rd.cnt[p];
         const int r = c < cap ? c : cap;
-        const long long K = scatter_stride(r);
-        for (int i = threadIdx.x; i < r; i += BLOCK)
-            copy_part<DIM, T>(rd.st, (long long)rd.seg[p] + (int)(((long long)i * K) % r), rd.lv,
-                              (long long)rd.seg2[p] + i);
+        const long long src0 = rd.seg[p], dst0 = rd.seg2[p];
+        const int ncell = rd.P[0] * rd.P[1] * (DIM == 3 ? rd.P[2] : 1);
+        const int tid = threadIdx.x;
+        for (int k = tid; k < ncell; k += BLOCK) s_off[k] = 0;
+        __syncthreads();
+        for (int i = tid; i < r; i += BLOCK) atomicAdd(&s_off[local_cell<DIM, T>(rd, rd.st, src0 + i, p)], 1);
+        __syncthreads();
+        // exclusive scan of the cell counts: contiguous runs per thread
+        const int per = (ncell + BLOCK - 1) / BLOCK;
+        const int k0 = tid * per, k1 = min(ncell, k0 + per);
+        int run = 0;
+        for (int k = k0; k < k1; ++k) run += s_off[k];
+        s_sum[tid] = run;
+        __syncthreads();
+        for (int off = 1; off < BLOCK; off <<= 1) {
+            const int t = tid >= off ? s_sum[tid - off] : 0;
+            __syncthreads();
+            s_sum[tid] += t;
+            __syncthreads();
+        }
+        int acc = s_sum[tid] - run;
+        for (int k = k0; k < k1; ++k) {
+            const int v = s_off[k];
+            s_off[k] = acc;
+            acc += v;
+        }
+        __syncthreads();
+        const int M = max(1, (r + ncell / 2) / max(ncell, 1));
+        const int R = (r + M - 1) / M;
+        const int lastc = r - (R - 1) * M;
+        for (int i = tid; i < r; i += BLOCK) {
+            const int j = atomicAdd(&s_off[local_cell<DIM, T>(rd, rd.st, src0 + i, p)], 1);
+            const int row = j / M, col = j - row * M;
+            const int slot = col * R - max(0, col - lastc) + row;
+            copy_part<DIM, T>(rd.st, src0 + i, rd.lv, dst0 + slot);
+        }
         return;
     }
     const int nsp = min(rd.ctl->nspill, rd.n_total);

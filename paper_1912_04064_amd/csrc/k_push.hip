@@ -363,17 +363,21 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
 
 // PX: exact patch edge (0 = sizes from the run descriptor); PC: LDS sizing
 // class (the largest patch edge the instantiation accepts)
+// threads per particle-kernel workgroup
+constexpr int PUSH_BLOCK = 256;
+
 template <int DIM, class T, int PX, int PC>
-__global__ __launch_bounds__(BLOCK) void push_kernel(const RunDev *__restrict__ runs, const int2 *__restrict__ items,
-                                                     int par)
+__global__ __launch_bounds__(PUSH_BLOCK) void push_kernel(const RunDev *__restrict__ runs,
+                                                          const int2 *__restrict__ items, int par)
 {
     using R = typename T::real;
+    constexpr int BLOCK = PUSH_BLOCK;
     constexpr int WN = (PC + 3) * (PC + 3) * (DIM == 3 ? PC + 3 : 1);
     constexpr int TN = (PC + 5) * (PC + 5) * (DIM == 3 ? PC + 5 : 1);
     constexpr int NW = BLOCK / 64;
     __shared__ R s_win[6 * WN];
     __shared__ double s_tile[3 * TN];
-    __shared__ int s_wsum[2][NW];
+    __shared__ int s_wsum[2][NW], s_lsum[2][NW];
 
     const int2 item = items[blockIdx.x];
     const RunDev &rd = runs[item.x];
@@ -406,53 +410,54 @@ __global__ __launch_bounds__(BLOCK) void push_kernel(const RunDev *__restrict__ 
     int n = rd.cnt[q];
     n = n < cap ? n : cap;
     int err = 0;
-    int stay = 0;   // stayers compacted so far (uniform)
+    int stay = 0, left = 0;   // stayers compacted / leavers written so far (uniform)
     int chunk = 0;
     const unsigned long long lt = (1ull << lane) - 1ull;
 
+    // the next chunk's particles are loaded before this chunk is pushed: its
+    // slots lie above every slot this chunk's stores can reach
+    Part<T> nxt;
+    if (tid < n) load_part<DIM, T>(rd.st, seg0 + tid, nxt);
     for (int base = 0; base < n; base += BLOCK, ++chunk) {
         const int i = base + tid;
         const bool valid = i < n;
-        Part<T> pt;
+        Part<T> pt = nxt;
+        if (i + BLOCK < n) load_part<DIM, T>(rd.st, seg0 + i + BLOCK, nxt);
         int dest = q;
-        if (valid) {
-            load_part<DIM, T>(rd.st, seg0 + i, pt);
-            dest = push_one<DIM, T, PX>(rd, s_win, s_tile, p0, P, pt, err);
-        }
+        if (valid) dest = push_one<DIM, T, PX>(rd, s_win, s_tile, p0, P, pt, err);
         const bool st = valid && dest == q;
         const bool lv = valid && dest != q;
         const unsigned long long ms = __ballot(st), ml = __ballot(lv);
-        int lbase = 0;
-        if (ml) {
-            if (lane == 0) lbase = atomicAdd(&rd.ctl->nleave, __popcll(ml));
-            lbase = __shfl(lbase, 0);
+        if (lane == 0) {
+            s_wsum[chunk & 1][wave] = __popcll(ms);
+            s_lsum[chunk & 1][wave] = __popcll(ml);
         }
-        if (lane == 0) s_wsum[chunk & 1][wave] = __popcll(ms);
         __syncthreads();   // every particle of the chunk is loaded before any store
-        int wb = stay, tot = 0;
+        int wb = stay, lb = left, tot = 0, ltot = 0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-            const int c = s_wsum[chunk & 1][w];
+            const int c = s_wsum[chunk & 1][w], l = s_lsum[chunk & 1][w];
             wb += w < wave ? c : 0;
+            lb += w < wave ? l : 0;
             tot += c;
+            ltot += l;
         }
         if (st) {
             const int slot = wb + __popcll(ms & lt);
             store_part<DIM, T>(rd.st, seg0 + slot, pt, slot != i);
         }
         if (lv) {
-            const int slot = lbase + __popcll(ml & lt);
-            if (slot < rd.cap_total) {
-                store_part<DIM, T>(rd.lv, slot, pt, true);
-                rd.lpatch[slot] = dest;
-            } else {
-                err |= ERR_CAPACITY;
-            }
+            // the patch's own leaver region: stayers + leavers <= n <= capacity
+            const long long slot = seg0 + lb + __popcll(ml & lt);
+            store_part<DIM, T>(rd.lv, slot, pt, true);
+            rd.lpatch[slot] = dest;
         }
         stay += tot;
+        left += ltot;
     }
 
-    // particles parked in the spill store that belong to this patch
+    // particles parked in the spill store that belong to this patch re-enter
+    // through the overflow leaver store
     const int nsp = min(rd.ctl->nspill, rd.n_total);
     for (int base = 0; base < nsp; base += BLOCK) {
         const int i = base + tid;
@@ -471,9 +476,9 @@ __global__ __launch_bounds__(BLOCK) void push_kernel(const RunDev *__restrict__ 
         }
         if (mine) {
             const int slot = lbase + __popcll(ml & lt);
-            if (slot < rd.cap_total) {
-                store_part<DIM, T>(rd.lv, slot, pt, true);
-                rd.lpatch[slot] = dest;
+            if (slot < rd.n_total) {
+                store_part<DIM, T>(rd.lo, slot, pt, true);
+                rd.lopatch[slot] = dest;
             } else {
                 err |= ERR_CAPACITY;
             }
@@ -481,7 +486,10 @@ __global__ __launch_bounds__(BLOCK) void push_kernel(const RunDev *__restrict__ 
     }
 
     if (err) atomicOr(&rd.ctl->err, err);
-    if (tid == 0) rd.cnt[q] = stay;
+    if (tid == 0) {
+        rd.cnt[q] = stay;
+        rd.nlv[q] = left;
+    }
     __syncthreads();
     // flush the tile in the tile precision (transfer (i) reads it)
     R *dst = (R *)rd.tiles + (long long)q * 3 * TS;
@@ -490,7 +498,7 @@ __global__ __launch_bounds__(BLOCK) void push_kernel(const RunDev *__restrict__ 
 
 #define PUSH_CASE(D, TT, PXV, PCV)                                                                  \
     if (dims == D && split == TT::split && px == PXV && pc == PCV) {                                \
-        push_kernel<D, TT, PXV, PCV><<<n_items, BLOCK, 0, s>>>(runs, items, par);                   \
+        push_kernel<D, TT, PXV, PCV><<<n_items, PUSH_BLOCK, 0, s>>>(runs, items, par);                   \
         return hipGetLastError();                                                                   \
     }
 

@@ -15,11 +15,12 @@
 //              per axis, origin = patch origin - 2 (FP32 in the split form,
 //              FP64 in the plain form).
 //   particles: SoA, patch-segmented.  Patch p owns slots [seg[p], seg[p+1])
-//              of which the first cnt[p] are live.  A second store of the
-//              same capacity receives the particles leaving their patch
-//              each step and serves as the scratch of a re-layout; a third
-//              one ("spill") parks particles that found their patch segment
-//              full until the next re-layout.
+//              of which the first cnt[p] are live.  A second store with
+//              the same segments receives each patch's leavers (at most
+//              cnt[p], so they always fit) and serves as the scratch of a
+//              re-layout; a third one ("spill") parks particles that found
+//              their patch segment full until the next re-layout, and a
+//              fourth takes those parked particles when they re-enter.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -67,9 +68,9 @@ struct Store {
 
 // per-run device counters
 struct Ctl {
-    int nleave;       // particles written to the leaver store this step
+    int nleave;       // particles appended to the overflow leaver store this step
     int nspill;       // particles parked in the spill store
-    int ins_done;     // insert workgroups finished (last one resets nleave)
+    int ins_done;     // overflow-insert workgroups finished (last one resets nleave)
     int err;          // ERR_* bits, sticky
     int relayout;     // set by the re-layout planner when a re-layout runs
     int n_relayout;   // re-layouts done
@@ -92,7 +93,8 @@ struct RunDev {
     int tsz;             // nodes per tile component
     int cap_total;       // slots of the patch store
     int n_total;         // particles of the run
-    int ins_blocks;      // insert workgroups per step
+    int ins_blocks;      // workgroups inserting the overflow leavers
+    int ins_patches;     // patches per leaver-insert workgroup
     int ghosts;          // ghost nodes per region
     double d[3], L[3];
     double dt, q, m;
@@ -107,6 +109,9 @@ struct RunDev {
     int *seg2, *tot, *fill;   // re-layout scratch
     Store st, lv, sp;    // patch store, leaver / scratch store, spill store
     int *lpatch, *spatch;
+    int *nlv;            // [n_patch] leavers of each patch this step, in lv at seg[p]
+    Store lo;            // overflow leavers (parked particles re-entering)
+    int *lopatch;
     Ctl *ctl;
 };
 

@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--phase-samples", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 512 MiB device copy first (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
@@ -104,6 +106,13 @@ def main():
     from paper_1912_04064_amd import binding as B
     if not torch.cuda.is_available():
         raise SystemExit("no GPU")
+    if args.calib_copy:
+        x = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     wl = workload(args.workload)
     N = wl.n_particles
     ncell = wl.n_cells

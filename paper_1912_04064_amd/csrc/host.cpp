@@ -156,6 +156,7 @@ struct Layout {
     bool split;
     int n[3], P[3], np[3], nreg[3], rs[3], ra[3], TA[3];
     int n_patch, n_regions, tsz, ghosts;
+    int seg_cap, seg_max;
     long long rsize;
     long long n_total, cap_total;
     size_t bytes;
@@ -171,6 +172,9 @@ static int patch_class(int dims, const int P[3])
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// live particles per segment a re-layout aims at: 8 chunks of 256
+constexpr int SEG_CAP = 2048;
 
 // exact patch edge with a compiled fast path of the particle kernel, or 0
 static int fast_patch(const Layout &L)
@@ -253,7 +257,11 @@ static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::st
         L.ghosts = G2 * L.ra[0] * L.ra[1] + L.rs[2] * G2 * L.ra[0] + L.rs[2] * L.rs[1] * G2;
     L.n_total = cfg->particles ? cfg->particles->n : 0;
     if (L.n_total < 0) return fail("negative particle count");
-    L.cap_total = L.n_total + L.n_total / 4 + 16LL * L.n_patch + 1024;
+    // segments: a re-layout splits a patch into ceil(count / seg_cap)
+    // segments, so at most n_patch + N / seg_cap of them exist
+    L.seg_cap = SEG_CAP;
+    L.seg_max = (int)(L.n_patch + (L.n_total + L.seg_cap - 1) / L.seg_cap + 16);
+    L.cap_total = L.n_total + L.n_total / 4 + 16LL * L.seg_max + 1024;
     if (L.cap_total > (1LL << 31) - 1) return fail("too many particles for one run");
     // bytes
     const size_t rsz = L.split ? 4 : 8;
@@ -261,8 +269,8 @@ static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::st
     const size_t per = dims * rsz + (L.split ? 2 : 0) + 3 * rsz + rsz + (ids ? 4 : 0);
     size_t b = 0;
     b += align256((size_t)L.n_regions * F_NCOMP * L.rsize * 8);
-    b += align256((size_t)L.n_patch * 3 * L.tsz * rsz);
-    b += 5 * align256((size_t)(L.n_patch + 1) * 4);
+    b += align256((size_t)L.seg_max * 3 * L.tsz * rsz);
+    b += 5 * align256((size_t)(L.n_patch + 1) * 4) + 6 * align256((size_t)(L.seg_max + 1) * 4);
     b += 2 * (size_t)L.cap_total * per + align256((size_t)L.cap_total * 4);
     b += 2 * (size_t)std::max<long long>(L.n_total, 1) * (per + 4);
     b += 64 * 256;   // per-array rounding and the control block
@@ -340,6 +348,27 @@ static int check_run_err(pic_ctx *c, int slot, int *flags_out = nullptr)
     return PIC_OK;
 }
 
+// host copy of a run's segment table (diagnostics and export only)
+struct SegView {
+    int nseg = 0;
+    std::vector<int> sseg, scnt, spat;
+};
+
+static int read_segments(pic_ctx *c, int slot, const Ctl &ctl, SegView &v)
+{
+    const RunDev &d = c->runs[slot].rd;
+    v.nseg = std::max(0, std::min(ctl.nseg, d.seg_max));
+    v.sseg.assign(v.nseg + 1, 0);
+    v.scnt.assign(std::max(v.nseg, 1), 0);
+    v.spat.assign(std::max(v.nseg, 1), 0);
+    HIPCHK(c, hipMemcpy(v.sseg.data(), d.sseg, (v.nseg + 1) * 4, hipMemcpyDeviceToHost));
+    if (v.nseg > 0) {
+        HIPCHK(c, hipMemcpy(v.scnt.data(), d.scnt, v.nseg * 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(v.spat.data(), d.spat, v.nseg * 4, hipMemcpyDeviceToHost));
+    }
+    return PIC_OK;
+}
+
 static int relayout_one(pic_ctx *c, int slot, int force)
 {
     Run &r = c->runs[slot];
@@ -390,9 +419,11 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     d.rsize = L.rsize;
     d.tsz = L.tsz;
     d.cap_total = (int)L.cap_total;
+    d.seg_max = L.seg_max;
+    d.seg_cap = L.seg_cap;
     d.n_total = (int)L.n_total;
     d.ins_blocks = std::max(1, std::min(64, (int)(L.n_total / 65536)));
-    d.ins_patches = 16;
+    d.ins_segs = 16;
     d.ghosts = L.ghosts;
     d.dt = cfg->dt;
     d.q = cfg->q;
@@ -408,14 +439,22 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     const bool ids = cfg->track_ids != 0;
     bool ok = true;
     d.fld = (double *)run_alloc(c, r, (size_t)L.n_regions * F_NCOMP * L.rsize * 8);
-    d.tiles = run_alloc(c, r, (size_t)L.n_patch * 3 * L.tsz * rsz);
-    d.seg = (int *)run_alloc(c, r, (size_t)(L.n_patch + 1) * 4);
-    d.cnt = (int *)run_alloc(c, r, (size_t)(L.n_patch + 1) * 4);
-    d.seg2 = (int *)run_alloc(c, r, (size_t)(L.n_patch + 1) * 4);
-    d.tot = (int *)run_alloc(c, r, (size_t)(L.n_patch + 1) * 4);
-    d.fill = (int *)run_alloc(c, r, (size_t)(L.n_patch + 1) * 4);
+    d.tiles = run_alloc(c, r, (size_t)L.seg_max * 3 * L.tsz * rsz);
+    const size_t pb = (size_t)(L.n_patch + 1) * 4, sb = (size_t)(L.seg_max + 1) * 4;
+    d.pseg = (int *)run_alloc(c, r, pb);
+    d.pseg2 = (int *)run_alloc(c, r, pb);
+    d.tot = (int *)run_alloc(c, r, pb);
+    d.preg = (int *)run_alloc(c, r, pb);
+    d.fill = (int *)run_alloc(c, r, pb);
+    d.sseg = (int *)run_alloc(c, r, sb);
+    d.scnt = (int *)run_alloc(c, r, sb);
+    d.spat = (int *)run_alloc(c, r, sb);
+    d.sseg2 = (int *)run_alloc(c, r, sb);
+    d.scnt2 = (int *)run_alloc(c, r, sb);
+    d.spat2 = (int *)run_alloc(c, r, sb);
     d.ctl = (Ctl *)run_alloc(c, r, sizeof(Ctl));
-    ok = d.fld && d.tiles && d.seg && d.cnt && d.seg2 && d.tot && d.fill && d.ctl;
+    ok = d.fld && d.tiles && d.pseg && d.pseg2 && d.tot && d.preg && d.fill && d.sseg && d.scnt && d.spat &&
+         d.sseg2 && d.scnt2 && d.spat2 && d.ctl;
     make_store(c, r, d.st, L.cap_total, L.split, L.dims, ids, ok);
     make_store(c, r, d.lv, L.cap_total, L.split, L.dims, ids, ok);
     make_store(c, r, d.sp, L.n_total, L.split, L.dims, ids, ok);
@@ -423,7 +462,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     d.lpatch = (int *)run_alloc(c, r, (size_t)L.cap_total * 4);
     d.spatch = (int *)run_alloc(c, r, (size_t)std::max<long long>(L.n_total, 1) * 4);
     d.lopatch = (int *)run_alloc(c, r, (size_t)std::max<long long>(L.n_total, 1) * 4);
-    d.nlv = (int *)run_alloc(c, r, (size_t)(L.n_patch + 1) * 4);
+    d.nlv = (int *)run_alloc(c, r, sb);
     ok = ok && d.lpatch && d.spatch && d.lopatch && d.nlv;
     r.bytes = 0;
     for (auto &b : r.bufs) r.bytes += b.bytes;
@@ -434,10 +473,11 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     r.active = true;
     hipStream_t s = c->stream;
     HIPCHK(c, hipMemsetAsync(d.fld, 0, (size_t)L.n_regions * F_NCOMP * L.rsize * 8, s));
-    HIPCHK(c, hipMemsetAsync(d.tiles, 0, (size_t)L.n_patch * 3 * L.tsz * rsz, s));
-    HIPCHK(c, hipMemsetAsync(d.seg, 0, (size_t)(L.n_patch + 1) * 4, s));
-    HIPCHK(c, hipMemsetAsync(d.cnt, 0, (size_t)(L.n_patch + 1) * 4, s));
-    HIPCHK(c, hipMemsetAsync(d.nlv, 0, (size_t)(L.n_patch + 1) * 4, s));
+    HIPCHK(c, hipMemsetAsync(d.tiles, 0, (size_t)L.seg_max * 3 * L.tsz * rsz, s));
+    HIPCHK(c, hipMemsetAsync(d.pseg, 0, pb, s));
+    HIPCHK(c, hipMemsetAsync(d.sseg, 0, sb, s));
+    HIPCHK(c, hipMemsetAsync(d.scnt, 0, sb, s));
+    HIPCHK(c, hipMemsetAsync(d.nlv, 0, sb, s));
     HIPCHK(c, hipMemsetAsync(d.ctl, 0, sizeof(Ctl), s));
     if ((rc = upload_rd(c, slot))) return rc;
 
@@ -558,10 +598,10 @@ static int rebuild_items(pic_ctx *c)
             fc = &c->fcls.back();
         }
         const RunDev &d = r.rd;
-        // push items: XCD-aware order -- workgroup i runs on XCD i % 8, so
-        // give each XCD a contiguous band of patches (shared window halos
-        // then hit the same L2)
-        const int np = d.n_patch;
+        // push items, one per segment slot: XCD-aware order -- workgroup i
+        // runs on XCD i % 8, so give each XCD a contiguous band of segments
+        // (neighbouring patches share window halos in that XCD's L2)
+        const int np = d.seg_max;
         const int band = (np + 7) / 8;
         std::vector<char> seen(np, 0);
         size_t base = pc->h.size();
@@ -591,7 +631,7 @@ static int rebuild_items(pic_ctx *c)
             }
         // post items
         for (int g = 0; g < r.total_ghosts; g += BLOCK) fc->hp.push_back(make_int4(slot, 0, g, 0));
-        for (int p = 0; p < d.n_patch; p += d.ins_patches) fc->hp.push_back(make_int4(slot, 1, p, d.ins_patches));
+        for (int sg = 0; sg < d.seg_max; sg += d.ins_segs) fc->hp.push_back(make_int4(slot, 1, sg, d.ins_segs));
         for (int b = 0; b < d.ins_blocks; ++b) fc->hp.push_back(make_int4(slot, 2, b, d.ins_blocks));
         fc->slots.push_back(slot);
         const int nsb = std::max(1, std::min(1024, (int)(d.n_total / (BLOCK * 64))));
@@ -904,7 +944,7 @@ int pic_fields(pic_ctx *c, int32_t run, uint32_t mask, double *dst, size_t dst_l
         } else {
             Ctl ctl = read_ctl(c, run, e);
             if (e == hipSuccess)
-                e = launch_rho(r.dims, r.split, c->d_runs, run, r.rd.n_patch, ctl.nspill, r.ncell, tmp, c->stream);
+                e = launch_rho(r.dims, r.split, c->d_runs, run, r.rd.seg_max, ctl.nspill, r.ncell, tmp, c->stream);
         }
         if (e == hipSuccess)
             e = hipMemcpyAsync(dst + o, tmp, nc * 8, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
@@ -929,16 +969,18 @@ int pic_diag(pic_ctx *c, int32_t run, pic_diag_t *out)
     hipError_t ce;
     Ctl ctl = read_ctl(c, run, ce);
     HIPCHK(c, ce);
-    std::vector<int> seg(d.n_patch + 1), cnt(d.n_patch);
-    HIPCHK(c, hipMemcpy(seg.data(), d.seg, seg.size() * 4, hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(cnt.data(), d.cnt, cnt.size() * 4, hipMemcpyDeviceToHost));
+    SegView sv;
+    int rc0 = read_segments(c, run, ctl, sv);
+    if (rc0) return rc0;
     std::vector<long long> per(d.n_patch, 0);
     std::vector<int> sp(ctl.nspill);
     if (ctl.nspill > 0) HIPCHK(c, hipMemcpy(sp.data(), d.spatch, sp.size() * 4, hipMemcpyDeviceToHost));
     long long n = 0;
-    for (int q = 0; q < d.n_patch; ++q) {
-        per[q] = std::min(cnt[q], seg[q + 1] - seg[q]);
-        n += per[q];
+    for (int k = 0; k < sv.nseg; ++k) {
+        const int q = sv.spat[k];
+        const long long l = std::min(sv.scnt[k], sv.sseg[k + 1] - sv.sseg[k]);
+        if (q >= 0 && q < d.n_patch) per[q] += l;
+        n += l;
     }
     for (int q : sp)
         if (q >= 0 && q < d.n_patch) per[q]++;
@@ -953,10 +995,11 @@ int pic_diag(pic_ctx *c, int32_t run, pic_diag_t *out)
     }
     const double dV = d.d[0] * d.d[1] * (d.dims == 3 ? d.d[2] : 1.0);
     const int nb = std::max(1, std::min(1024, (r.ncell + BLOCK - 1) / BLOCK));
-    double *part = (double *)dev_alloc(c, (size_t)std::max(2 * nb, d.n_patch + 1) * 8);
+    const int nk = d.seg_max + 1;
+    double *part = (double *)dev_alloc(c, (size_t)std::max(2 * nb, nk) * 8);
     if (!part) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
-    DevBuf pb{part, align256((size_t)std::max(2 * nb, d.n_patch + 1) * 8)};
-    std::vector<double> h(std::max(2 * nb, d.n_patch + 1));
+    DevBuf pb{part, align256((size_t)std::max(2 * nb, nk) * 8)};
+    std::vector<double> h(std::max(2 * nb, nk));
     HIPCHK(c, launch_field_energy(c->d_runs, run, r.ncell, c->par, part, nb, c->stream));
     HIPCHK(c, hipMemcpyAsync(h.data(), part, 2 * nb * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -965,11 +1008,11 @@ int pic_diag(pic_ctx *c, int32_t run, pic_diag_t *out)
         ue += h[2 * i];
         ub += h[2 * i + 1];
     }
-    HIPCHK(c, launch_kinetic(r.dims, r.split, c->d_runs, run, d.n_patch, ctl.nspill, part, c->stream));
-    HIPCHK(c, hipMemcpyAsync(h.data(), part, (d.n_patch + 1) * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, launch_kinetic(r.dims, r.split, c->d_runs, run, d.seg_max, ctl.nspill, part, c->stream));
+    HIPCHK(c, hipMemcpyAsync(h.data(), part, (size_t)nk * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double k = 0;
-    for (int i = 0; i <= d.n_patch; ++i) k += h[i];
+    for (int i = 0; i < nk; ++i) k += h[i];
     dev_free(c, pb);
     out->U_E = 0.5 * ue * dV;
     out->U_B = 0.5 * ub * dV;
@@ -992,15 +1035,16 @@ int pic_particles(pic_ctx *c, int32_t run, pic_particles_out *out)
     hipError_t ce;
     Ctl ctl = read_ctl(c, run, ce);
     HIPCHK(c, ce);
-    std::vector<int> seg(d.n_patch + 1), cnt(d.n_patch), off(d.n_patch + 1);
-    HIPCHK(c, hipMemcpy(seg.data(), d.seg, seg.size() * 4, hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(cnt.data(), d.cnt, cnt.size() * 4, hipMemcpyDeviceToHost));
+    SegView sv;
+    int rc0 = read_segments(c, run, ctl, sv);
+    if (rc0) return rc0;
+    std::vector<int> off(sv.nseg + 1);
     long long n = 0;
-    for (int q = 0; q < d.n_patch; ++q) {
-        off[q] = (int)n;
-        n += std::min(cnt[q], seg[q + 1] - seg[q]);
+    for (int k = 0; k < sv.nseg; ++k) {
+        off[k] = (int)n;
+        n += std::min(sv.scnt[k], sv.sseg[k + 1] - sv.sseg[k]);
     }
-    off[d.n_patch] = (int)n;
+    off[sv.nseg] = (int)n;
     n += ctl.nspill;
     out->n = n;
     if (out->capacity < n) return set_err(c, PIC_E_INVAL, "capacity %lld < %lld particles", (long long)out->capacity, n);
@@ -1029,7 +1073,7 @@ int pic_particles(pic_ctx *c, int32_t run, pic_particles_out *out)
     hipError_t e = hipSuccess;
     if (!rc) e = hipMemcpyAsync(doff, off.data(), off.size() * 4, hipMemcpyHostToDevice, c->stream);
     if (!rc && e == hipSuccess)
-        e = launch_export(r.dims, r.split, c->d_runs, run, d.n_patch, ctl.nspill, doff, dx[0], dx[1], dx[2], dx[3], dx[4],
+        e = launch_export(r.dims, r.split, c->d_runs, run, d.seg_max, ctl.nspill, doff, dx[0], dx[1], dx[2], dx[3], dx[4],
                           dx[5], dx[6], did, dpat, c->stream);
     for (int i = 0; i < 7 && !rc && e == hipSuccess; ++i)
         if (dx[i]) e = hipMemcpyAsync(hx[i], dx[i], nn * 8, hipMemcpyDeviceToHost, c->stream);

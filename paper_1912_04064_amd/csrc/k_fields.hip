@@ -19,8 +19,9 @@
 namespace sdmd {
 
 // --------------------------------------------------------------- J gather
-// Current at global node g of component c: sum over the patch tiles whose
-// node range [p0-2, p0+P+2] covers g (periodic), in a fixed order.
+// Current at global node g of component c: sum over the segment tiles of the
+// patches whose node range [p0-2, p0+P+2] covers g (periodic), in a fixed
+// order.
 template <int DIM, class R>
 __device__ __forceinline__ double gather_J(const RunDev &rd, const R *__restrict__ tiles, int c, const int g[3])
 {
@@ -39,11 +40,13 @@ __device__ __forceinline__ double gather_J(const RunDev &rd, const R *__restrict
                 const int qx = wrapi(pa[0] + ox, rd.np[0]);
                 const int qy = wrapi(pa[1] + oy, rd.np[1]);
                 const int qz = DIM == 3 ? wrapi(pa[2] + oz, rd.np[2]) : 0;
-                const long long q = qx + (long long)rd.np[0] * (qy + (long long)rd.np[1] * qz);
+                const int q = qx + rd.np[0] * (qy + rd.np[1] * qz);
                 const int tx = l[0] - ox * rd.P[0] + 2;
                 const int ty = l[1] - oy * rd.P[1] + 2;
                 const int tz = DIM == 3 ? l[2] - oz * rd.P[2] + 2 : 0;
-                s += (double)tiles[(q * 3 + c) * rd.tsz + (tz * rd.TA[1] + ty) * rd.TA[0] + tx];
+                const int off = (tz * rd.TA[1] + ty) * rd.TA[0] + tx;
+                for (int sg = rd.pseg[q]; sg < rd.pseg[q + 1]; ++sg)
+                    s += (double)tiles[((long long)sg * 3 + c) * rd.tsz + off];
             }
     return s;
 }
@@ -251,11 +254,14 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
     const int tid_ = threadIdx.x;
     int err = 0;
     auto insert = [&](const Store &src, const int *srcpatch, long long i) {
+        // the destination patch's segments take leavers in turn
         const int q = srcpatch[i];
-        const int slot = atomicAdd(&rd.cnt[q], 1);
-        const int cap = rd.seg[q + 1] - rd.seg[q];
+        const int k0 = rd.pseg[q], nk = rd.pseg[q + 1] - k0;
+        const int t = k0 + (nk > 1 ? (int)(i % nk) : 0);
+        const int slot = atomicAdd(&rd.scnt[t], 1);
+        const int cap = rd.sseg[t + 1] - rd.sseg[t];
         if (slot < cap) {
-            copy_part<DIM, T>(src, i, rd.st, (long long)rd.seg[q] + slot);
+            copy_part<DIM, T>(src, i, rd.st, (long long)rd.sseg[t] + slot);
         } else {
             const int s = atomicAdd(&rd.ctl->nspill, 1);
             if (s < rd.n_total) {
@@ -267,13 +273,13 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
         }
     };
     if (it.y == 1) {
-        // one wavefront per patch: the patch's leavers sit in its own
+        // one wavefront per segment: the segment's leavers sit in its own
         // region of the leaver store
         const int wave = tid_ >> 6, lane = tid_ & 63;
-        const int p1 = min(it.z + it.w, rd.n_patch);
-        for (int p = it.z + wave; p < p1; p += BLOCK / 64) {
-            const int nl = rd.nlv[p];
-            const long long b = rd.seg[p];
+        const int s1 = min(it.z + it.w, rd.ctl->nseg);
+        for (int sg = it.z + wave; sg < s1; sg += BLOCK / 64) {
+            const int nl = rd.nlv[sg];
+            const long long b = rd.sseg[sg];
             for (int k = lane; k < nl; k += 64) insert(rd.lv, rd.lpatch, b + k);
         }
         if (err) atomicOr(&rd.ctl->err, err);

@@ -92,6 +92,16 @@ __device__ long long block_exclusive_scan(long long v, long long *buf, long long
     return ex;
 }
 
+constexpr int MAX_OLD_SEGS = 1024;      // segments per patch (LDS prefix of the move kernel)
+
+// segments of a patch holding t particles
+__device__ __forceinline__ int segs_for(int t, int cs) { return min(MAX_OLD_SEGS, max(1, (t + cs - 1) / cs)); }
+
+// Plan a re-layout of one run (one workgroup): per-patch totals (live
+// particles of its segments + parked ones), the number of segments of each
+// patch K_p = ceil(total / seg_cap), an even split of the total over them,
+// and each segment's capacity (live + 25 % + 16, or an even share of the
+// free slots if that does not fit).
 __global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev *__restrict__ runs,
                                                                    const int *__restrict__ slots, int force)
 {
@@ -104,44 +114,72 @@ __global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev 
         return;
     }
     const int np = rd.n_patch;
+    const int nseg = rd.ctl->nseg;
     for (int p = tid; p < np; p += PLAN_BLOCK) {
-        const int cap = rd.seg[p + 1] - rd.seg[p];
-        const int c = rd.cnt[p];
-        rd.tot[p] = c < cap ? c : cap;
+        rd.tot[p] = 0;
         rd.fill[p] = 0;
     }
     __syncthreads();
+    for (int sg = tid; sg < nseg; sg += PLAN_BLOCK) {
+        const int cap = rd.sseg[sg + 1] - rd.sseg[sg];
+        atomicAdd(&rd.tot[rd.spat[sg]], min(rd.scnt[sg], cap));
+    }
+    __syncthreads();
+    for (int p = tid; p < np; p += PLAN_BLOCK) rd.preg[p] = rd.tot[p];
+    __syncthreads();
     for (int i = tid; i < nsp; i += PLAN_BLOCK) atomicAdd(&rd.tot[rd.spatch[i]], 1);
     __syncthreads();
-    // contiguous chunk of patches per thread
+    const int cs = rd.seg_cap > 0 ? rd.seg_cap : 1;
     const int chunk = (np + PLAN_BLOCK - 1) / PLAN_BLOCK;
     const int p0 = tid * chunk, p1 = min(np, p0 + chunk);
+    // segments per patch -> first segment of each patch
+    long long nk = 0;
+    for (int p = p0; p < p1; ++p) nk += segs_for(rd.tot[p], cs);
+    long long nseg2;
+    long long koff = block_exclusive_scan(nk, buf, nseg2);
+    for (int p = p0; p < p1; ++p) {
+        rd.pseg2[p] = (int)koff;
+        koff += segs_for(rd.tot[p], cs);
+    }
+    if (tid == 0) rd.pseg2[np] = (int)nseg2;
+    // capacities
     long long want = 0;
     for (int p = p0; p < p1; ++p) {
-        const int t = rd.tot[p];
-        want += t + t / 4 + 16;
+        const int t = rd.tot[p], K = segs_for(t, cs);
+        for (int k = 0; k < K; ++k) {
+            const int l = t / K + (k < t % K ? 1 : 0);
+            want += l + l / 4 + 16;
+        }
     }
     long long total;
     block_exclusive_scan(want, buf, total);
-    // fall back to an even share of the free slots if the generous layout
-    // does not fit
     const bool tight = total > rd.cap_total;
-    const int slack = tight ? (rd.cap_total - rd.n_total) / (np > 0 ? np : 1) : 0;
+    const int slack = tight ? (int)((rd.cap_total - rd.n_total) / (nseg2 > 0 ? nseg2 : 1)) : 0;
     long long mine = 0;
     for (int p = p0; p < p1; ++p) {
-        const int t = rd.tot[p];
-        mine += tight ? t + slack : t + t / 4 + 16;
+        const int t = rd.tot[p], K = segs_for(t, cs);
+        for (int k = 0; k < K; ++k) {
+            const int l = t / K + (k < t % K ? 1 : 0);
+            mine += tight ? l + slack : l + l / 4 + 16;
+        }
     }
     long long tot2;
     long long off = block_exclusive_scan(mine, buf, tot2);
     for (int p = p0; p < p1; ++p) {
-        rd.seg2[p] = (int)off;
-        const int t = rd.tot[p];
-        off += tight ? t + slack : t + t / 4 + 16;
+        const int t = rd.tot[p], K = segs_for(t, cs);
+        const int k0 = rd.pseg2[p];
+        for (int k = 0; k < K && k0 + k < rd.seg_max; ++k) {
+            const int l = t / K + (k < t % K ? 1 : 0);
+            rd.sseg2[k0 + k] = (int)off;
+            rd.scnt2[k0 + k] = l;
+            rd.spat2[k0 + k] = p;
+            off += tight ? l + slack : l + l / 4 + 16;
+        }
     }
     if (tid == 0) {
-        rd.seg2[np] = (int)tot2;
-        rd.ctl->relayout = 1;
+        if (nseg2 <= rd.seg_max) rd.sseg2[nseg2] = (int)tot2;
+        rd.ctl->relayout = (nseg2 <= rd.seg_max && tot2 <= rd.cap_total) ? 1 : 0;
+        if (!rd.ctl->relayout) atomicOr(&rd.ctl->err, ERR_CAPACITY);
     }
 }
 
@@ -175,6 +213,24 @@ __device__ __forceinline__ int local_cell(const RunDev &rd, const Store &s, long
     }
 }
 
+// position j of a patch's new particle list -> slot in its new segments
+// (segment k of K holds the k-th even share of the patch's t particles)
+__device__ __forceinline__ long long new_slot(const RunDev &rd, int p, int t, int j)
+{
+    const int k0 = rd.pseg2[p], K = rd.pseg2[p + 1] - k0;
+    const int base = t / K, extra = t % K;
+    int k, o;
+    if (j < extra * (base + 1)) {
+        k = j / (base + 1);
+        o = j - k * (base + 1);
+    } else {
+        const int jj = j - extra * (base + 1);
+        k = extra + (base > 0 ? jj / base : 0);
+        o = jj - (k - extra) * base;
+    }
+    return (long long)rd.sseg2[k0 + k] + o;
+}
+
 constexpr int MAX_PATCH_CELLS = 1024;   // 32 x 32 (2D) / 8 x 8 x 8 (3D)
 
 template <int DIM, class T>
@@ -186,64 +242,83 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
     const int np = rd.n_patch;
     const int n_spill_blocks = (int)gridDim.x - np;   // >= 1 by construction
     if ((int)blockIdx.x < np) {
-        // The patch's particles are sorted by cell (counting sort in LDS)
-        // and stored transposed: viewing the cell-sorted list as rows of M
-        // (~ particles per cell) entries, slot = column * rows + row.
-        // Consecutive slots -- the lanes of a wavefront -- then hold
-        // particles of consecutive cells, whose field-window reads and
-        // current-tile updates fall on different LDS banks.
+        // The patch's particles (from all its old segments) are sorted by
+        // cell (counting sort in LDS) and stored transposed: viewing the
+        // cell-sorted list as rows of M (~ particles per cell) entries,
+        // position = column * rows + row.  Consecutive positions -- the
+        // lanes of a wavefront -- then hold particles of consecutive cells,
+        // whose field-window reads and current-tile updates fall on
+        // different LDS banks.  Positions are then split evenly over the
+        // patch's new segments.
         __shared__ int s_off[MAX_PATCH_CELLS];
         __shared__ int s_sum[BLOCK];
+        __shared__ int s_seg[MAX_OLD_SEGS + 1];
         const int p = blockIdx.x;
-        const int cap = rd.seg[p + 1] - rd.seg[p];
-        const int c = rd.cnt[p];
-        const int r = c < cap ? c : cap;
-        const long long src0 = rd.seg[p], dst0 = rd.seg2[p];
-        const int ncell = rd.P[0] * rd.P[1] * (DIM == 3 ? rd.P[2] : 1);
         const int tid = threadIdx.x;
+        const int k0 = rd.pseg[p], K = min(rd.pseg[p + 1] - k0, MAX_OLD_SEGS);
+        // prefix of the old segments' live counts
+        if (tid == 0) {
+            int acc = 0;
+            for (int k = 0; k < K; ++k) {
+                s_seg[k] = acc;
+                const int cap = rd.sseg[k0 + k + 1] - rd.sseg[k0 + k];
+                acc += min(rd.scnt[k0 + k], cap);
+            }
+            s_seg[K] = acc;
+        }
+        const int ncell = rd.P[0] * rd.P[1] * (DIM == 3 ? rd.P[2] : 1);
         for (int k = tid; k < ncell; k += BLOCK) s_off[k] = 0;
         __syncthreads();
-        for (int i = tid; i < r; i += BLOCK) atomicAdd(&s_off[local_cell<DIM, T>(rd, rd.st, src0 + i, p)], 1);
+        const int r = s_seg[K];
+        const int t = rd.tot[p];
+        auto src = [&](int i) -> long long {   // i-th live particle of the patch
+            int lo = 0, hi = K;                // s_seg[lo] <= i < s_seg[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_seg[mid] <= i) lo = mid; else hi = mid;
+            }
+            return (long long)rd.sseg[k0 + lo] + (i - s_seg[lo]);
+        };
+        for (int i = tid; i < r; i += BLOCK) atomicAdd(&s_off[local_cell<DIM, T>(rd, rd.st, src(i), p)], 1);
         __syncthreads();
         // exclusive scan of the cell counts: contiguous runs per thread
         const int per = (ncell + BLOCK - 1) / BLOCK;
-        const int k0 = tid * per, k1 = min(ncell, k0 + per);
+        const int c0 = tid * per, c1 = min(ncell, c0 + per);
         int run = 0;
-        for (int k = k0; k < k1; ++k) run += s_off[k];
+        for (int k = c0; k < c1; ++k) run += s_off[k];
         s_sum[tid] = run;
         __syncthreads();
         for (int off = 1; off < BLOCK; off <<= 1) {
-            const int t = tid >= off ? s_sum[tid - off] : 0;
+            const int v = tid >= off ? s_sum[tid - off] : 0;
             __syncthreads();
-            s_sum[tid] += t;
+            s_sum[tid] += v;
             __syncthreads();
         }
         int acc = s_sum[tid] - run;
-        for (int k = k0; k < k1; ++k) {
+        for (int k = c0; k < c1; ++k) {
             const int v = s_off[k];
             s_off[k] = acc;
             acc += v;
         }
         __syncthreads();
         const int M = max(1, (r + ncell / 2) / max(ncell, 1));
-        const int R = (r + M - 1) / M;
-        const int lastc = r - (R - 1) * M;
+        const int Rw = (r + M - 1) / M;
+        const int lastc = r - (Rw - 1) * M;
         for (int i = tid; i < r; i += BLOCK) {
-            const int j = atomicAdd(&s_off[local_cell<DIM, T>(rd, rd.st, src0 + i, p)], 1);
+            const long long si = src(i);
+            const int j = atomicAdd(&s_off[local_cell<DIM, T>(rd, rd.st, si, p)], 1);
             const int row = j / M, col = j - row * M;
-            const int slot = col * R - max(0, col - lastc) + row;
-            copy_part<DIM, T>(rd.st, src0 + i, rd.lv, dst0 + slot);
+            const int pos = col * Rw - max(0, col - lastc) + row;
+            copy_part<DIM, T>(rd.st, si, rd.lv, new_slot(rd, p, t, pos));
         }
         return;
     }
+    // parked particles follow the patch-store ones in their patch's list
     const int nsp = min(rd.ctl->nspill, rd.n_total);
     for (int i = (blockIdx.x - np) * BLOCK + threadIdx.x; i < nsp; i += n_spill_blocks * BLOCK) {
         const int q = rd.spatch[i];
-        const int cap = rd.seg[q + 1] - rd.seg[q];
-        const int c = rd.cnt[q];
-        const int r = c < cap ? c : cap;
-        const int slot = rd.seg2[q] + r + atomicAdd(&rd.fill[q], 1);
-        copy_part<DIM, T>(rd.sp, i, rd.lv, slot);
+        const int pos = rd.preg[q] + atomicAdd(&rd.fill[q], 1);
+        copy_part<DIM, T>(rd.sp, i, rd.lv, new_slot(rd, q, rd.tot[q], pos));
     }
 }
 
@@ -254,15 +329,22 @@ __global__ __launch_bounds__(BLOCK) void relayout_commit_kernel(const RunDev *__
     const RunDev &rd = runs[slots[blockIdx.y]];
     if (!rd.ctl->relayout) return;
     const int np = rd.n_patch;
-    const int total = rd.seg2[np];
+    const int S = rd.pseg2[np];
+    const int total = rd.sseg2[S];
     const int stride = gridDim.x * BLOCK;
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < total; i += stride) copy_part<DIM, T>(rd.lv, i, rd.st, i);
-    for (int p = blockIdx.x * BLOCK + threadIdx.x; p <= np; p += stride) {
-        rd.seg[p] = rd.seg2[p];
-        if (p < np) rd.cnt[p] = rd.tot[p];
+    for (int k = blockIdx.x * BLOCK + threadIdx.x; k <= S; k += stride) {
+        rd.sseg[k] = rd.sseg2[k];
+        if (k < S) {
+            rd.scnt[k] = rd.scnt2[k];
+            rd.spat[k] = rd.spat2[k];
+            rd.nlv[k] = 0;
+        }
     }
+    for (int p = blockIdx.x * BLOCK + threadIdx.x; p <= np; p += stride) rd.pseg[p] = rd.pseg2[p];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         rd.ctl->nspill = 0;
+        rd.ctl->nseg = S;
         rd.ctl->n_relayout += 1;
     }
 }
@@ -302,21 +384,24 @@ __global__ __launch_bounds__(BLOCK) void export_kernel(const RunDev *__restrict_
                                                        double *ux, double *uy, double *uz, double *w, uint32_t *id,
                                                        int *patch)
 {
+    // blocks [0, seg_max): one segment each; the rest: the spill store.
+    // off[s] = output offset of segment s, off[nseg] = start of the spill part
     const RunDev &rd = runs[run];
-    const int np = rd.n_patch;
-    if ((int)blockIdx.x < np) {
-        const int q = blockIdx.x;
-        const int cap = rd.seg[q + 1] - rd.seg[q];
-        const int c = rd.cnt[q];
-        const int r = c < cap ? c : cap;
+    const int S = rd.ctl->nseg;
+    if ((int)blockIdx.x < rd.seg_max) {
+        const int sg = blockIdx.x;
+        if (sg >= S) return;
+        const int cap = rd.sseg[sg + 1] - rd.sseg[sg];
+        const int r = min(rd.scnt[sg], cap);
+        const int q = rd.spat[sg];
         for (int i = threadIdx.x; i < r; i += BLOCK)
-            export_one<DIM, T>(rd, rd.st, (long long)rd.seg[q] + i, q, (long long)off[q] + i, x, y, z, ux, uy, uz, w, id,
-                               patch);
+            export_one<DIM, T>(rd, rd.st, (long long)rd.sseg[sg] + i, q, (long long)off[sg] + i, x, y, z, ux, uy, uz,
+                               w, id, patch);
         return;
     }
-    const int nb = gridDim.x - np;
-    for (int i = (blockIdx.x - np) * BLOCK + threadIdx.x; i < nspill; i += nb * BLOCK)
-        export_one<DIM, T>(rd, rd.sp, i, rd.spatch[i], (long long)off[np] + i, x, y, z, ux, uy, uz, w, id, patch);
+    const int nb = gridDim.x - rd.seg_max;
+    for (int i = (blockIdx.x - rd.seg_max) * BLOCK + threadIdx.x; i < nspill; i += nb * BLOCK)
+        export_one<DIM, T>(rd, rd.sp, i, rd.spatch[i], (long long)off[S] + i, x, y, z, ux, uy, uz, w, id, patch);
 }
 
 // ---------------------------------------------------------------- kinetic energy
@@ -327,19 +412,19 @@ __global__ __launch_bounds__(BLOCK) void kinetic_kernel(const RunDev *__restrict
     using R = typename T::real;
     const RunDev &rd = runs[run];
     __shared__ double sk[BLOCK];
-    const int np = rd.n_patch;
     double k = 0.0;
     auto add = [&](const Store &s, long long i) {
         const double a = ((const R *)s.u[0])[i], b = ((const R *)s.u[1])[i], c = ((const R *)s.u[2])[i];
         const double g = sqrt(1.0 + a * a + b * b + c * c);
         k += rd.m * (double)((const R *)s.w)[i] * (g - 1.0);
     };
-    if ((int)blockIdx.x < np) {
-        const int q = blockIdx.x;
-        const int cap = rd.seg[q + 1] - rd.seg[q];
-        const int c = rd.cnt[q];
-        const int r = c < cap ? c : cap;
-        for (int i = threadIdx.x; i < r; i += BLOCK) add(rd.st, (long long)rd.seg[q] + i);
+    if ((int)blockIdx.x < rd.seg_max) {
+        const int sg = blockIdx.x;
+        if (sg < rd.ctl->nseg) {
+            const int cap = rd.sseg[sg + 1] - rd.sseg[sg];
+            const int r = min(rd.scnt[sg], cap);
+            for (int i = threadIdx.x; i < r; i += BLOCK) add(rd.st, (long long)rd.sseg[sg] + i);
+        }
     } else {
         for (int i = threadIdx.x; i < nspill; i += BLOCK) add(rd.sp, i);
     }
@@ -389,13 +474,13 @@ __global__ __launch_bounds__(BLOCK) void rho_kernel(const RunDev *__restrict__ r
                                                     double *__restrict__ rho)
 {
     const RunDev &rd = runs[run];
-    const int np = rd.n_patch;
-    if ((int)blockIdx.x < np) {
-        const int q = blockIdx.x;
-        const int cap = rd.seg[q + 1] - rd.seg[q];
-        const int c = rd.cnt[q];
-        const int r = c < cap ? c : cap;
-        for (int i = threadIdx.x; i < r; i += BLOCK) rho_one<DIM, T>(rd, rd.st, (long long)rd.seg[q] + i, q, rho);
+    if ((int)blockIdx.x < rd.seg_max) {
+        const int sg = blockIdx.x;
+        if (sg >= rd.ctl->nseg) return;
+        const int cap = rd.sseg[sg + 1] - rd.sseg[sg];
+        const int r = min(rd.scnt[sg], cap);
+        const int q = rd.spat[sg];
+        for (int i = threadIdx.x; i < r; i += BLOCK) rho_one<DIM, T>(rd, rd.st, (long long)rd.sseg[sg] + i, q, rho);
         return;
     }
     for (int i = threadIdx.x; i < nspill; i += BLOCK) rho_one<DIM, T>(rd, rd.sp, i, rd.spatch[i], rho);
@@ -450,30 +535,30 @@ hipError_t launch_relayout(int dims, bool split, const RunDev *runs, const int *
     DISPATCH_ALL(RELAYOUT_BODY)
 }
 
-hipError_t launch_export(int dims, bool split, const RunDev *runs, int run, int n_patch, int nspill, const int *off,
+hipError_t launch_export(int dims, bool split, const RunDev *runs, int run, int seg_max, int nspill, const int *off,
                          double *x, double *y, double *z, double *ux, double *uy, double *uz, double *w, uint32_t *id,
                          int *patch, hipStream_t s)
 {
-    const int nb = n_patch + spill_blocks(nspill > 0 ? nspill * 64 : 1);
+    const int nb = seg_max + spill_blocks(nspill > 0 ? nspill * 64 : 1);
 #define EXPORT_BODY(D, TT) \
     export_kernel<D, TT><<<nb, BLOCK, 0, s>>>(runs, run, nspill, off, x, y, z, ux, uy, uz, w, id, patch)
     DISPATCH_ALL(EXPORT_BODY)
 }
 
-hipError_t launch_kinetic(int dims, bool split, const RunDev *runs, int run, int n_patch, int nspill, double *partial,
+hipError_t launch_kinetic(int dims, bool split, const RunDev *runs, int run, int seg_max, int nspill, double *partial,
                           hipStream_t s)
 {
-#define KIN_BODY(D, TT) kinetic_kernel<D, TT><<<n_patch + 1, BLOCK, 0, s>>>(runs, run, nspill, partial)
+#define KIN_BODY(D, TT) kinetic_kernel<D, TT><<<seg_max + 1, BLOCK, 0, s>>>(runs, run, nspill, partial)
     DISPATCH_ALL(KIN_BODY)
 }
 
-hipError_t launch_rho(int dims, bool split, const RunDev *runs, int run, int n_patch, int nspill, int ncell,
+hipError_t launch_rho(int dims, bool split, const RunDev *runs, int run, int seg_max, int nspill, int ncell,
                       double *rho, hipStream_t s)
 {
     fill_kernel<<<(ncell + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(rho, ncell, 0.0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-#define RHO_BODY(D, TT) rho_kernel<D, TT><<<n_patch + 1, BLOCK, 0, s>>>(runs, run, nspill, rho)
+#define RHO_BODY(D, TT) rho_kernel<D, TT><<<seg_max + 1, BLOCK, 0, s>>>(runs, run, nspill, rho)
     DISPATCH_ALL(RHO_BODY)
 }
 

@@ -1,7 +1,8 @@
 // k_push.hip -- the "Particles" phase of one SDMD step (section 3.3 of the
-// paper: interpolation, push, deposition), one workgroup per patch.
+// paper: interpolation, push, deposition), one workgroup per segment of a
+// patch.
 //
-// Per patch workgroup:
+// Per workgroup:
 //   1. transfer (ii) of section 2.2: the patch's window of E^n and Bm^n
 //      (nodes [p0-1, p0+P+1] per axis) is read from its region into LDS,
 //      converted to the particle precision;
@@ -12,8 +13,11 @@
 //      3D: the 4-node sub-frame that holds both the old and new shapes);
 //   3. particles that stay are compacted in place in the patch segment;
 //      particles that leave go to the leaver store with their new patch;
-//   4. the LDS tile is written to the patch's tile slot in HBM, where the
+//   4. the LDS tile is written to the segment's tile slot in HBM, where the
 //      field kernel sums it into the region (transfer (i)).
+// The work item is a segment: a patch denser than the segment cap is split
+// into several segments (the paper's task decomposition of one patch) that
+// load the same window and deposit into their own tiles.
 // Particles parked in the spill store that belong to this patch are pushed
 // here too and all re-enter through the leaver store.
 #include "launch.h"
@@ -381,7 +385,9 @@ __global__ __launch_bounds__(PUSH_BLOCK) void push_kernel(const RunDev *__restri
 
     const int2 item = items[blockIdx.x];
     const RunDev &rd = runs[item.x];
-    const int q = item.y;
+    const int sg = item.y;               // segment
+    if (sg >= rd.ctl->nseg) return;      // segment slot not in use this layout
+    const int q = rd.spat[sg];           // its patch
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     const int P[3] = {PX ? PX : rd.P[0], PX ? PX : rd.P[1], DIM == 3 ? (PX ? PX : rd.P[2]) : 1};
@@ -405,9 +411,9 @@ __global__ __launch_bounds__(PUSH_BLOCK) void push_kernel(const RunDev *__restri
     for (int idx = tid; idx < 3 * TS; idx += BLOCK) s_tile[idx] = 0.0;
     __syncthreads();
 
-    const long long seg0 = rd.seg[q];
-    const int cap = rd.seg[q + 1] - rd.seg[q];
-    int n = rd.cnt[q];
+    const long long seg0 = rd.sseg[sg];
+    const int cap = rd.sseg[sg + 1] - rd.sseg[sg];
+    int n = rd.scnt[sg];
     n = n < cap ? n : cap;
     int err = 0;
     int stay = 0, left = 0;   // stayers compacted / leavers written so far (uniform)
@@ -457,8 +463,8 @@ __global__ __launch_bounds__(PUSH_BLOCK) void push_kernel(const RunDev *__restri
     }
 
     // particles parked in the spill store that belong to this patch re-enter
-    // through the overflow leaver store
-    const int nsp = min(rd.ctl->nspill, rd.n_total);
+    // through the overflow leaver store (pushed by the patch's first segment)
+    const int nsp = sg == rd.pseg[q] ? min(rd.ctl->nspill, rd.n_total) : 0;
     for (int base = 0; base < nsp; base += BLOCK) {
         const int i = base + tid;
         const bool mine = i < nsp && rd.spatch[i] == q;
@@ -487,12 +493,12 @@ __global__ __launch_bounds__(PUSH_BLOCK) void push_kernel(const RunDev *__restri
 
     if (err) atomicOr(&rd.ctl->err, err);
     if (tid == 0) {
-        rd.cnt[q] = stay;
-        rd.nlv[q] = left;
+        rd.scnt[sg] = stay;
+        rd.nlv[sg] = left;
     }
     __syncthreads();
     // flush the tile in the tile precision (transfer (i) reads it)
-    R *dst = (R *)rd.tiles + (long long)q * 3 * TS;
+    R *dst = (R *)rd.tiles + (long long)sg * 3 * TS;
     for (int idx = tid; idx < 3 * TS; idx += BLOCK) dst[idx] = (R)s_tile[idx];
 }
 

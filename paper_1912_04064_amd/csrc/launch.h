@@ -42,18 +42,18 @@ hipError_t launch_convert(int dims, bool split, const RunDev *runs, int run, int
 // (plan / move / commit); force = 1 re-lays out even without parked particles
 hipError_t launch_relayout(int dims, bool split, const RunDev *runs, const int *slots, int n_slots, int move_gx,
                            int commit_gx, int force, hipStream_t s);
-// export: live particles -> FP64 arrays at per-patch offsets (off[n_patch]
+// export: live particles -> FP64 arrays at per-segment offsets (off[nseg]
 // = start of the spill part)
-hipError_t launch_export(int dims, bool split, const RunDev *runs, int run, int n_patch, int nspill, const int *off,
+hipError_t launch_export(int dims, bool split, const RunDev *runs, int run, int seg_max, int nspill, const int *off,
                          double *x, double *y, double *z, double *ux, double *uy, double *uz, double *w, uint32_t *id,
                          int *patch, hipStream_t s);
 // diagnostics: partial sums (field energy per block; kinetic per patch)
 hipError_t launch_field_energy(const RunDev *runs, int run, int ncell, int par, double *partial, int nblocks,
                                hipStream_t s);
-hipError_t launch_kinetic(int dims, bool split, const RunDev *runs, int run, int n_patch, int nspill, double *partial,
+hipError_t launch_kinetic(int dims, bool split, const RunDev *runs, int run, int seg_max, int nspill, double *partial,
                           hipStream_t s);
 // charge density (electrons) at primal nodes, global FP64 array (zeroed here)
-hipError_t launch_rho(int dims, bool split, const RunDev *runs, int run, int n_patch, int nspill, int ncell,
+hipError_t launch_rho(int dims, bool split, const RunDev *runs, int run, int seg_max, int nspill, int ncell,
                       double *rho, hipStream_t s);
 
 }  // namespace sdmd

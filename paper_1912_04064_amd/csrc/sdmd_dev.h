@@ -10,17 +10,22 @@
 //              the fused Ampere/Faraday kernel can recompute a one-node halo
 //              of E^{n+1} without reading values another workgroup already
 //              overwrote.
-//   tiles    : per patch, 3 current components on the nodes the patch's
-//              particles can reach, [patch][component][z][y][x], extent P+5
-//              per axis, origin = patch origin - 2 (FP32 in the split form,
-//              FP64 in the plain form).
-//   particles: SoA, patch-segmented.  Patch p owns slots [seg[p], seg[p+1])
-//              of which the first cnt[p] are live.  A second store with
-//              the same segments receives each patch's leavers (at most
-//              cnt[p], so they always fit) and serves as the scratch of a
-//              re-layout; a third one ("spill") parks particles that found
-//              their patch segment full until the next re-layout, and a
-//              fourth takes those parked particles when they re-enter.
+//   particles: SoA in segments.  A patch owns 1..K consecutive segments
+//              (segments [pseg[p], pseg[p+1])); a re-layout gives a patch
+//              as many segments as it needs to keep each at most seg_cap
+//              live particles, so a dense patch is worked on by several
+//              workgroups at once.  Segment s owns slots [sseg[s],
+//              sseg[s+1]) of which the first scnt[s] are live.  A second
+//              store with the same segments receives each segment's leavers
+//              (at most scnt[s], so they always fit) and serves as the
+//              scratch of a re-layout; a third one ("spill") parks
+//              particles that found their destination segment full until
+//              the next re-layout, and a fourth takes those parked
+//              particles when they re-enter.
+//   tiles    : per segment, 3 current components on the nodes its patch's
+//              particles can reach, [segment][component][z][y][x], extent
+//              P+5 per axis, origin = patch origin - 2 (FP32 in the split
+//              form, FP64 in the plain form).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -75,7 +80,7 @@ struct Ctl {
     int relayout;     // set by the re-layout planner when a re-layout runs
     int n_relayout;   // re-layouts done
     int max_spill;    // largest nspill seen
-    int pad;
+    int nseg;         // segments in use
 };
 
 struct RunDev {
@@ -92,9 +97,11 @@ struct RunDev {
     int TA[3];           // tile extent per axis (P + 5; 1 in 2D z)
     int tsz;             // nodes per tile component
     int cap_total;       // slots of the patch store
+    int seg_max;         // segment slots allocated
+    int seg_cap;         // live particles per segment a re-layout aims at
     int n_total;         // particles of the run
     int ins_blocks;      // workgroups inserting the overflow leavers
-    int ins_patches;     // patches per leaver-insert workgroup
+    int ins_segs;        // segments per leaver-insert workgroup
     int ghosts;          // ghost nodes per region
     double d[3], L[3];
     double dt, q, m;
@@ -105,11 +112,14 @@ struct RunDev {
     float f_q;
     double *fld;         // regions
     void *tiles;
-    int *seg, *cnt;      // [n_patch + 1], [n_patch]
-    int *seg2, *tot, *fill;   // re-layout scratch
+    int *pseg;           // [n_patch + 1] first segment of each patch
+    int *sseg, *scnt;    // [seg_max + 1] first slot, [seg_max] live count of each segment
+    int *spat;           // [seg_max] patch of each segment
+    int *pseg2, *sseg2, *scnt2, *spat2;   // re-layout: the new segment layout
+    int *tot, *preg, *fill;               // re-layout: per-patch totals, patch-store part, spill fill
     Store st, lv, sp;    // patch store, leaver / scratch store, spill store
     int *lpatch, *spatch;
-    int *nlv;            // [n_patch] leavers of each patch this step, in lv at seg[p]
+    int *nlv;            // [seg_max] leavers of each segment this step, in lv at sseg[s]
     Store lo;            // overflow leavers (parked particles re-entering)
     int *lopatch;
     Ctl *ctl;

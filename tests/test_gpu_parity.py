@@ -288,3 +288,25 @@ def test_empty_run_and_ragged_grid():
     Fg, gp, _ = gpu_run(wl, 3)
     Fo, P, _ = oracle_run(wl, 3)
     assert max(max_family_error(Fg, Fo).values()) < 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32s"])
+def test_dense_patches_split_into_segments(prec):
+    """64 particles per cell: 4096 per 8x8 patch, above the per-segment cap,
+    so every patch is worked on as several segments with their own tiles."""
+    say(f"case: dense segments {prec}")
+    wl = WL.thermal_2d(n=(32, 32), ppc=64, vth=0.05, patch=(8, 8), nreg=(2, 1), precision=prec, density=1.0)
+    g, F, P = oracle_state(wl)
+    O.step_sdsd(g, F, P)
+    Fg1, gp1, d1 = gpu_run(wl, 1)
+    e1 = max_family_error(Fg1, {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]})
+    L = wl.n[0] * wl.d[0]
+    assert wrapped_diff(gp1["x"], P.x, L).max() < (1e-13 if prec == "fp64" else 1e-6)
+    for _ in range(19):
+        O.step_sdsd(g, F, P)
+    Fg, gp, diag = gpu_run(wl, 20)
+    e20 = max_family_error(Fg, {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]})
+    say(f"dense {prec}: 1-step {e1}; 20-step {e20}; patch max {diag['patch_max']}")
+    assert max(e1.values()) < (1e-12 if prec == "fp64" else 1e-5)
+    assert max(e20.values()) < 1e-3
+    assert diag["n_particles"] == wl.n_particles and diag["patch_min"] > 2048

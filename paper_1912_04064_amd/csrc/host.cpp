@@ -261,7 +261,7 @@ static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::st
     // segments, so at most n_patch + N / seg_cap of them exist
     L.seg_cap = SEG_CAP;
     L.seg_max = (int)(L.n_patch + (L.n_total + L.seg_cap - 1) / L.seg_cap + 16);
-    L.cap_total = L.n_total + L.n_total / 4 + 16LL * L.seg_max + 1024;
+    L.cap_total = L.n_total + L.n_total / 2 + 32LL * L.seg_max + 1024;
     if (L.cap_total > (1LL << 31) - 1) return fail("too many particles for one run");
     // bytes
     const size_t rsz = L.split ? 4 : 8;
@@ -374,7 +374,7 @@ static int relayout_one(pic_ctx *c, int slot, int force)
     Run &r = c->runs[slot];
     HIPCHK(c, hipMemcpyAsync(c->d_slot1, &slot, sizeof(int), hipMemcpyHostToDevice, c->stream));
     const int nsb = std::max(1, std::min(1024, (int)(r.rd.n_total / (BLOCK * 64))));
-    int cb = (int)std::min<long long>(4096, std::max<long long>(1, (r.rd.cap_total + BLOCK - 1) / BLOCK));
+    int cb = (int)std::min<long long>(64, std::max<long long>(1, (r.rd.seg_max + BLOCK) / BLOCK));
     HIPCHK(c, launch_relayout(r.dims, r.split, c->d_runs, c->d_slot1, 1, r.rd.n_patch + nsb, cb, force, c->stream));
     return PIC_OK;
 }
@@ -636,8 +636,7 @@ static int rebuild_items(pic_ctx *c)
         fc->slots.push_back(slot);
         const int nsb = std::max(1, std::min(1024, (int)(d.n_total / (BLOCK * 64))));
         fc->move_gx = std::max(fc->move_gx, d.n_patch + nsb);
-        fc->commit_gx = std::max(fc->commit_gx,
-                                 (int)std::min<long long>(4096, std::max<long long>(1, (d.cap_total + BLOCK - 1) / BLOCK)));
+        fc->commit_gx = std::max(fc->commit_gx, std::min(64, std::max(1, (d.seg_max + BLOCK) / BLOCK)));
     }
     int rc;
     for (auto &pc : c->pcls)

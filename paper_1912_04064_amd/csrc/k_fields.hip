@@ -260,13 +260,23 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
         const int t = k0 + (nk > 1 ? (int)(i % nk) : 0);
         const int slot = atomicAdd(&rd.scnt[t], 1);
         const int cap = rd.sseg[t + 1] - rd.sseg[t];
-        if (slot < cap) {
-            copy_part<DIM, T>(src, i, rd.st, (long long)rd.sseg[t] + slot);
-        } else {
-            const int s = atomicAdd(&rd.ctl->nspill, 1);
+        return slot < cap ? (long long)rd.sseg[t] + slot : -1ll - q;
+    };
+    // parking (full destination segment) claims its slots once per wavefront
+    auto place = [&](const Store &src, long long i, bool valid, long long dst) {
+        const bool park = valid && dst < 0;
+        const unsigned long long mp = __ballot(park);
+        int pbase = 0;
+        if (mp) {
+            if ((threadIdx.x & 63) == 0) pbase = atomicAdd(&rd.ctl->nspill, __popcll(mp));
+            pbase = __shfl(pbase, 0);
+        }
+        if (valid && dst >= 0) copy_part<DIM, T>(src, i, rd.st, dst);
+        if (park) {
+            const int s = pbase + __popcll(mp & ((1ull << (threadIdx.x & 63)) - 1ull));
             if (s < rd.n_total) {
                 copy_part<DIM, T>(src, i, rd.sp, s);
-                rd.spatch[s] = q;
+                rd.spatch[s] = (int)(-1ll - dst);
             } else {
                 err |= ERR_CAPACITY;
             }
@@ -280,7 +290,11 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
         for (int sg = it.z + wave; sg < s1; sg += BLOCK / 64) {
             const int nl = rd.nlv[sg];
             const long long b = rd.sseg[sg];
-            for (int k = lane; k < nl; k += 64) insert(rd.lv, rd.lpatch, b + k);
+            for (int k0 = 0; k0 < nl; k0 += 64) {
+                const int k = k0 + lane;
+                const bool v = k < nl;
+                place(rd.lv, b + k, v, v ? insert(rd.lv, rd.lpatch, b + k) : 0);
+            }
         }
         if (err) atomicOr(&rd.ctl->err, err);
         return;
@@ -290,7 +304,11 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
     __shared__ int s_last;
     const int nb = it.w;
     const int nl = min(rd.ctl->nleave, rd.n_total);
-    for (int i = it.z * BLOCK + tid_; i < nl; i += nb * BLOCK) insert(rd.lo, rd.lopatch, i);
+    for (int i0 = it.z * BLOCK; i0 < nl; i0 += nb * BLOCK) {
+        const int i = i0 + tid_;
+        const bool v = i < nl;
+        place(rd.lo, i, v, v ? insert(rd.lo, rd.lopatch, i) : 0);
+    }
     if (err) atomicOr(&rd.ctl->err, err);
     __syncthreads();
     if (tid_ == 0) {

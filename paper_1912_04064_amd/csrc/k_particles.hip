@@ -4,10 +4,10 @@
 // Binning (the patch decomposition of section 2.2): a particle belongs to
 // the patch holding its cell; cell = floor(x/d) clamped to [0, n-1] in the
 // FP64 form, the integer cell in the split form.  The store keeps the
-// particles of patch p in slots [seg[p], seg[p]+cnt[p]).  A re-layout gives
-// every patch a new capacity (live count + 25 % + 16) and moves the live and
-// parked particles into it; it runs at init (binning of the initial state)
-// and whenever particles had to be parked because their patch was full.
+// particles of a patch in its segments.  A re-layout gives every patch new
+// segments (live count + 50 % + 32 capacity each) and moves the live and
+// parked particles into them; it runs at init (binning of the initial
+// state) and whenever particles had to be parked because a segment was full.
 #include "launch.h"
 #include "part.h"
 #include "sdmd_dev.h"
@@ -93,6 +93,7 @@ __device__ long long block_exclusive_scan(long long v, long long *buf, long long
 }
 
 constexpr int MAX_OLD_SEGS = 1024;      // segments per patch (LDS prefix of the move kernel)
+constexpr int PLAN_LDS_PATCHES = 16384; // patch counts the planner histograms in LDS
 
 // segments of a patch holding t particles
 __device__ __forceinline__ int segs_for(int t, int cs) { return min(MAX_OLD_SEGS, max(1, (t + cs - 1) / cs)); }
@@ -100,13 +101,14 @@ __device__ __forceinline__ int segs_for(int t, int cs) { return min(MAX_OLD_SEGS
 // Plan a re-layout of one run (one workgroup): per-patch totals (live
 // particles of its segments + parked ones), the number of segments of each
 // patch K_p = ceil(total / seg_cap), an even split of the total over them,
-// and each segment's capacity (live + 25 % + 16, or an even share of the
+// and each segment's capacity (live + 50 % + 32, or an even share of the
 // free slots if that does not fit).
 __global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev *__restrict__ runs,
                                                                    const int *__restrict__ slots, int force)
 {
     const RunDev &rd = runs[slots[blockIdx.x]];
     __shared__ long long buf[PLAN_BLOCK];
+    __shared__ int s_hist[PLAN_LDS_PATCHES];
     const int tid = threadIdx.x;
     const int nsp = min(rd.ctl->nspill, rd.n_total);
     if (!force && nsp == 0) {
@@ -127,7 +129,16 @@ __global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev 
     __syncthreads();
     for (int p = tid; p < np; p += PLAN_BLOCK) rd.preg[p] = rd.tot[p];
     __syncthreads();
-    for (int i = tid; i < nsp; i += PLAN_BLOCK) atomicAdd(&rd.tot[rd.spatch[i]], 1);
+    // parked particles per patch: LDS histogram when the patch count fits
+    if (np <= PLAN_LDS_PATCHES) {
+        for (int p = tid; p < np; p += PLAN_BLOCK) s_hist[p] = 0;
+        __syncthreads();
+        for (int i = tid; i < nsp; i += PLAN_BLOCK) atomicAdd(&s_hist[rd.spatch[i]], 1);
+        __syncthreads();
+        for (int p = tid; p < np; p += PLAN_BLOCK) rd.tot[p] += s_hist[p];
+    } else {
+        for (int i = tid; i < nsp; i += PLAN_BLOCK) atomicAdd(&rd.tot[rd.spatch[i]], 1);
+    }
     __syncthreads();
     const int cs = rd.seg_cap > 0 ? rd.seg_cap : 1;
     const int chunk = (np + PLAN_BLOCK - 1) / PLAN_BLOCK;
@@ -148,7 +159,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev 
         const int t = rd.tot[p], K = segs_for(t, cs);
         for (int k = 0; k < K; ++k) {
             const int l = t / K + (k < t % K ? 1 : 0);
-            want += l + l / 4 + 16;
+            want += l + l / 2 + 32;
         }
     }
     long long total;
@@ -160,7 +171,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev 
         const int t = rd.tot[p], K = segs_for(t, cs);
         for (int k = 0; k < K; ++k) {
             const int l = t / K + (k < t % K ? 1 : 0);
-            mine += tight ? l + slack : l + l / 4 + 16;
+            mine += tight ? l + slack : l + l / 2 + 32;
         }
     }
     long long tot2;
@@ -173,7 +184,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev 
             rd.sseg2[k0 + k] = (int)off;
             rd.scnt2[k0 + k] = l;
             rd.spat2[k0 + k] = p;
-            off += tight ? l + slack : l + l / 4 + 16;
+            off += tight ? l + slack : l + l / 2 + 32;
         }
     }
     if (tid == 0) {
@@ -322,17 +333,17 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
     }
 }
 
+// The moved particles are in the scratch store: the scratch store becomes
+// the patch store (a swap of the two store descriptors in the run table, no
+// copy) and the new segment table is installed.
 template <int DIM, class T>
-__global__ __launch_bounds__(BLOCK) void relayout_commit_kernel(const RunDev *__restrict__ runs,
-                                                               const int *__restrict__ slots)
+__global__ __launch_bounds__(BLOCK) void relayout_commit_kernel(RunDev *__restrict__ runs, const int *__restrict__ slots)
 {
-    const RunDev &rd = runs[slots[blockIdx.y]];
+    RunDev &rd = runs[slots[blockIdx.y]];
     if (!rd.ctl->relayout) return;
     const int np = rd.n_patch;
     const int S = rd.pseg2[np];
-    const int total = rd.sseg2[S];
     const int stride = gridDim.x * BLOCK;
-    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < total; i += stride) copy_part<DIM, T>(rd.lv, i, rd.st, i);
     for (int k = blockIdx.x * BLOCK + threadIdx.x; k <= S; k += stride) {
         rd.sseg[k] = rd.sseg2[k];
         if (k < S) {
@@ -343,6 +354,9 @@ __global__ __launch_bounds__(BLOCK) void relayout_commit_kernel(const RunDev *__
     }
     for (int p = blockIdx.x * BLOCK + threadIdx.x; p <= np; p += stride) rd.pseg[p] = rd.pseg2[p];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const Store t = rd.st;
+        rd.st = rd.lv;
+        rd.lv = t;
         rd.ctl->nspill = 0;
         rd.ctl->nseg = S;
         rd.ctl->n_relayout += 1;
@@ -520,7 +534,7 @@ static int spill_blocks(int n_total)
     return b < 1 ? 1 : (b > 1024 ? 1024 : b);
 }
 
-hipError_t launch_relayout(int dims, bool split, const RunDev *runs, const int *slots, int n_slots, int move_gx,
+hipError_t launch_relayout(int dims, bool split, RunDev *runs, const int *slots, int n_slots, int move_gx,
                            int commit_gx, int force, hipStream_t s)
 {
     if (n_slots <= 0) return hipSuccess;

@@ -40,7 +40,7 @@ hipError_t launch_convert(int dims, bool split, const RunDev *runs, int run, int
                           const uint32_t *id, hipStream_t s);
 // re-layout of the patch stores of the runs listed in slots[0..n_slots)
 // (plan / move / commit); force = 1 re-lays out even without parked particles
-hipError_t launch_relayout(int dims, bool split, const RunDev *runs, const int *slots, int n_slots, int move_gx,
+hipError_t launch_relayout(int dims, bool split, RunDev *runs, const int *slots, int n_slots, int move_gx,
                            int commit_gx, int force, hipStream_t s);
 // export: live particles -> FP64 arrays at per-segment offsets (off[nseg]
 // = start of the spill part)

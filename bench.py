@@ -85,6 +85,59 @@ def cpu_baseline(wl_name, budget_s=20.0):
             "sample": f"{sample}: {P.n} particles x {steps} steps in {dt:.1f} s"}
 
 
+def bench_scan(args):
+    """Batched parameter scan: independent 2D3V runs stepped together (one
+    launch per phase for all runs, two-step hipGraph replay); patch size from
+    the autotuner.  Value = particle pushes/s summed over the runs."""
+    import torch
+    from paper_1912_04064_amd import binding as B
+    from paper_1912_04064_amd import workloads as WL
+    wls = WL.scan_batch(n_runs=args.runs, steps=args.steps)
+    N = sum(w.n_particles for w in wls)
+    print(f"[bench] scan: {len(wls)} runs, {N} particles", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ctx = B.Context(wls)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    ctx.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    patches = {}
+    for i in range(len(wls)):
+        p = ctx.diag(i)["patch"][0]
+        patches[p] = patches.get(p, 0) + 1
+    ctx.close()
+    return {"metric": "particle-pushes/s (batched scan)", "value": N * args.steps / dt, "unit": "particle-pushes/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+            "data": "synthetic", "config": {"workload": f"scan{len(wls)}", "runs": len(wls), "particles": N,
+                                            "patches_chosen": patches, "init_s": t_init}}
+
+
+def bench_serve(args):
+    """Served request stream: Poisson arrivals, admission by HBM budget and
+    free slots, continuous batching; p50/p99 latency and throughput."""
+    from paper_1912_04064_amd import serving as S
+    from paper_1912_04064_amd import workloads as WL
+    reqs = WL.request_stream(args.serve, window_s=args.window)
+    mk = lambda r: WL.request_workload(r)
+    be = S.GpuBackend(max_runs=args.slots, hbm_budget=0)
+    srv = S.Server(be, hbm_budget=int(args.budget_gb * 2 ** 30), max_runs=args.slots, steps_per_call=20)
+    print(f"[bench] serve: {len(reqs)} requests at {args.serve}/s over {args.window} s", file=sys.stderr, flush=True)
+    recs = srv.serve(reqs, mk)
+    be.close()
+    summ = S.summarize(recs)
+    return {"metric": "runs/s + p99 latency (served)", "value": summ["runs_per_s"], "unit": "runs/s", "n_gpus": 1,
+            "higher_is_better": True, "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],
+            "particle_pushes_per_s": summ["particle_pushes_per_s"], "max_concurrent": srv.max_active,
+            "config": {"workload": f"poisson{args.serve:g}", "requests": len(reqs), "window_s": args.window,
+                       "slots": args.slots, "budget_gb": args.budget_gb}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +147,11 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--phase-samples", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--runs", type=int, default=256, help="runs of the batched scan (--workload scan)")
+    ap.add_argument("--serve", type=float, default=0.0, help="served stream: arrival rate in runs/s")
+    ap.add_argument("--window", type=float, default=10.0, help="served stream: arrival window in s")
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 512 MiB device copy first (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -106,6 +164,12 @@ def main():
     from paper_1912_04064_amd import binding as B
     if not torch.cuda.is_available():
         raise SystemExit("no GPU")
+    if args.serve > 0:
+        print(json.dumps(bench_serve(args)), flush=True)
+        return
+    if args.workload == "scan":
+        print(json.dumps(bench_scan(args)), flush=True)
+        return
     if args.calib_copy:
         x = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)

@@ -125,7 +125,10 @@ typedef struct {
  *     patch[a] = 0 on every axis asks the autotuner to choose;
  *   regions are rectangular, of equal shape, and made of whole patches
  *     (section 2.2, rule B): n_regions[a] >= 1 divides n_cells[a]/patch[a];
- *   shape_order is 2; bc[a] is PIC_BC_PERIODIC; m > 0. */
+ *   shape_order is 2; bc[a] is PIC_BC_PERIODIC; m > 0.
+ * A patch of 0 on every axis lets the library choose: it times a few steps
+ * of each admissible square patch (8, 16, 32 in 2D; 4, 8 in 3D) on this
+ * config and keeps the fastest (cached per grid, precision and density). */
 typedef struct {
     int32_t dims;
     int32_t n_cells[3];
@@ -138,6 +141,9 @@ typedef struct {
     int32_t bc[3];
     int32_t track_ids;          /* carry ids through steps (pic_particles)  */
     double  q, m;               /* species charge and mass; electrons -1, 1 */
+    int64_t max_steps;          /* steps this run takes, 0 = unlimited: once
+                                   they are done the run is left untouched by
+                                   later pic_step calls (continuous batching) */
     const pic_particles_in *particles;   /* may be null: no particles      */
     const pic_fields_in    *fields;      /* may be null: zero fields       */
 } pic_config;
@@ -225,7 +231,8 @@ int pic_admit(pic_ctx *ctx, const pic_config *cfg, int32_t *run_id);
  * before.  Enqueued work is drained first. */
 int pic_retire(pic_ctx *ctx, int32_t run);
 
-/* Number of steps `run` has taken (host counter, no synchronisation). */
+/* Number of steps `run` has taken or will have taken once the enqueued work
+ * completes (host counter, no synchronisation; capped at max_steps). */
 int pic_run_steps(pic_ctx *ctx, int32_t run, int64_t *steps);
 
 /* Time one step phase by phase with HIP events (synchronising, for the

@@ -61,7 +61,8 @@ class PicConfig(C.Structure):
     _fields_ = [("dims", C.c_int32), ("n_cells", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double),
                 ("patch", C.c_int32 * 3), ("n_regions", C.c_int32 * 3), ("shape_order", C.c_int32),
                 ("precision", C.c_int32), ("bc", C.c_int32 * 3), ("track_ids", C.c_int32), ("q", C.c_double),
-                ("m", C.c_double), ("particles", C.POINTER(PicParticlesIn)), ("fields", C.POINTER(PicFieldsIn))]
+                ("m", C.c_double), ("max_steps", C.c_int64), ("particles", C.POINTER(PicParticlesIn)),
+                ("fields", C.POINTER(PicFieldsIn))]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -141,7 +142,7 @@ def _ptr(a: Optional[np.ndarray], ctype=C.c_double):
 class _CfgHolder:
     """A PicConfig plus the numpy arrays its pointers refer to."""
 
-    def __init__(self, wl, track_ids=False, patch=None):
+    def __init__(self, wl, track_ids=False, patch=None, max_steps=0):
         self.keep = []
         p = wl.parts
         n = len(p["x"])
@@ -171,7 +172,7 @@ class _CfgHolder:
         prec = PIC_FP64 if wl.precision == "fp64" else PIC_FP32_SPLIT
         self.cfg = PicConfig(dims, (C.c_int32 * 3)(*nc[:3]), (C.c_double * 3)(*d[:3]), wl.dt,
                              (C.c_int32 * 3)(*pt[:3]), (C.c_int32 * 3)(*nr[:3]), 2, prec, (C.c_int32 * 3)(0, 0, 0),
-                             1 if track_ids else 0, wl.q, wl.m, C.pointer(self.pin),
+                             1 if track_ids else 0, wl.q, wl.m, int(max_steps), C.pointer(self.pin),
                              C.pointer(self.fin) if self.fin is not None else C.POINTER(PicFieldsIn)())
 
 
@@ -193,7 +194,7 @@ class Context:
     """A live set of runs on cuda:0.  Workloads come from ``workloads``."""
 
     def __init__(self, workloads: Sequence, track_ids=False, use_torch=True, graph=True, max_runs=0,
-                 hbm_budget=0, patch=None):
+                 hbm_budget=0, patch=None, max_steps=None):
         self.L = load()
         self._torch = None
         self._cbs = None
@@ -218,7 +219,10 @@ class Context:
 
             self._cbs = (ALLOC_FN(_alloc), FREE_FN(_free))
         self.track_ids = track_ids
-        self._holders = [_CfgHolder(w, track_ids, patch) for w in workloads]
+        ms = max_steps if max_steps is not None else [0] * len(workloads)
+        if isinstance(ms, int):
+            ms = [ms] * len(workloads)
+        self._holders = [_CfgHolder(w, track_ids, patch, m) for w, m in zip(workloads, ms)]
         cfgs = (PicConfig * max(1, len(workloads)))(*[h.cfg for h in self._holders])
         rt = PicRuntime()
         if self._cbs:
@@ -297,8 +301,8 @@ class Context:
         arrs = {k: v[: o.n] for k, v in arrs.items()}
         return arrs
 
-    def admit(self, wl) -> int:
-        h = _CfgHolder(wl, self.track_ids)
+    def admit(self, wl, max_steps=0, patch=None) -> int:
+        h = _CfgHolder(wl, self.track_ids, patch, max_steps)
         rid = C.c_int32()
         _check(self.L, self.ctx, self.L.pic_admit(self.ctx, C.byref(h.cfg), C.byref(rid)), "pic_admit")
         self.workloads[rid.value] = wl

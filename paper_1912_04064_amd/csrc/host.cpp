@@ -13,12 +13,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -44,7 +46,10 @@ struct Run {
     bool split = false;
     int ncell = 0;
     int total_ghosts = 0;
-    int64_t steps = 0;
+    int64_t steps = 0;     // steps taken (issued, capped at target)
+    int64_t issued = 0;    // steps enqueued since admission
+    int64_t target = 0;    // max_steps (0 = unlimited)
+    int par0 = 0;          // E/B buffer holding the state at admission
     size_t bytes = 0;
     RunDev rd{};
     std::vector<DevBuf> bufs;
@@ -379,11 +384,102 @@ static int relayout_one(pic_ctx *c, int slot, int force)
     return PIC_OK;
 }
 
+// ------------------------------------------------------------------ autotuner
+// Square patch edges the particle kernel has compiled paths for
+static std::vector<int> patch_candidates(const pic_config *cfg)
+{
+    std::vector<int> out;
+    const int c2[] = {8, 16, 32}, c3[] = {4, 8};
+    const int *cs = cfg->dims == 2 ? c2 : c3;
+    const int nc = cfg->dims == 2 ? 3 : 2;
+    for (int i = 0; i < nc; ++i) {
+        bool ok = true;
+        for (int a = 0; a < cfg->dims; ++a) {
+            const int nr = cfg->n_regions[a] < 1 ? 1 : cfg->n_regions[a];
+            if (cfg->n_cells[a] % (cs[i] * nr)) ok = false;
+        }
+        if (ok) out.push_back(cs[i]);
+    }
+    return out;
+}
+
+static bool auto_patch(const pic_config *cfg)
+{
+    return cfg->patch[0] == 0 && cfg->patch[1] == 0 && (cfg->dims == 2 || cfg->patch[2] == 0);
+}
+
+using TuneKey = std::tuple<int, int, int, int, int, int, int, int, int>;
+static std::map<TuneKey, int> g_tune_cache;
+static std::mutex g_tune_mu;
+
+// Time 4 steps (after 2 warm-up steps) of the config with each candidate
+// patch in a scratch context on the caller's stream; keep the fastest.
+static void autotune_patch(pic_ctx *c, const pic_config *cfg, int P[3])
+{
+    std::vector<int> cand = patch_candidates(cfg);
+    if (cand.empty()) {
+        default_patch(cfg, P);
+        return;
+    }
+    const long long n = cfg->particles ? cfg->particles->n : 0;
+    long long ncell = 1;
+    for (int a = 0; a < cfg->dims; ++a) ncell *= cfg->n_cells[a];
+    const int ppcb = (int)std::lround(std::log2(std::max(1.0, (double)n / (double)ncell)));
+    const TuneKey key{cfg->dims, cfg->n_cells[0], cfg->n_cells[1], cfg->dims == 3 ? cfg->n_cells[2] : 1,
+                      cfg->precision, ppcb, cfg->n_regions[0], cfg->n_regions[1], cfg->n_regions[2]};
+    int best = cand[0];
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) best = it->second;
+    }
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        cached = g_tune_cache.count(key) > 0;
+    }
+    if (!cached && cand.size() > 1) {
+        float best_ms = 1e30f;
+        for (int p : cand) {
+            pic_config tc = *cfg;
+            tc.patch[0] = tc.patch[1] = p;
+            tc.patch[2] = cfg->dims == 3 ? p : 1;
+            tc.max_steps = 0;
+            pic_runtime trt = c->rt;
+            trt.flags |= PIC_RT_NO_GRAPH;
+            trt.max_runs = 1;
+            trt.hbm_budget = 0;
+            pic_ctx *t = nullptr;
+            if (pic_init(&tc, 1, &trt, &t) != PIC_OK) continue;
+            hipEvent_t e0, e1;
+            float ms = 1e30f;
+            if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+                pic_step(t, 2);
+                hipEventRecord(e0, t->stream);
+                pic_step(t, 4);
+                hipEventRecord(e1, t->stream);
+                if (hipEventSynchronize(e1) == hipSuccess) hipEventElapsedTime(&ms, e0, e1);
+                hipEventDestroy(e0);
+                hipEventDestroy(e1);
+            }
+            pic_free(t);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = p;
+            }
+        }
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    P[0] = P[1] = best;
+    P[2] = cfg->dims == 3 ? best : 1;
+}
+
 static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
 {
     Run &r = c->runs[slot];
     int P[3] = {cfg->patch[0], cfg->patch[1], cfg->patch[2]};
-    if (P[0] == 0 && P[1] == 0 && (cfg->dims == 2 || P[2] == 0)) default_patch(cfg, P);
+    if (auto_patch(cfg)) autotune_patch(c, cfg, P);
     Layout L;
     std::string why;
     int rc = make_layout(cfg, P, L, why);
@@ -424,6 +520,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     d.n_total = (int)L.n_total;
     d.ins_blocks = std::max(1, std::min(64, (int)(L.n_total / 65536)));
     d.ins_segs = 16;
+    d.post_blocks = (r.total_ghosts + BLOCK - 1) / BLOCK + (d.seg_max + d.ins_segs - 1) / d.ins_segs + d.ins_blocks;
     d.ghosts = L.ghosts;
     d.dt = cfg->dt;
     d.q = cfg->q;
@@ -479,6 +576,15 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     HIPCHK(c, hipMemsetAsync(d.scnt, 0, sb, s));
     HIPCHK(c, hipMemsetAsync(d.nlv, 0, sb, s));
     HIPCHK(c, hipMemsetAsync(d.ctl, 0, sizeof(Ctl), s));
+    {
+        Ctl init;
+        memset(&init, 0, sizeof init);
+        init.remaining = cfg->max_steps > 0 ? (int)std::min<int64_t>(cfg->max_steps, (1LL << 30)) : -1;
+        HIPCHK(c, hipMemcpyAsync(d.ctl, &init, sizeof init, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
+    r.target = cfg->max_steps > 0 ? cfg->max_steps : 0;
+    r.par0 = c->par;
     if ((rc = upload_rd(c, slot))) return rc;
 
     // fields
@@ -737,10 +843,15 @@ static bool any_active(pic_ctx *c)
     return false;
 }
 
+static int run_par(const Run &r) { return r.par0 ^ (int)(r.steps & 1); }
+
 static void advance(pic_ctx *c, int nsteps)
 {
     for (auto &r : c->runs)
-        if (r.active) r.steps += nsteps;
+        if (r.active) {
+            r.issued += nsteps;
+            r.steps = r.target > 0 ? std::min(r.issued, r.target) : r.issued;
+        }
     c->step += nsteps;
     if (nsteps & 1) c->par ^= 1;
 }
@@ -768,13 +879,26 @@ const char *pic_last_error(pic_ctx *ctx) { return ctx ? ctx->err.c_str() : g_ini
 int pic_mem_bytes(const pic_config *cfg, size_t *bytes)
 {
     if (!cfg || !bytes) return set_err(nullptr, PIC_E_INVAL, "null argument");
-    int P[3] = {cfg->patch[0], cfg->patch[1], cfg->patch[2]};
-    if (P[0] == 0 && P[1] == 0 && (cfg->dims == 2 || P[2] == 0)) default_patch(cfg, P);
-    Layout L;
-    std::string why;
-    int rc = make_layout(cfg, P, L, why);
-    if (rc) return set_err(nullptr, rc, "%s", why.c_str());
-    *bytes = L.bytes;
+    std::vector<std::array<int, 3>> shapes;
+    if (auto_patch(cfg)) {
+        for (int p : patch_candidates(cfg)) shapes.push_back({p, p, cfg->dims == 3 ? p : 1});
+        if (shapes.empty()) {
+            int P[3];
+            default_patch(cfg, P);
+            shapes.push_back({P[0], P[1], P[2]});
+        }
+    } else {
+        shapes.push_back({cfg->patch[0], cfg->patch[1], cfg->patch[2]});
+    }
+    size_t worst = 0;
+    for (auto &sh : shapes) {
+        Layout L;
+        std::string why;
+        int rc = make_layout(cfg, sh.data(), L, why);
+        if (rc) return set_err(nullptr, rc, "%s", why.c_str());
+        worst = std::max(worst, L.bytes);
+    }
+    *bytes = worst;
     return PIC_OK;
 }
 
@@ -799,7 +923,14 @@ int pic_init(const pic_config *cfgs, int32_t n_runs, const pic_runtime *rt, pic_
     // validate every config before touching the device
     for (int i = 0; i < n_runs; ++i) {
         int P[3] = {cfgs[i].patch[0], cfgs[i].patch[1], cfgs[i].patch[2]};
-        if (P[0] == 0 && P[1] == 0 && (cfgs[i].dims == 2 || P[2] == 0)) default_patch(&cfgs[i], P);
+        if (auto_patch(&cfgs[i])) {
+            std::vector<int> cand = patch_candidates(&cfgs[i]);
+            if (cand.empty())
+                default_patch(&cfgs[i], P);
+            else
+                P[0] = P[1] = P[2] = cand[0];
+            if (cfgs[i].dims == 2) P[2] = 1;
+        }
         Layout L;
         std::string why;
         int rc = make_layout(&cfgs[i], P, L, why);
@@ -939,7 +1070,7 @@ int pic_fields(pic_ctx *c, int32_t run, uint32_t mask, double *dst, size_t dst_l
         if (!(mask & (1u << b))) continue;
         hipError_t e;
         if (b < 12) {
-            e = launch_assemble(c->d_runs, run, r.ncell, field_comp(b, c->par), tmp, c->stream);
+            e = launch_assemble(c->d_runs, run, r.ncell, field_comp(b, run_par(r)), tmp, c->stream);
         } else {
             Ctl ctl = read_ctl(c, run, e);
             if (e == hipSuccess)
@@ -999,7 +1130,7 @@ int pic_diag(pic_ctx *c, int32_t run, pic_diag_t *out)
     if (!part) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
     DevBuf pb{part, align256((size_t)std::max(2 * nb, nk) * 8)};
     std::vector<double> h(std::max(2 * nb, nk));
-    HIPCHK(c, launch_field_energy(c->d_runs, run, r.ncell, c->par, part, nb, c->stream));
+    HIPCHK(c, launch_field_energy(c->d_runs, run, r.ncell, run_par(r), part, nb, c->stream));
     HIPCHK(c, hipMemcpyAsync(h.data(), part, 2 * nb * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double ue = 0, ub = 0;

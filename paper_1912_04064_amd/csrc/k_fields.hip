@@ -76,6 +76,7 @@ __global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ r
     const int4 it = items[blockIdx.x];
     const RunDev &rd = runs[it.x];
     const int tid = threadIdx.x;
+    if (rd.ctl->remaining == 0) return;   // the run has taken all its steps
     // one workgroup per run clears the spill counter: the particle phase of
     // this step has consumed the spill store
     if (it.w && tid == 0) rd.ctl->nspill = 0;
@@ -236,6 +237,10 @@ __device__ __forceinline__ void ghost_copy(const RunDev &rd, int gk, const int *
 }
 
 // ------------------------------------------------------------ post kernel
+// Every workgroup of a run reads the run's step budget before it arrives at
+// the run's arrival counter; the last to arrive ends the step for the run
+// (clears the overflow counter, spends one step of the budget).  Kernels of
+// the next step see the new budget, so a run stops exactly on its last step.
 template <int DIM, class T>
 __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ runs, const int4 *__restrict__ items,
                                                      int par_new)
@@ -243,84 +248,86 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
     const int4 it = items[blockIdx.x];
     const RunDev &rd = runs[it.x];
     const int tid = threadIdx.x;
-    if (it.y == 0) {
+    const bool active = rd.ctl->remaining != 0;
+    int err = 0;
+    if (active && it.y == 0) {
         const int comps[9] = {f_E(par_new), f_E(par_new) + 1, f_E(par_new) + 2, f_B(par_new), f_B(par_new) + 1,
                               f_B(par_new) + 2, F_BM, F_BM + 1, F_BM + 2};
         const int gk = it.z + tid;
         if (gk < rd.ghosts * rd.n_regions) ghost_copy(rd, gk, comps, 9);
-        return;
-    }
-    // insert the leavers of this step into their destination patch
-    const int tid_ = threadIdx.x;
-    int err = 0;
-    auto insert = [&](const Store &src, const int *srcpatch, long long i) {
-        // the destination patch's segments take leavers in turn
-        const int q = srcpatch[i];
-        const int k0 = rd.pseg[q], nk = rd.pseg[q + 1] - k0;
-        const int t = k0 + (nk > 1 ? (int)(i % nk) : 0);
-        const int slot = atomicAdd(&rd.scnt[t], 1);
-        const int cap = rd.sseg[t + 1] - rd.sseg[t];
-        return slot < cap ? (long long)rd.sseg[t] + slot : -1ll - q;
-    };
-    // parking (full destination segment) claims its slots once per wavefront
-    auto place = [&](const Store &src, long long i, bool valid, long long dst) {
-        const bool park = valid && dst < 0;
-        const unsigned long long mp = __ballot(park);
-        int pbase = 0;
-        if (mp) {
-            if ((threadIdx.x & 63) == 0) pbase = atomicAdd(&rd.ctl->nspill, __popcll(mp));
-            pbase = __shfl(pbase, 0);
-        }
-        if (valid && dst >= 0) copy_part<DIM, T>(src, i, rd.st, dst);
-        if (park) {
-            const int s = pbase + __popcll(mp & ((1ull << (threadIdx.x & 63)) - 1ull));
-            if (s < rd.n_total) {
-                copy_part<DIM, T>(src, i, rd.sp, s);
-                rd.spatch[s] = (int)(-1ll - dst);
-            } else {
-                err |= ERR_CAPACITY;
+    } else if (active) {
+        // insert the leavers of this step into their destination patch
+        auto insert = [&](const int *srcpatch, long long i) -> long long {
+            // the destination patch's segments take leavers in turn
+            const int q = srcpatch[i];
+            const int k0 = rd.pseg[q], nk = rd.pseg[q + 1] - k0;
+            const int t = k0 + (nk > 1 ? (int)(i % nk) : 0);
+            const int slot = atomicAdd(&rd.scnt[t], 1);
+            const int cap = rd.sseg[t + 1] - rd.sseg[t];
+            return slot < cap ? (long long)rd.sseg[t] + slot : -1ll - q;
+        };
+        // parking (full destination segment) claims its slots once per wavefront
+        auto place = [&](const Store &src, long long i, bool valid, long long dst) {
+            const bool park = valid && dst < 0;
+            const unsigned long long mp = __ballot(park);
+            int pbase = 0;
+            if (mp) {
+                if ((tid & 63) == 0) pbase = atomicAdd(&rd.ctl->nspill, __popcll(mp));
+                pbase = __shfl(pbase, 0);
+            }
+            if (valid && dst >= 0) copy_part<DIM, T>(src, i, rd.st, dst);
+            if (park) {
+                const int s = pbase + __popcll(mp & ((1ull << (tid & 63)) - 1ull));
+                if (s < rd.n_total) {
+                    copy_part<DIM, T>(src, i, rd.sp, s);
+                    rd.spatch[s] = (int)(-1ll - dst);
+                } else {
+                    err |= ERR_CAPACITY;
+                }
+            }
+        };
+        if (it.y == 1) {
+            // one wavefront per segment: the segment's leavers sit in its own
+            // region of the leaver store
+            const int wave = tid >> 6, lane = tid & 63;
+            const int s1 = min(it.z + it.w, rd.ctl->nseg);
+            for (int sg = it.z + wave; sg < s1; sg += BLOCK / 64) {
+                const int nl = rd.nlv[sg];
+                const long long b = rd.sseg[sg];
+                for (int k0 = 0; k0 < nl; k0 += 64) {
+                    const int k = k0 + lane;
+                    const bool v = k < nl;
+                    place(rd.lv, b + k, v, v ? insert(rd.lpatch, b + k) : 0);
+                }
+            }
+        } else {
+            // overflow leavers (parked particles that re-entered): a few
+            // workgroups stride over them
+            const int nb = it.w;
+            const int nl = min(rd.ctl->nleave, rd.n_total);
+            for (int i0 = it.z * BLOCK; i0 < nl; i0 += nb * BLOCK) {
+                const int i = i0 + tid;
+                const bool v = i < nl;
+                place(rd.lo, i, v, v ? insert(rd.lopatch, i) : 0);
             }
         }
-    };
-    if (it.y == 1) {
-        // one wavefront per segment: the segment's leavers sit in its own
-        // region of the leaver store
-        const int wave = tid_ >> 6, lane = tid_ & 63;
-        const int s1 = min(it.z + it.w, rd.ctl->nseg);
-        for (int sg = it.z + wave; sg < s1; sg += BLOCK / 64) {
-            const int nl = rd.nlv[sg];
-            const long long b = rd.sseg[sg];
-            for (int k0 = 0; k0 < nl; k0 += 64) {
-                const int k = k0 + lane;
-                const bool v = k < nl;
-                place(rd.lv, b + k, v, v ? insert(rd.lv, rd.lpatch, b + k) : 0);
-            }
-        }
-        if (err) atomicOr(&rd.ctl->err, err);
-        return;
-    }
-    // overflow leavers (parked particles that re-entered): a few workgroups
-    // stride over them; the last one to finish clears the counter
-    __shared__ int s_last;
-    const int nb = it.w;
-    const int nl = min(rd.ctl->nleave, rd.n_total);
-    for (int i0 = it.z * BLOCK; i0 < nl; i0 += nb * BLOCK) {
-        const int i = i0 + tid_;
-        const bool v = i < nl;
-        place(rd.lo, i, v, v ? insert(rd.lo, rd.lopatch, i) : 0);
     }
     if (err) atomicOr(&rd.ctl->err, err);
+    __shared__ int s_last;
     __syncthreads();
-    if (tid_ == 0) {
+    if (tid == 0) {
         __threadfence();
-        s_last = atomicAdd(&rd.ctl->ins_done, 1) == nb - 1;
+        s_last = atomicAdd(&rd.ctl->post_done, 1) == rd.post_blocks - 1;
     }
     __syncthreads();
-    if (s_last && tid_ == 0) {
-        const int ns = rd.ctl->nspill;
-        if (ns > rd.ctl->max_spill) rd.ctl->max_spill = ns;
-        rd.ctl->nleave = 0;
-        rd.ctl->ins_done = 0;
+    if (s_last && tid == 0) {
+        if (active) {
+            const int ns = rd.ctl->nspill;
+            if (ns > rd.ctl->max_spill) rd.ctl->max_spill = ns;
+            rd.ctl->nleave = 0;
+            if (rd.ctl->remaining > 0) rd.ctl->remaining -= 1;
+        }
+        rd.ctl->post_done = 0;
     }
 }
 

@@ -386,7 +386,7 @@ __global__ __launch_bounds__(PUSH_BLOCK) void push_kernel(const RunDev *__restri
     const int2 item = items[blockIdx.x];
     const RunDev &rd = runs[item.x];
     const int sg = item.y;               // segment
-    if (sg >= rd.ctl->nseg) return;      // segment slot not in use this layout
+    if (sg >= rd.ctl->nseg || rd.ctl->remaining == 0) return;   // slot unused, or run finished
     const int q = rd.spat[sg];           // its patch
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 

@@ -75,12 +75,14 @@ struct Store {
 struct Ctl {
     int nleave;       // particles appended to the overflow leaver store this step
     int nspill;       // particles parked in the spill store
-    int ins_done;     // overflow-insert workgroups finished (last one resets nleave)
+    int post_done;    // post-kernel workgroups of this run finished this step
     int err;          // ERR_* bits, sticky
     int relayout;     // set by the re-layout planner when a re-layout runs
     int n_relayout;   // re-layouts done
     int max_spill;    // largest nspill seen
     int nseg;         // segments in use
+    int remaining;    // steps left (-1: unlimited); 0 makes every kernel skip the run
+    int pad[3];
 };
 
 struct RunDev {
@@ -102,6 +104,7 @@ struct RunDev {
     int n_total;         // particles of the run
     int ins_blocks;      // workgroups inserting the overflow leavers
     int ins_segs;        // segments per leaver-insert workgroup
+    int post_blocks;     // post-kernel workgroups of this run per step
     int ghosts;          // ghost nodes per region
     double d[3], L[3];
     double dt, q, m;

@@ -367,15 +367,18 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
 
 // PX: exact patch edge (0 = sizes from the run descriptor); PC: LDS sizing
 // class (the largest patch edge the instantiation accepts)
-// threads per particle-kernel workgroup
-constexpr int PUSH_BLOCK = 256;
+// threads per particle-kernel workgroup: 3D workgroups hold an 85 KB LDS
+// window + tile, so only one fits per CU; 16 wavefronts keep it busy
+// (FP64 3D: 512, its 128+ registers per lane do not fit 16 wavefronts)
+template <int DIM, class T>
+constexpr int push_block() { return DIM == 3 ? (T::split ? 1024 : 512) : 256; }
 
 template <int DIM, class T, int PX, int PC>
-__global__ __launch_bounds__(PUSH_BLOCK) void push_kernel(const RunDev *__restrict__ runs,
-                                                          const int2 *__restrict__ items, int par)
+__global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunDev *__restrict__ runs,
+                                                                 const int2 *__restrict__ items, int par)
 {
     using R = typename T::real;
-    constexpr int BLOCK = PUSH_BLOCK;
+    constexpr int BLOCK = push_block<DIM, T>();
     constexpr int WN = (PC + 3) * (PC + 3) * (DIM == 3 ? PC + 3 : 1);
     constexpr int TN = (PC + 5) * (PC + 5) * (DIM == 3 ? PC + 5 : 1);
     constexpr int NW = BLOCK / 64;
@@ -504,7 +507,7 @@ __global__ __launch_bounds__(PUSH_BLOCK) void push_kernel(const RunDev *__restri
 
 #define PUSH_CASE(D, TT, PXV, PCV)                                                                  \
     if (dims == D && split == TT::split && px == PXV && pc == PCV) {                                \
-        push_kernel<D, TT, PXV, PCV><<<n_items, PUSH_BLOCK, 0, s>>>(runs, items, par);                   \
+        push_kernel<D, TT, PXV, PCV><<<n_items, push_block<D, TT>(), 0, s>>>(runs, items, par);                   \
         return hipGetLastError();                                                                   \
     }
 

@@ -56,6 +56,26 @@ def particle_bytes(wl):
     return rd + wr
 
 
+def push_traffic(wl_name):
+    """HBM bytes per particle-kernel launch from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs (scaled by a plain copy of known size), or None
+    when the workload differs or the kernel sources changed since then."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get("push_kernel", {})
+    if rec.get("workload") != {"lwfa": "lwfa2048x256"}.get(wl_name):
+        return None
+    h = hashlib.sha256()
+    for f in ("k_push.hip", "part.h", "sdmd_dev.h"):
+        with open(os.path.join(ROOT, "paper_1912_04064_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != rec.get("source_sha"):
+        return None
+    return float(rec["bytes_per_launch"])
+
+
 def cpu_baseline(wl_name, budget_s=20.0):
     """The FP64 oracle (single thread) on a bounded sample of the same
     workload: a horizontal band of the grid with its particles, full steps."""
@@ -228,7 +248,7 @@ def main():
         "phase_ms": {"particles": push_avg, "reduce_maxwell": float(np.mean(yee_ms)),
                      "sync_rebin": float(np.mean(post_ms))},
         "roofline": {"bound": "hbm", "kernel": "push_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": push_traffic(args.workload),
                      "bytes_per_launch": alg_push},
         "relayouts": d["n_relayout"],
     }

@@ -50,6 +50,7 @@ class OCfg(C.Structure):
         ("m", C.c_double),
         ("patch", C.c_int32 * 3),
         ("nreg", C.c_int32 * 3),
+        ("filter", C.c_int32),
     ]
 
 
@@ -81,6 +82,7 @@ def lib():
         L.oracle_deposit_one.argtypes = [C.POINTER(OCfg), dp, dp, dp, C.c_double, C.c_double]
         L.oracle_yee.argtypes = [C.POINTER(OCfg), dp]
         L.oracle_init_fields.argtypes = [C.POINTER(OCfg), dp]
+        L.oracle_filter.argtypes = [C.POINTER(OCfg), dp, C.c_int32, C.c_int32]
         L.oracle_wrap.restype = C.c_double
         L.oracle_wrap.argtypes = [C.c_double, C.c_double]
         L.oracle_cell.restype = C.c_int64
@@ -113,7 +115,7 @@ def _dp(a: np.ndarray):
 class Grid:
     """Grid/decomposition description handed to every oracle call."""
 
-    def __init__(self, dims, n, d, dt, q=-1.0, m=1.0, patch=(8, 8, 8), nreg=(1, 1, 1)):
+    def __init__(self, dims, n, d, dt, q=-1.0, m=1.0, patch=(8, 8, 8), nreg=(1, 1, 1), filter=0):
         n = list(n) + [1] * (3 - len(n))
         d = list(d) + [1.0] * (3 - len(d))
         patch = list(patch) + [1] * (3 - len(patch))
@@ -121,9 +123,9 @@ class Grid:
         if dims == 2:
             n[2], d[2], patch[2], nreg[2] = 1, 1.0, 1, 1
         self.dims, self.n, self.d, self.dt, self.q, self.m = dims, n, d, dt, q, m
-        self.patch, self.nreg = patch, nreg
+        self.patch, self.nreg, self.filter = patch, nreg, filter
         self.c = OCfg(dims, (C.c_int32 * 3)(*n), (C.c_double * 3)(*d), dt, q, m,
-                      (C.c_int32 * 3)(*patch), (C.c_int32 * 3)(*nreg))
+                      (C.c_int32 * 3)(*patch), (C.c_int32 * 3)(*nreg), int(filter))
 
     @property
     def shape(self):
@@ -184,6 +186,15 @@ def deposit_one(g: Grid, J: np.ndarray, x0, x1, w, vz=0.0):
 
 def yee(g: Grid, F: np.ndarray):
     lib().oracle_yee(C.byref(g.c), _dp(F))
+
+
+def filter_arrays(g: Grid, a: np.ndarray, passes: int) -> np.ndarray:
+    """Binomial filter (``passes`` passes) of a stack of global arrays,
+    shape (k, nz, ny, nx) or (nz, ny, nx); returns a filtered copy."""
+    out = np.ascontiguousarray(a, dtype=np.float64).copy()
+    k = 1 if out.ndim == 3 else out.shape[0]
+    lib().oracle_filter(C.byref(g.c), _dp(out), int(k), int(passes))
+    return out
 
 
 def init_fields(g: Grid, F: np.ndarray):

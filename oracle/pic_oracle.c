@@ -65,6 +65,7 @@ typedef struct {
     double  q, m;        /* species charge and mass (electrons: -1, 1) */
     int32_t patch[3];    /* SDMD: cells per patch per axis */
     int32_t nreg[3];     /* SDMD: regions per axis */
+    int32_t filter;      /* passes of the binomial current filter (0 = none) */
 } ocfg;
 
 typedef struct {
@@ -362,6 +363,48 @@ void oracle_init_fields(const ocfg* c, double* F)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Binomial current filter (section 3.2: a two-pass binomial filter smooths  */
+/* the current densities every iteration; Birdsall & Langdon).  One pass     */
+/* smooths a component along x, then y, then z (3D) with the 1-2-1 kernel,   */
+/* out(i) = (in(i-1) + 2 in(i) + in(i+1)) / 4, periodic, on the component's  */
+/* own lattice (the kernel is shift invariant, so the staggering of Jx, Jy,  */
+/* Jz needs no special treatment).  Applied to J after deposition (and, in   */
+/* SDMD, after the patch -> region sum), before Ampere.                      */
+/* ------------------------------------------------------------------------ */
+static void binomial_sweep(const ocfg* c, double* a, double* tmp, int axis)
+{
+    for (int64_t k = 0; k < c->n[2]; ++k)
+        for (int64_t j = 0; j < c->n[1]; ++j)
+            for (int64_t i = 0; i < c->n[0]; ++i) {
+                int64_t lo, hi;
+                if (axis == 0) {
+                    lo = gidx(c, i - 1, j, k);
+                    hi = gidx(c, i + 1, j, k);
+                } else if (axis == 1) {
+                    lo = gidx(c, i, j - 1, k);
+                    hi = gidx(c, i, j + 1, k);
+                } else {
+                    lo = gidx(c, i, j, k - 1);
+                    hi = gidx(c, i, j, k + 1);
+                }
+                int64_t p = gidx(c, i, j, k);
+                tmp[p] = (a[lo] + 2.0 * a[p] + a[hi]) * 0.25;
+            }
+    memcpy(a, tmp, sizeof(double) * ncells(c));
+}
+
+/* `passes` passes over `ncomp` consecutive global arrays */
+void oracle_filter(const ocfg* c, double* a, int32_t ncomp, int32_t passes)
+{
+    int64_t N = ncells(c);
+    double* tmp = (double*)malloc(sizeof(double) * N);
+    for (int comp = 0; comp < ncomp; ++comp)
+        for (int pass = 0; pass < passes; ++pass)
+            for (int axis = 0; axis < c->dims; ++axis) binomial_sweep(c, a + comp * N, tmp, axis);
+    free(tmp);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Position wrap and cell / patch binning.                                   */
 /* ------------------------------------------------------------------------ */
 double oracle_wrap(double x, double L)
@@ -475,6 +518,7 @@ void oracle_push_only(const ocfg* c, const double* F, oparts* P)
 double oracle_step_sdsd(const ocfg* c, double* F, oparts* P)
 {
     double maxd = oracle_particles_sdsd(c, F, P);
+    if (c->filter > 0) oracle_filter(c, F + JX * ncells(c), 3, c->filter);
     oracle_yee(c, F);
     return maxd;
 }
@@ -745,6 +789,41 @@ int oracle_step_sdmd(const ocfg* c, double* F, oparts* P, int32_t fields_only)
         free(off);
         free(order);
         free(fill);
+
+        /* 4b. binomial filter on the regions: before each pass the regions  */
+        /*     synchronise their J ghosts; a sweep along an axis runs on the */
+        /*     interior along that axis and one ghost node further along the */
+        /*     axes still to be swept, so the next sweep finds its inputs.   */
+        for (int pass = 0; pass < c->filter; ++pass) {
+            for (int comp = JX; comp <= JZ; ++comp) exchange_ghosts(c, R, nR, rs, comp);
+            for (int r = 0; r < nR; ++r) {
+                region* g = &R[r];
+                int64_t S = rsize(g);
+                double* tmp = (double*)malloc(sizeof(double) * S);
+                for (int comp = JX; comp <= JZ; ++comp) {
+                    double* f = g->f + comp * S;
+                    for (int axis = 0; axis < dims; ++axis) {
+                        int64_t lo[3], hi[3];
+                        for (int b = 0; b < 3; ++b) {
+                            int ext = (b < dims && b > axis) ? 1 : 0;
+                            lo[b] = -ext;
+                            hi[b] = g->s[b] + ext;
+                        }
+                        memcpy(tmp, f, sizeof(double) * S);
+                        for (int64_t lk = lo[2]; lk < hi[2]; ++lk)
+                            for (int64_t lj = lo[1]; lj < hi[1]; ++lj)
+                                for (int64_t li = lo[0]; li < hi[0]; ++li) {
+                                    int64_t p = ridx(g, li, lj, lk);
+                                    int64_t m = ridx(g, li - (axis == 0), lj - (axis == 1), lk - (axis == 2));
+                                    int64_t q = ridx(g, li + (axis == 0), lj + (axis == 1), lk + (axis == 2));
+                                    tmp[p] = (f[m] + 2.0 * f[p] + f[q]) * 0.25;
+                                }
+                        memcpy(f, tmp, sizeof(double) * S);
+                    }
+                }
+                free(tmp);
+            }
+        }
     } else {
         /* currents are taken as given in F */
         for (int r = 0; r < nR; ++r)

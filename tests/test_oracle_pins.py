@@ -561,3 +561,95 @@ def test_diagnostics_closed_forms():
     assert k == pytest.approx(0.7 * (math.sqrt(1 + u @ u) - 1.0) * 0.5 * 0.25)
     r = O.rho(g, P)
     assert r.sum() == pytest.approx(-1.0 * (0.7 + 0.2), abs=1e-14)
+
+
+# --------------------------------------------------------------------------
+# binomial current filter
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dims", [2, 3])
+@pytest.mark.parametrize("passes", [1, 2, 3])
+def test_binomial_filter_fourier_transfer_function(dims, passes):
+    """The 1-2-1 kernel multiplies the periodic mode exp(i theta i) by
+    (2 + 2 cos theta) / 4 = cos^2(theta / 2); a pass applies it along every
+    axis, so a cosine mode comes back scaled by prod_a cos^2(pi m_a / n_a),
+    raised to the number of passes."""
+    n = (16, 12, 1) if dims == 2 else (8, 6, 10)
+    g = O.Grid(dims, n[:dims], (0.1,) * dims, 0.01)
+    rng = np.random.default_rng(40 + passes)
+    k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    for _ in range(4):
+        m = [int(rng.integers(0, n[a])) for a in range(3)]
+        if dims == 2:
+            m[2] = 0
+        phi = rng.uniform(0, 2 * math.pi)
+        a = np.cos(2 * math.pi * (m[0] * i / n[0] + m[1] * j / n[1] + m[2] * k / n[2]) + phi)
+        factor = 1.0
+        for ax in range(dims):
+            factor *= math.cos(math.pi * m[ax] / n[ax]) ** 2
+        out = O.filter_arrays(g, a, passes)
+        np.testing.assert_allclose(out, factor ** passes * a, rtol=0, atol=1e-14)
+
+
+def test_binomial_filter_special_cases():
+    """Constants pass unchanged, the checkerboard (Nyquist) mode along an axis
+    is removed by one pass, and the sum over the grid is preserved."""
+    g = O.Grid(2, (10, 8), (0.1, 0.1), 0.01)
+    const = np.full((1, 8, 10), 3.25)
+    assert np.array_equal(O.filter_arrays(g, const, 2), const)
+    nyq = np.tile((-1.0) ** np.arange(10), (1, 8, 1))
+    assert np.array_equal(O.filter_arrays(g, nyq, 1), np.zeros_like(nyq))
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((3, 1, 8, 10))
+    f = O.filter_arrays(g, a, 2)
+    np.testing.assert_allclose(f.sum(axis=(1, 2, 3)), a.sum(axis=(1, 2, 3)), atol=1e-13)
+    # each component is filtered on its own
+    np.testing.assert_array_equal(f[1], O.filter_arrays(g, a[1], 2))
+
+
+@pytest.mark.parametrize("nreg", [(2, 2), (4, 4)])
+def test_sdmd_filtered_step_matches_sdsd(nreg):
+    """With the filter on, regions filter with a J ghost exchange before each
+    pass; the result is the global filter's (regions = patches at (4, 4))."""
+    wl = WL.thermal_2d(n=(32, 32), ppc=4, vth=0.05, patch=(8, 8))
+    gA = O.Grid(2, wl.n, wl.d, wl.dt, patch=wl.patch, nreg=(1, 1), filter=2)
+    gB = O.Grid(2, wl.n, wl.d, wl.dt, patch=wl.patch, nreg=nreg, filter=2)
+    g0 = O.Grid(2, wl.n, wl.d, wl.dt, patch=wl.patch)
+    FA = gA.zeros_fields()
+    FB, F0 = FA.copy(), FA.copy()
+    PA, PB, P0 = _thermal_parts(wl), _thermal_parts(wl), _thermal_parts(wl)
+    O.step_sdsd(gA, FA, PA)
+    O.step_sdmd(gB, FB, PB)
+    O.step_sdsd(g0, F0, P0)
+    scale = np.abs(FA[9:12]).max()
+    assert np.abs(FA - FB).max() <= 1e-13 * scale
+    # the filter did act: the unfiltered current differs at O(1)
+    assert np.abs(FA[9:12] - F0[9:12]).max() > 0.1 * scale
+    np.testing.assert_allclose(FA[9:12], O.filter_arrays(g0, F0[9:12], 2), rtol=0, atol=1e-14 * scale)
+
+
+@pytest.mark.parametrize("nreg", [(1, 1), (3, 3)])
+def test_gauss_residual_with_filter(nreg):
+    """The binomial filter commutes with the discrete divergence (both are
+    shift invariant and periodic), so with a filtered current
+    div E - F(rho) stays constant, where F is the same filter applied to
+    rho."""
+    wl = WL.thermal_2d(n=(24, 24), ppc=4, vth=0.05)
+    g = O.Grid(2, wl.n, wl.d, wl.dt, patch=(8, 8), nreg=nreg, filter=2)
+    F = g.zeros_fields()
+    P = _thermal_parts(wl)
+
+    def resid():
+        return O.divE(g, F) - O.filter_arrays(g, O.rho(g, P), 2)[0]
+
+    r0 = resid()
+    scale = np.abs(O.rho(g, P)).max()
+    for _ in range(60):
+        if nreg == (1, 1):
+            O.step_sdsd(g, F, P)
+        else:
+            O.step_sdmd(g, F, P)
+    r1 = resid()
+    assert np.abs(r1 - r0).max() <= 1e-12 * scale
+    # without filtering rho the residual drifts: the filter is really there
+    r_unf = O.divE(g, F) - O.rho(g, P) - (0.0 - O.rho(g, _thermal_parts(wl)))
+    assert np.abs(r_unf).max() > 1e-6 * scale

@@ -158,6 +158,45 @@ def bench_serve(args):
                        "slots": args.slots, "budget_gb": args.budget_gb}}
 
 
+def bench_sdsd(args):
+    """The paper's central comparison on one GPU: the LWFA input with fields
+    on regions (SDMD, 4 regions of 512 x 256) against fields on the patches
+    themselves (SDSD: one region per patch, so every patch runs its own Yee
+    update and exchanges ghosts with its neighbours), for several patch
+    sizes.  Same particle kernel, same input; ms/step and phase split."""
+    import dataclasses
+    import torch
+    from paper_1912_04064_amd import binding as B
+    from paper_1912_04064_amd import workloads as WL
+    base = WL.lwfa_2d()
+    rows = []
+    for P in (8, 16, 32):
+        for mode in ("sdmd", "sdsd"):
+            nreg = (4, 1) if mode == "sdmd" else (base.n[0] // P, base.n[1] // P)
+            wl = dataclasses.replace(base, patch=(P, P), nreg=nreg)
+            ctx = B.Context([wl], graph=not args.no_graph)
+            ctx.step(args.warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.step(args.steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ph = []
+            for _ in range(max(1, args.phase_samples)):
+                ctx.time_phases()
+                ph.append(ctx.diag(0)["t_ms"][:3])
+            ctx.close()
+            ph = np.mean(np.array(ph), axis=0)
+            row = {"patch": P, "mode": mode, "regions": nreg[0] * nreg[1], "ms_per_step": dt * 1e3 / args.steps,
+                   "pushes_per_s": wl.n_particles * args.steps / dt, "particles_ms": float(ph[0]),
+                   "fields_ms": float(ph[1]), "sync_ms": float(ph[2])}
+            print(f"[bench] {row}", file=sys.stderr, flush=True)
+            rows.append(row)
+    return {"metric": "ms/step, SDMD regions vs SDSD patches", "unit": "ms/step", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": False, "vs_baseline": None, "dtype": "f32+f64",
+            "data": "synthetic", "config": {"workload": base.name, "precision": base.precision}, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +211,8 @@ def main():
     ap.add_argument("--window", type=float, default=10.0, help="served stream: arrival window in s")
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--compare-sdsd", action="store_true",
+                    help="fields on regions (SDMD) vs on patches (SDSD) for patch sizes 8, 16, 32")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 512 MiB device copy first (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -186,6 +227,9 @@ def main():
         raise SystemExit("no GPU")
     if args.serve > 0:
         print(json.dumps(bench_serve(args)), flush=True)
+        return
+    if args.compare_sdsd:
+        print(json.dumps(bench_sdsd(args)), flush=True)
         return
     if args.workload == "scan":
         print(json.dumps(bench_scan(args)), flush=True)

@@ -77,7 +77,8 @@ extern "C" {
 #define PIC_F_BHX  (1u << 6)   /* B at t^{n+1/2} (needed to resume a run)    */
 #define PIC_F_BHY  (1u << 7)
 #define PIC_F_BHZ  (1u << 8)
-#define PIC_F_JX   (1u << 9)   /* J at t^{n-1/2}, from the last step          */
+#define PIC_F_JX   (1u << 9)   /* J at t^{n-1/2}, from the last step, as the
+                                  Maxwell solve used it (after the filter)    */
 #define PIC_F_JY   (1u << 10)
 #define PIC_F_JZ   (1u << 11)
 #define PIC_F_RHO  (1u << 12)  /* electron charge density at t^n (deposited on
@@ -125,7 +126,8 @@ typedef struct {
  *     patch[a] = 0 on every axis asks the autotuner to choose;
  *   regions are rectangular, of equal shape, and made of whole patches
  *     (section 2.2, rule B): n_regions[a] >= 1 divides n_cells[a]/patch[a];
- *   shape_order is 2; bc[a] is PIC_BC_PERIODIC; m > 0.
+ *   shape_order is 2; bc[a] is PIC_BC_PERIODIC; m > 0;
+ *   0 <= filter_passes <= 4 (2D) or 2 (3D); reserved is 0.
  * A patch of 0 on every axis lets the library choose: it times a few steps
  * of each admissible square patch (8, 16, 32 in 2D; 4, 8 in 3D) on this
  * config and keeps the fastest (cached per grid, precision and density). */
@@ -140,6 +142,12 @@ typedef struct {
     int32_t precision;          /* PIC_FP64 or PIC_FP32_SPLIT */
     int32_t bc[3];
     int32_t track_ids;          /* carry ids through steps (pic_particles)  */
+    int32_t filter_passes;      /* binomial current filter (section 3.2, the
+                                   paper's run uses two passes): 0 = off; a
+                                   pass smooths each J component with the
+                                   1-2-1 kernel along x, then y, then z;
+                                   at most 4 passes in 2D, 2 in 3D          */
+    int32_t reserved;           /* must be 0                                */
     double  q, m;               /* species charge and mass; electrons -1, 1 */
     int64_t max_steps;          /* steps this run takes, 0 = unlimited: once
                                    they are done the run is left untouched by

@@ -66,6 +66,8 @@ struct PushClass {
 struct FieldClass {
     int dims;
     bool split;
+    int tx;      // Yee tile x extent
+    bool filt;   // runs with the binomial current filter
     std::vector<int4> hy, hp;
     std::vector<int> slots;
     int4 *dy = nullptr, *dp = nullptr;
@@ -216,6 +218,9 @@ static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::st
     }
     if (dims == 2 && cfg->n_cells[2] != 1) return fail("n_cells[2] must be 1 in 2D");
     if (!(cfg->dt > 0) || !(cfg->dt < 1.0 / std::sqrt(inv2))) return fail("dt must satisfy 0 < dt < 1/sqrt(sum 1/d^2)");
+    if (cfg->filter_passes < 0 || cfg->filter_passes > (dims == 2 ? 4 : 2))
+        return fail("filter_passes must be 0..4 in 2D, 0..2 in 3D");
+    if (cfg->reserved != 0) return fail("reserved must be 0");
     const int pmax = dims == 2 ? 32 : 8;
     L.dims = dims;
     L.split = cfg->precision == PIC_FP32_SPLIT;
@@ -499,6 +504,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     memset(&d, 0, sizeof d);
     d.dims = L.dims;
     d.prec = cfg->precision;
+    d.filter = cfg->filter_passes;
     for (int a = 0; a < 3; ++a) {
         d.n[a] = L.n[a];
         d.P[a] = L.P[a];
@@ -696,11 +702,13 @@ static int rebuild_items(pic_ctx *c)
             c->pcls.push_back(PushClass{r.dims, r.pc, r.px, r.split});
             pc = &c->pcls.back();
         }
+        const bool filt = r.rd.filter > 0;
+        const int ytx = yee_tile_x(r.dims, r.rd.rs[0], filt);
         FieldClass *fc = nullptr;
         for (auto &x : c->fcls)
-            if (x.dims == r.dims && x.split == r.split) fc = &x;
+            if (x.dims == r.dims && x.split == r.split && x.tx == ytx && x.filt == filt) fc = &x;
         if (!fc) {
-            c->fcls.push_back(FieldClass{r.dims, r.split});
+            c->fcls.push_back(FieldClass{r.dims, r.split, ytx, filt});
             fc = &c->fcls.back();
         }
         const RunDev &d = r.rd;
@@ -726,8 +734,9 @@ static int rebuild_items(pic_ctx *c)
         for (int q = 0; q < np && k < np; ++q)
             if (!seen[q]) pc->h[base + k++] = make_int2(slot, q);
         // yee items
-        constexpr int TX2 = 64, TY2 = 4, TX3 = 32, TY3 = 4, TZ3 = 2;
-        const int tx = r.dims == 2 ? TX2 : TX3, ty = r.dims == 2 ? TY2 : TY3, tz = r.dims == 2 ? 1 : TZ3;
+        int shape[3];
+        yee_tile_shape(r.dims, ytx, shape);
+        const int tx = shape[0], ty = shape[1], tz = shape[2];
         const int ntiles = ((d.rs[0] + tx - 1) / tx) * ((d.rs[1] + ty - 1) / ty) * ((d.rs[2] + tz - 1) / tz);
         bool first = true;
         for (int reg = 0; reg < d.n_regions; ++reg)
@@ -769,7 +778,7 @@ static hipError_t enqueue_push(pic_ctx *c, int par, hipStream_t s)
 static hipError_t enqueue_yee(pic_ctx *c, int par, hipStream_t s)
 {
     for (auto &fc : c->fcls) {
-        hipError_t e = launch_yee(fc.dims, fc.split, c->d_runs, fc.dy, (int)fc.hy.size(), par, s);
+        hipError_t e = launch_yee(fc.dims, fc.split, fc.tx, fc.filt, c->d_runs, fc.dy, (int)fc.hy.size(), par, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -1,7 +1,7 @@
 // k_fields.hip -- region-side kernels of the SDMD step.
 //
-//   yee_kernel   : transfer (i) of section 2.2 fused with the Yee update
-//                  (section 3.2).  For every node of its tile (plus a
+//   yee_kernel   : transfer (i) of section 2.2 fused with the optional
+//                  binomial current filter and the Yee update (section 3.2).  For every node of its tile (plus a
 //                  one-node high halo) a workgroup sums the current of the
 //                  patch tiles covering that node (at most 2 patches per
 //                  axis when P >= 5, fixed order, FP64 sum), applies Ampere,
@@ -19,11 +19,13 @@
 namespace sdmd {
 
 // --------------------------------------------------------------- J gather
-// Current at global node g of component c: sum over the segment tiles of the
-// patches whose node range [p0-2, p0+P+2] covers g (periodic), in a fixed
-// order.
+// Current at global node g: for each component, the sum over the segment
+// tiles of the patches whose node range [p0-2, p0+P+2] covers g (periodic),
+// in a fixed order (patches by offset, then segments).  The three components
+// are read in one pass so their loads overlap.
 template <int DIM, class R>
-__device__ __forceinline__ double gather_J(const RunDev &rd, const R *__restrict__ tiles, int c, const int g[3])
+__device__ __forceinline__ void gather_J(const RunDev &rd, const SDMD_GLOBAL R *__restrict__ tiles, const int g[3],
+                                         double J[3])
 {
     int pa[3] = {0, 0, 0}, l[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
 #pragma unroll
@@ -33,7 +35,9 @@ __device__ __forceinline__ double gather_J(const RunDev &rd, const R *__restrict
         lo[a] = l[a] <= 2 ? -1 : 0;
         hi[a] = l[a] >= rd.P[a] - 2 ? 1 : 0;
     }
-    double s = 0.0;
+    const long long tsz = rd.tsz;
+    const SDMD_GLOBAL int *pseg = gp(rd.pseg);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int oz = lo[2]; oz <= hi[2]; ++oz)
         for (int oy = lo[1]; oy <= hi[1]; ++oy)
             for (int ox = lo[0]; ox <= hi[0]; ++ox) {
@@ -45,33 +49,60 @@ __device__ __forceinline__ double gather_J(const RunDev &rd, const R *__restrict
                 const int ty = l[1] - oy * rd.P[1] + 2;
                 const int tz = DIM == 3 ? l[2] - oz * rd.P[2] + 2 : 0;
                 const int off = (tz * rd.TA[1] + ty) * rd.TA[0] + tx;
-                for (int sg = rd.pseg[q]; sg < rd.pseg[q + 1]; ++sg)
-                    s += (double)tiles[((long long)sg * 3 + c) * rd.tsz + off];
+                const int e = pseg[q + 1];
+                for (int sg = pseg[q]; sg < e; ++sg) {
+                    const SDMD_GLOBAL R *t = tiles + (long long)sg * 3 * tsz + off;
+                    s0 += (double)t[0];
+                    s1 += (double)t[tsz];
+                    s2 += (double)t[2 * tsz];
+                }
             }
-    return s;
+    J[0] = s0;
+    J[1] = s1;
+    J[2] = s2;
 }
 
 // ------------------------------------------------------------ Yee kernel
-template <int DIM>
+// Yee tile shapes: BLOCK nodes per workgroup, x extent TX chosen per run
+// from the region width (64 for wide regions; 32, 16 or 8 when regions are
+// as small as patches, so that a tile does not straddle mostly empty space).
+template <int DIM, int TX>
 struct YeeTile;
-template <>
-struct YeeTile<2> {
-    static constexpr int X = 64, Y = 4, Z = 1;
+template <int TX>
+struct YeeTile<2, TX> {
+    static constexpr int X = TX, Y = BLOCK / TX, Z = 1;
 };
-template <>
-struct YeeTile<3> {
-    static constexpr int X = 32, Y = 4, Z = 2;
+template <int TX>
+struct YeeTile<3, TX> {
+    static constexpr int X = TX, Y = TX == 32 ? 4 : TX == 16 ? 4 : 8, Z = BLOCK / (TX * Y);
 };
 
-template <int DIM, class T>
+// Binomial current filter (section 3.2): when the run asks for k passes, the
+// workgroup first gathers the raw current on its tile + halo widened by k
+// nodes on every side, then applies the passes in LDS -- a pass smooths each
+// component with the 1-2-1 kernel along x, then y, then z -- so the Ampere
+// step reads filtered J on tile + halo.  A sweep along an axis leaves the
+// outermost layer along that axis stale; after k passes the stale layers
+// are exactly the k-wide margin, never read.
+template <int DIM, bool FILT>
+struct FilterMax {
+    static constexpr int K = FILT ? (DIM == 2 ? 4 : 2) : 0;
+};
+
+template <int DIM, class T, int TXC, bool FILT>
 __global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ runs, const int4 *__restrict__ items,
                                                     int par)
 {
     using R = typename T::real;
-    constexpr int TX = YeeTile<DIM>::X, TY = YeeTile<DIM>::Y, TZ = YeeTile<DIM>::Z;
+    constexpr int TX = YeeTile<DIM, TXC>::X, TY = YeeTile<DIM, TXC>::Y, TZ = YeeTile<DIM, TXC>::Z;
+    static_assert(TX * TY * TZ == BLOCK, "one node per thread");
     constexpr int HX = TX + 1, HY = TY + 1, HZ = DIM == 3 ? TZ + 1 : 1;
     constexpr int HN = HX * HY * HZ;
+    constexpr int KM = FilterMax<DIM, FILT>::K;
+    constexpr int EXS = HX + 2 * KM, EYS = HY + 2 * KM, EZS = DIM == 3 ? HZ + 2 * KM : 1;
+    constexpr int EN = FILT ? EXS * EYS * EZS : 1;
     __shared__ double sE[3][HN];
+    __shared__ double sJ[FILT ? 4 : 1][EN];   // 3 components + one sweep buffer
 
     const int4 it = items[blockIdx.x];
     const RunDev &rd = runs[it.x];
@@ -91,30 +122,83 @@ __global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ r
     const int rs0 = rd.rs[0], rs1 = rd.rs[1], rs2 = DIM == 3 ? rd.rs[2] : 1;
 
     const double dt = rd.dt, dx = rd.d[0], dy = rd.d[1], dz = DIM == 3 ? rd.d[2] : 1.0;
-    const double *Eo[3], *Bo[3];
-    double *En[3], *Bn[3], *Bm[3], *Jr[3];
+    const SDMD_GLOBAL double *Eo[3], *Bo[3];
+    SDMD_GLOBAL double *En[3], *Bn[3], *Bm[3], *Jr[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        Eo[c] = rcomp(rd, region, f_E(par) + c);
-        Bo[c] = rcomp(rd, region, f_B(par) + c);
-        En[c] = rcomp(rd, region, f_E(1 - par) + c);
-        Bn[c] = rcomp(rd, region, f_B(1 - par) + c);
-        Bm[c] = rcomp(rd, region, F_BM + c);
-        Jr[c] = rcomp(rd, region, F_J + c);
+        Eo[c] = gp((const double *)rcomp(rd, region, f_E(par) + c));
+        Bo[c] = gp((const double *)rcomp(rd, region, f_B(par) + c));
+        En[c] = gp(rcomp(rd, region, f_E(1 - par) + c));
+        Bn[c] = gp(rcomp(rd, region, f_B(1 - par) + c));
+        Bm[c] = gp(rcomp(rd, region, F_BM + c));
+        Jr[c] = gp(rcomp(rd, region, F_J + c));
     }
-    const R *tiles = (const R *)rd.tiles;
+    const SDMD_GLOBAL R *tiles = gp((const R *)rd.tiles);
     const long long sx = 1, sy = rd.ra[0], sz = (long long)rd.ra[0] * rd.ra[1];
 
-    // phase 1: J gather and Ampere on tile + high halo
+    int kf = 0;   // filter passes of this run
+    if constexpr (FILT) {
+        kf = min(max(rd.filter, 0), KM);
+        const int bx = HX + 2 * kf, by = HY + 2 * kf, bz = DIM == 3 ? HZ + 2 * kf : 1;
+        const int nb = bx * by * bz;
+        // raw current on the widened box
+        for (int h = tid; h < nb; h += BLOCK) {
+            const int ex = h % bx, ey = (h / bx) % by, ez = h / (bx * by);
+            const int g[3] = {wrapi(ro[0] + ox - kf + ex, rd.n[0]), wrapi(ro[1] + oy - kf + ey, rd.n[1]),
+                              DIM == 3 ? wrapi(ro[2] + oz - kf + ez, rd.n[2]) : 0};
+            double J[3];
+            gather_J<DIM, R>(rd, tiles, g, J);
+            const int e = (ez * EYS + ey) * EXS + ex;
+            sJ[0][e] = J[0];
+            sJ[1][e] = J[1];
+            sJ[2][e] = J[2];
+        }
+        __syncthreads();
+        for (int c = 0; c < 3; ++c) {
+            double *a = sJ[c], *b = sJ[3];
+            for (int pass = 0; pass < kf; ++pass)
+                for (int axis = 0; axis < DIM; ++axis) {
+                    const int st = axis == 0 ? 1 : axis == 1 ? EXS : EXS * EYS;
+                    const int ext = axis == 0 ? bx : axis == 1 ? by : bz;
+                    for (int h = tid; h < nb; h += BLOCK) {
+                        const int ex = h % bx, ey = (h / bx) % by, ez = h / (bx * by);
+                        const int co = axis == 0 ? ex : axis == 1 ? ey : ez;
+                        if (co < 1 || co > ext - 2) continue;
+                        const int e = (ez * EYS + ey) * EXS + ex;
+                        b[e] = (a[e - st] + 2.0 * a[e] + a[e + st]) * 0.25;
+                    }
+                    __syncthreads();
+                    double *t = a;
+                    a = b;
+                    b = t;
+                }
+            if (a != sJ[c]) {
+                for (int h = tid; h < nb; h += BLOCK) {
+                    const int ex = h % bx, ey = (h / bx) % by, ez = h / (bx * by);
+                    const int e = (ez * EYS + ey) * EXS + ex;
+                    sJ[c][e] = a[e];
+                }
+                __syncthreads();
+            }
+        }
+    }
+
+    // phase 1: J (gathered, or filtered from LDS) and Ampere on tile + high halo
     for (int h = tid; h < HN; h += BLOCK) {
         const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
         const int li = ox + hx, lj = oy + hy, lk = oz + hz;
         if (li > rs0 || lj > rs1 || (DIM == 3 && lk > rs2)) continue;
-        const int g[3] = {wrapi(ro[0] + li, rd.n[0]), wrapi(ro[1] + lj, rd.n[1]),
-                          DIM == 3 ? wrapi(ro[2] + lk, rd.n[2]) : 0};
         double J[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) J[c] = gather_J<DIM, R>(rd, tiles, c, g);
+        if constexpr (FILT) {
+            const int e = ((DIM == 3 ? hz + kf : 0) * EYS + hy + kf) * EXS + hx + kf;
+            J[0] = sJ[0][e];
+            J[1] = sJ[1][e];
+            J[2] = sJ[2][e];
+        } else {
+            const int g[3] = {wrapi(ro[0] + li, rd.n[0]), wrapi(ro[1] + lj, rd.n[1]),
+                              DIM == 3 ? wrapi(ro[2] + lk, rd.n[2]) : 0};
+            gather_J<DIM, R>(rd, tiles, g, J);
+        }
         const long long p = rindex(rd, li, lj, DIM == 3 ? lk : 0);
         double e0, e1, e2;
         if constexpr (DIM == 2) {
@@ -338,14 +422,46 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
         return hipGetLastError();                                                                     \
     }
 
-hipError_t launch_yee(int dims, bool split, const RunDev *runs, const int4 *items, int n_items, int par,
-                      hipStream_t s)
+#define YEE_CASE(D, TT, X, FL)                                                                        \
+    if (dims == D && split == TT::split && tx == X && filt == FL) {                                   \
+        yee_kernel<D, TT, X, FL><<<n_items, BLOCK, 0, s>>>(runs, items, par);                         \
+        return hipGetLastError();                                                                     \
+    }
+
+int yee_tile_x(int dims, int rs0, bool filt)
+{
+    if (dims == 3 && filt) return 8;   // the widened box of the filter fits LDS at 8 x 8 x 4
+    const int top = dims == 2 ? 64 : 32;
+    for (int x = top; x > 8; x /= 2)
+        if (rs0 >= x) return x;
+    return 8;
+}
+
+void yee_tile_shape(int dims, int tx, int shape[3])
+{
+    shape[0] = tx;
+    if (dims == 2) {
+        shape[1] = BLOCK / tx;
+        shape[2] = 1;
+    } else {
+        shape[1] = tx >= 16 ? 4 : 8;
+        shape[2] = BLOCK / (tx * shape[1]);
+    }
+}
+
+hipError_t launch_yee(int dims, bool split, int tx, bool filt, const RunDev *runs, const int4 *items, int n_items,
+                      int par, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
-    DT_CASE(2, F32S, yee_kernel, runs, items, par)
-    DT_CASE(2, FP64, yee_kernel, runs, items, par)
-    DT_CASE(3, F32S, yee_kernel, runs, items, par)
-    DT_CASE(3, FP64, yee_kernel, runs, items, par)
+    YEE_CASE(2, F32S, 64, false) YEE_CASE(2, F32S, 32, false) YEE_CASE(2, F32S, 16, false)
+    YEE_CASE(2, F32S, 8, false) YEE_CASE(2, FP64, 64, false) YEE_CASE(2, FP64, 32, false)
+    YEE_CASE(2, FP64, 16, false) YEE_CASE(2, FP64, 8, false)
+    YEE_CASE(3, F32S, 32, false) YEE_CASE(3, F32S, 16, false) YEE_CASE(3, F32S, 8, false)
+    YEE_CASE(3, FP64, 32, false) YEE_CASE(3, FP64, 16, false) YEE_CASE(3, FP64, 8, false)
+    YEE_CASE(2, F32S, 64, true) YEE_CASE(2, F32S, 32, true) YEE_CASE(2, F32S, 16, true)
+    YEE_CASE(2, F32S, 8, true) YEE_CASE(2, FP64, 64, true) YEE_CASE(2, FP64, 32, true)
+    YEE_CASE(2, FP64, 16, true) YEE_CASE(2, FP64, 8, true)
+    YEE_CASE(3, F32S, 8, true) YEE_CASE(3, FP64, 8, true)
     return hipErrorInvalidValue;
 }
 

@@ -408,15 +408,15 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
         const int c = idx / WS, rem = idx - c * WS;
         const int wx = rem % W0, tq = rem / W0, wy = tq % W1, wz = tq / W1;
         const int comp = c < 3 ? f_E(par) + c : F_BM + (c - 3);
-        const double *A = rcomp(rd, region, comp);
+        const SDMD_GLOBAL double *A = gp((const double *)rcomp(rd, region, comp));
         s_win[idx] = (R)A[rindex(rd, o[0] - 1 + wx, o[1] - 1 + wy, DIM == 3 ? o[2] - 1 + wz : 0)];
     }
     for (int idx = tid; idx < 3 * TS; idx += BLOCK) s_tile[idx] = 0.0;
     __syncthreads();
 
-    const long long seg0 = rd.sseg[sg];
-    const int cap = rd.sseg[sg + 1] - rd.sseg[sg];
-    int n = rd.scnt[sg];
+    const long long seg0 = gp(rd.sseg)[sg];
+    const int cap = gp(rd.sseg)[sg + 1] - (int)seg0;
+    int n = gp(rd.scnt)[sg];
     n = n < cap ? n : cap;
     int err = 0;
     int stay = 0, left = 0;   // stayers compacted / leavers written so far (uniform)
@@ -459,7 +459,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
             // the patch's own leaver region: stayers + leavers <= n <= capacity
             const long long slot = seg0 + lb + __popcll(ml & lt);
             store_part<DIM, T>(rd.lv, slot, pt, true);
-            rd.lpatch[slot] = dest;
+            gp(rd.lpatch)[slot] = dest;
         }
         stay += tot;
         left += ltot;
@@ -470,7 +470,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     const int nsp = sg == rd.pseg[q] ? min(rd.ctl->nspill, rd.n_total) : 0;
     for (int base = 0; base < nsp; base += BLOCK) {
         const int i = base + tid;
-        const bool mine = i < nsp && rd.spatch[i] == q;
+        const bool mine = i < nsp && gp(rd.spatch)[i] == q;
         Part<T> pt;
         int dest = q;
         if (mine) {
@@ -487,7 +487,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
             const int slot = lbase + __popcll(ml & lt);
             if (slot < rd.n_total) {
                 store_part<DIM, T>(rd.lo, slot, pt, true);
-                rd.lopatch[slot] = dest;
+                gp(rd.lopatch)[slot] = dest;
             } else {
                 err |= ERR_CAPACITY;
             }
@@ -496,12 +496,12 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
 
     if (err) atomicOr(&rd.ctl->err, err);
     if (tid == 0) {
-        rd.scnt[sg] = stay;
-        rd.nlv[sg] = left;
+        gp(rd.scnt)[sg] = stay;
+        gp(rd.nlv)[sg] = left;
     }
     __syncthreads();
     // flush the tile in the tile precision (transfer (i) reads it)
-    R *dst = (R *)rd.tiles + (long long)sg * 3 * TS;
+    SDMD_GLOBAL R *dst = gp((R *)rd.tiles) + (long long)sg * 3 * TS;
     for (int idx = tid; idx < 3 * TS; idx += BLOCK) dst[idx] = (R)s_tile[idx];
 }
 

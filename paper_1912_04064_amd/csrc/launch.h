@@ -13,9 +13,13 @@ namespace sdmd {
 hipError_t launch_push(int dims, bool split, int px, int pc, const RunDev *runs, const int2 *items, int n_items,
                        int par, hipStream_t s);
 
-// transfer (i) + Maxwell: items (run, region, tile, first-item-of-run flag)
-hipError_t launch_yee(int dims, bool split, const RunDev *runs, const int4 *items, int n_items, int par,
-                      hipStream_t s);
+// transfer (i) + current filter + Maxwell: items (run, region, tile,
+// first-item-of-run flag); tx: x extent of the tile, from
+// yee_tile_x(dims, region width, filter on); filt: runs with filter passes
+int yee_tile_x(int dims, int rs0, bool filt);
+void yee_tile_shape(int dims, int tx, int shape[3]);
+hipError_t launch_yee(int dims, bool split, int tx, bool filt, const RunDev *runs, const int4 *items, int n_items,
+                      int par, hipStream_t s);
 
 // ghost synchronisation of the new fields + insertion of the leavers:
 // items (run, kind, a, b); kind 0 ghost chunk starting at a, kind 1 insert

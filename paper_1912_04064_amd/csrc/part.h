@@ -20,12 +20,12 @@ __device__ __forceinline__ void load_part(const Store &s, long long i, Part<T> &
 {
     using R = typename T::real;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) p.pos[a] = ((const R *)s.pos[a])[i];
-    if constexpr (T::split) p.cell = s.cell[i];
+    for (int a = 0; a < DIM; ++a) p.pos[a] = gp((const R *)s.pos[a])[i];
+    if constexpr (T::split) p.cell = gp((const uint16_t *)s.cell)[i];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) p.u[a] = ((const R *)s.u[a])[i];
-    p.w = ((const R *)s.w)[i];
-    if (s.id) p.id = s.id[i];
+    for (int a = 0; a < 3; ++a) p.u[a] = gp((const R *)s.u[a])[i];
+    p.w = gp((const R *)s.w)[i];
+    if (s.id) p.id = gp((const uint32_t *)s.id)[i];
 }
 
 template <int DIM, class T>
@@ -33,13 +33,13 @@ __device__ __forceinline__ void store_part(const Store &s, long long i, const Pa
 {
     using R = typename T::real;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) ((R *)s.pos[a])[i] = p.pos[a];
-    if constexpr (T::split) s.cell[i] = (uint16_t)p.cell;
+    for (int a = 0; a < DIM; ++a) gp((R *)s.pos[a])[i] = p.pos[a];
+    if constexpr (T::split) gp(s.cell)[i] = (uint16_t)p.cell;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) ((R *)s.u[a])[i] = p.u[a];
+    for (int a = 0; a < 3; ++a) gp((R *)s.u[a])[i] = p.u[a];
     if (full) {
-        ((R *)s.w)[i] = p.w;
-        if (s.id) s.id[i] = p.id;
+        gp((R *)s.w)[i] = p.w;
+        if (s.id) gp(s.id)[i] = p.id;
     }
 }
 

@@ -106,6 +106,7 @@ struct RunDev {
     int ins_segs;        // segments per leaver-insert workgroup
     int post_blocks;     // post-kernel workgroups of this run per step
     int ghosts;          // ghost nodes per region
+    int filter;          // binomial current filter passes (0 = off)
     double d[3], L[3];
     double dt, q, m;
     double qmh;          // (q/m) dt/2
@@ -129,6 +130,24 @@ struct RunDev {
 };
 
 // ---------------------------------------------------------------- helpers
+// Device pointers read from memory (the fields of RunDev and Store) are
+// generic to the compiler, which then emits flat memory instructions.  A flat
+// instruction also counts against the LDS wait counter, so every wait for an
+// LDS read would also wait for outstanding HBM loads, and a prefetch could
+// never stay in flight across LDS work.  Hot HBM accesses go through global
+// (address space 1) pointers instead.
+#define SDMD_GLOBAL __attribute__((address_space(1)))
+template <class V>
+__device__ __forceinline__ SDMD_GLOBAL V *gp(V *p)
+{
+    return (SDMD_GLOBAL V *)p;
+}
+template <class V>
+__device__ __forceinline__ const SDMD_GLOBAL V *gp(const V *p)
+{
+    return (const SDMD_GLOBAL V *)p;
+}
+
 __device__ __forceinline__ long long rindex(const RunDev &r, int li, int lj, int lk)
 {
     const int gz = (r.dims == 3) ? GH : 0;

@@ -57,6 +57,7 @@ class Workload:
     q: float = -1.0
     m: float = 1.0
     seed: int = 0
+    filter: int = 0               # binomial current filter passes (0 = off)
 
     @property
     def n_particles(self) -> int:

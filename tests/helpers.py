@@ -6,7 +6,7 @@ import oracle as O
 
 def oracle_state(wl):
     """Oracle Grid, fields (initial half step applied) and particles of a workload."""
-    g = O.Grid(wl.dims, wl.n, wl.d, wl.dt, q=wl.q, m=wl.m, patch=wl.patch, nreg=wl.nreg)
+    g = O.Grid(wl.dims, wl.n, wl.d, wl.dt, q=wl.q, m=wl.m, patch=wl.patch, nreg=wl.nreg, filter=wl.filter)
     F = g.zeros_fields()
     if wl.E0 is not None:
         F[0:3] = wl.E0

@@ -143,6 +143,45 @@ def test_regions_one_vs_four_bitwise():
     assert np.abs(out[1]["E"] - F[0:3]).max() < 1e-12 * np.abs(F[0:3]).max()
 
 
+def _same_run(a, b, tol):
+    """Two GPU runs of one input agree to round-off.  The FP64 LDS atomics
+    of the current tiles add contributions from different wavefronts in a
+    timing-dependent order, so J, and through it everything else, can
+    differ in the last bits between any two runs."""
+    for k in ("E", "BH", "Bm", "J"):
+        nrm = np.linalg.norm(a[k])
+        if nrm > 0:
+            assert np.linalg.norm(a[k] - b[k]) <= tol * nrm, k
+        else:
+            assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32s"])
+@pytest.mark.parametrize("dims", [2, 3])
+def test_sdsd_regions_equal_patches(dims, precision):
+    """SDSD as the special case of SDMD where both decompositions coincide
+    (one region per patch, section 2.2): the same per-node arithmetic as one
+    region, so results agree to round-off (the fields-only case is bitwise,
+    test_regions_one_vs_four_bitwise)."""
+    say(f"case: sdsd dims={dims} {precision}")
+    if dims == 2:
+        wl0 = WL.thermal_2d(n=(64, 32), ppc=4, vth=0.05, patch=(8, 8), precision=precision)
+        nregs = [(1, 1), (8, 4), (2, 4)]
+    else:
+        wl0 = WL.cylinder_3d(n=(16, 16, 16), radius=3.0, ppc_bg=2, ppc_cyl=16, patch=(4, 4, 4), precision=precision)
+        nregs = [(1, 1, 1), (4, 4, 4)]
+    import dataclasses
+    out = [gpu_run(dataclasses.replace(wl0, nreg=nreg), 12) for nreg in nregs]
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for F, parts, _ in out[1:]:
+        _same_run(out[0][0], F, tol)
+        assert np.array_equal(out[0][1]["id"], parts["id"])
+        L = np.array(wl0.n) * np.array(wl0.d)
+        for a, k in enumerate(("x", "y", "z")[:dims]):
+            d = np.abs(out[0][1][k] - parts[k])
+            assert np.minimum(d, L[a] - d).max() <= (1e-12 if precision == "fp64" else 1e-4), k
+
+
 # ---------------------------------------------------------------- full steps
 @pytest.mark.parametrize("graph", [True, False])
 def test_fp64_one_step_matches_oracle(graph):
@@ -244,6 +283,77 @@ def test_continuity_and_gauss_on_gpu_data():
     divE = (E[0] - np.roll(E[0], 1, axis=2)) / dx + (E[1] - np.roll(E[1], 1, axis=1)) / dy
     # E starts at zero, so div E^1 = rho^1 - rho^0 exactly up to round-off
     assert np.abs(divE - (r1 - r0)).max() < 2e-6 * np.abs(r0).max()
+
+
+@pytest.mark.parametrize("prec,tol1", [("fp64", 1e-12), ("fp32s", 1e-5)])
+def test_filtered_current_matches_oracle(prec, tol1):
+    """Two-pass binomial current filter fused into the field kernel: 1 and
+    40 steps against the oracle's global filter."""
+    say(f"case: filter 2 thermal {prec}")
+    import dataclasses
+    wl = dataclasses.replace(WL.thermal_2d(n=(64, 48), ppc=4, vth=0.05, patch=(8, 8), nreg=(2, 3), precision=prec),
+                             filter=2)
+    g, F, P = oracle_state(wl)
+    O.step_sdsd(g, F, P)
+    Fg1, _, _ = gpu_run(wl, 1, track_ids=False)
+    e1 = max_family_error(Fg1, {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]})
+    for _ in range(39):
+        O.step_sdsd(g, F, P)
+    Fg, _, _ = gpu_run(wl, 40, track_ids=False)
+    e40 = max_family_error(Fg, {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]})
+    say(f"{prec}: 1-step {e1}; 40-step {e40}")
+    assert max(e1.values()) < tol1
+    assert max(e40.values()) < (1e-9 if prec == "fp64" else 1e-3)
+
+
+@pytest.mark.parametrize("dims,passes", [(2, 1), (2, 2), (2, 4), (3, 1), (3, 2)])
+def test_filter_regions_and_patches(dims, passes):
+    """The filter reads a widened box of raw current, so the result does not
+    depend on where region or tile edges fall: one region, several regions
+    and one region per patch agree (to the round-off of the atomics)."""
+    say(f"case: filter regions dims={dims} passes={passes}")
+    import dataclasses
+    if dims == 2:
+        wl0 = WL.thermal_2d(n=(64, 32), ppc=4, vth=0.05, patch=(8, 8), precision="fp32s")
+        nregs = [(1, 1), (4, 2), (8, 4)]
+    else:
+        wl0 = WL.cylinder_3d(n=(16, 16, 8), radius=3.0, ppc_bg=2, ppc_cyl=16, patch=(4, 4, 4), precision="fp64")
+        nregs = [(1, 1, 1), (2, 2, 1), (4, 4, 2)]
+    out = [gpu_run(dataclasses.replace(wl0, nreg=nr, filter=passes), 6, track_ids=False)[0] for nr in nregs]
+    tol = 1e-12 if wl0.precision == "fp64" else 1e-5
+    for F in out[1:]:
+        _same_run(out[0], F, tol)
+    # against the oracle's global filter after one step
+    g, Fo, P = oracle_state(dataclasses.replace(wl0, filter=passes))
+    O.step_sdsd(g, Fo, P)
+    F1 = gpu_run(dataclasses.replace(wl0, nreg=nregs[-1], filter=passes), 1, track_ids=False)[0]
+    e1 = max_family_error(F1, {"E": Fo[0:3], "Bm": Fo[6:9], "BH": Fo[3:6], "J": Fo[9:12]})
+    say(f"filter {passes} passes, regions {nregs[-1]}: 1-step {e1}")
+    assert max(e1.values()) < (1e-12 if wl0.precision == "fp64" else 1e-5)
+    ref = gpu_run(dataclasses.replace(wl0, filter=0), 6, track_ids=False)[0]
+    assert np.linalg.norm(ref["J"] - out[0]["J"]) > 1e-3 * np.linalg.norm(ref["J"])
+
+
+def test_gauss_with_filter_on_gpu_data():
+    """With a filtered current, div E - F(rho) is conserved, F the same
+    filter applied to rho (the oracle's filter on the GPU's rho)."""
+    say("case: gauss with filter fp64")
+    import dataclasses
+    wl = dataclasses.replace(WL.thermal_2d(n=(64, 64), ppc=4, vth=0.1, precision="fp64"), filter=2)
+    g = O.Grid(2, wl.n, wl.d, wl.dt, patch=wl.patch)
+    with B.Context([wl]) as ctx:
+        r0 = ctx.fields(0, B.F_RHO)[0]
+        ctx.step(10)
+        F = ctx.fields(0, B.F_RHO | B.F_E)
+    E, r1 = F[0:3], F[3]
+    dx, dy = wl.d
+    divE = (E[0] - np.roll(E[0], 1, axis=2)) / dx + (E[1] - np.roll(E[1], 1, axis=1)) / dy
+    fr = O.filter_arrays(g, np.stack([r1 - r0]), 2)[0]
+    scale = np.abs(r0).max()
+    say(f"gauss residual with filtered rho: {np.abs(divE - fr).max() / scale:.3e}; "
+        f"unfiltered: {np.abs(divE - (r1 - r0)).max() / scale:.3e}")
+    assert np.abs(divE - fr).max() < 1e-12 * scale
+    assert np.abs(divE - (r1 - r0)).max() > 1e-6 * scale
 
 
 def test_converging_flow_spills_and_relayouts():

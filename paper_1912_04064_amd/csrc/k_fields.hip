@@ -41,9 +41,9 @@ __device__ __forceinline__ void gather_J(const RunDev &rd, const SDMD_GLOBAL R *
     for (int oz = lo[2]; oz <= hi[2]; ++oz)
         for (int oy = lo[1]; oy <= hi[1]; ++oy)
             for (int ox = lo[0]; ox <= hi[0]; ++ox) {
-                const int qx = wrapi(pa[0] + ox, rd.np[0]);
-                const int qy = wrapi(pa[1] + oy, rd.np[1]);
-                const int qz = DIM == 3 ? wrapi(pa[2] + oz, rd.np[2]) : 0;
+                const int qx = wrap1(pa[0] + ox, rd.np[0]);
+                const int qy = wrap1(pa[1] + oy, rd.np[1]);
+                const int qz = DIM == 3 ? wrap1(pa[2] + oz, rd.np[2]) : 0;
                 const int q = qx + rd.np[0] * (qy + rd.np[1] * qz);
                 const int tx = l[0] - ox * rd.P[0] + 2;
                 const int ty = l[1] - oy * rd.P[1] + 2;
@@ -144,8 +144,8 @@ __global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ r
         // raw current on the widened box
         for (int h = tid; h < nb; h += BLOCK) {
             const int ex = h % bx, ey = (h / bx) % by, ez = h / (bx * by);
-            const int g[3] = {wrapi(ro[0] + ox - kf + ex, rd.n[0]), wrapi(ro[1] + oy - kf + ey, rd.n[1]),
-                              DIM == 3 ? wrapi(ro[2] + oz - kf + ez, rd.n[2]) : 0};
+            const int g[3] = {wrap1(ro[0] + ox - kf + ex, rd.n[0]), wrap1(ro[1] + oy - kf + ey, rd.n[1]),
+                              DIM == 3 ? wrap1(ro[2] + oz - kf + ez, rd.n[2]) : 0};
             double J[3];
             gather_J<DIM, R>(rd, tiles, g, J);
             const int e = (ez * EYS + ey) * EXS + ex;
@@ -195,8 +195,8 @@ __global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ r
             J[1] = sJ[1][e];
             J[2] = sJ[2][e];
         } else {
-            const int g[3] = {wrapi(ro[0] + li, rd.n[0]), wrapi(ro[1] + lj, rd.n[1]),
-                              DIM == 3 ? wrapi(ro[2] + lk, rd.n[2]) : 0};
+            const int g[3] = {wrap1(ro[0] + li, rd.n[0]), wrap1(ro[1] + lj, rd.n[1]),
+                              DIM == 3 ? wrap1(ro[2] + lk, rd.n[2]) : 0};
             gather_J<DIM, R>(rd, tiles, g, J);
         }
         const long long p = rindex(rd, li, lj, DIM == 3 ? lk : 0);
@@ -310,8 +310,8 @@ __device__ __forceinline__ void ghost_copy(const RunDev &rd, int gk, const int *
     int li, lj, lk;
     ghost_coords(rd, gk - region * rd.ghosts, li, lj, lk);
     const int rr[3] = {region % rd.nreg[0], (region / rd.nreg[0]) % rd.nreg[1], region / (rd.nreg[0] * rd.nreg[1])};
-    const int g[3] = {wrapi(rr[0] * rd.rs[0] + li, rd.n[0]), wrapi(rr[1] * rd.rs[1] + lj, rd.n[1]),
-                      rd.dims == 3 ? wrapi(rr[2] * rd.rs[2] + lk, rd.n[2]) : 0};
+    const int g[3] = {wrap1(rr[0] * rd.rs[0] + li, rd.n[0]), wrap1(rr[1] * rd.rs[1] + lj, rd.n[1]),
+                      rd.dims == 3 ? wrap1(rr[2] * rd.rs[2] + lk, rd.n[2]) : 0};
     const int sr[3] = {g[0] / rd.rs[0], g[1] / rd.rs[1], rd.dims == 3 ? g[2] / rd.rs[2] : 0};
     const int src = sr[0] + rd.nreg[0] * (sr[1] + rd.nreg[1] * sr[2]);
     const long long ps = rindex(rd, g[0] - sr[0] * rd.rs[0], g[1] - sr[1] * rd.rs[1],

@@ -476,8 +476,8 @@ __device__ __forceinline__ void rho_one(const RunDev &rd, const Store &s, long l
     for (int k = 0; k < nk; ++k)
         for (int j = 0; j < 3; ++j)
             for (int ii = 0; ii < 3; ++ii) {
-                const int gi = wrapi(base[0] + ii, rd.n[0]), gj = wrapi(base[1] + j, rd.n[1]);
-                const int gk = DIM == 3 ? wrapi(base[2] + k, rd.n[2]) : 0;
+                const int gi = wrap1(base[0] + ii, rd.n[0]), gj = wrap1(base[1] + j, rd.n[1]);
+                const int gk = DIM == 3 ? wrap1(base[2] + k, rd.n[2]) : 0;
                 const double v = qw * wt[0][ii] * wt[1][j] * (DIM == 3 ? wt[2][k] : 1.0);
                 atomicAdd(&rho[gi + (long long)rd.n[0] * (gj + (long long)rd.n[1] * gk)], v);
             }

@@ -159,10 +159,14 @@ __device__ __forceinline__ double *rcomp(const RunDev &r, int region, int comp)
     return r.fld + ((long long)region * F_NCOMP + comp) * r.rsize;
 }
 
-__device__ __forceinline__ int wrapi(int i, int n)
+// i mod n for i in [-n, 2n).  Every caller steps at most a few nodes
+// (the 5-node deposition frame, the ghost layers, the filter margin: <= 4)
+// outside [0, n), and n >= 4 because a patch holds at least 4 cells per
+// axis; two compares replace an integer division.
+__device__ __forceinline__ int wrap1(int i, int n)
 {
-    i %= n;
-    return i < 0 ? i + n : i;
+    i = i < 0 ? i + n : i;
+    return i >= n ? i - n : i;
 }
 
 // quadratic B-spline weights at nodes -1, 0, +1 for offset d in [-1/2, 1/2]

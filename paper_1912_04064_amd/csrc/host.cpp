@@ -712,27 +712,12 @@ static int rebuild_items(pic_ctx *c)
             fc = &c->fcls.back();
         }
         const RunDev &d = r.rd;
-        // push items, one per segment slot: XCD-aware order -- workgroup i
-        // runs on XCD i % 8, so give each XCD a contiguous band of segments
-        // (neighbouring patches share window halos in that XCD's L2)
-        const int np = d.seg_max;
-        const int band = (np + 7) / 8;
-        std::vector<char> seen(np, 0);
-        size_t base = pc->h.size();
-        pc->h.resize(base + np);
-        int k = 0;
-        for (int i = 0; k < np; ++i) {
-            const int xcd = i % 8, j = i / 8;
-            const int q = xcd * band + j;
-            if (j >= band || q >= np) {
-                if (i > 16 * np + 64) break;
-                continue;
-            }
-            pc->h[base + k++] = make_int2(slot, q);
-            seen[q] = 1;
-        }
-        for (int q = 0; q < np && k < np; ++q)
-            if (!seen[q]) pc->h[base + k++] = make_int2(slot, q);
+        // push items: the run's block of (run, l) items, l = 0 .. seg_max
+        // rounded up to a multiple of 8, starting at a multiple of 8 so that
+        // item l runs on XCD l % 8; the kernel maps l to a segment from the
+        // live segment count (see push_kernel)
+        const int npad = (d.seg_max + 7) / 8 * 8;
+        for (int l = 0; l < npad; ++l) pc->h.push_back(make_int2(slot, l));
         // yee items
         int shape[3];
         yee_tile_shape(r.dims, ytx, shape);

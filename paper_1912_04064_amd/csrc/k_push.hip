@@ -420,10 +420,18 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     __shared__ double s_tile[3 * TN];
     __shared__ int s_wsum[2][NW], s_lsum[2][NW];
 
+    // Work item l of a run runs on XCD l % 8 (workgroups are dealt to the
+    // 8 XCDs in turn, and every run's items start at a multiple of 8).  The
+    // live segments are cut into 8 contiguous bands, one per XCD: each
+    // XCD's L2 sees neighbouring patches (shared window halos), and the
+    // live work is spread evenly however many slots are in use.
     const int2 item = items[blockIdx.x];
     const RunDev &rd = runs[item.x];
-    const int sg = item.y;               // segment
-    if (sg >= rd.ctl->nseg || rd.ctl->remaining == 0) return;   // slot unused, or run finished
+    const int nseg = rd.ctl->nseg;
+    const int band = (nseg + 7) >> 3;
+    const int jb = item.y >> 3;
+    const int sg = (item.y & 7) * band + jb;   // segment
+    if (jb >= band || sg >= nseg || rd.ctl->remaining == 0) return;   // slot unused, or run finished
     const int q = rd.spat[sg];           // its patch
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 

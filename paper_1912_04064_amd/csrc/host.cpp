@@ -280,7 +280,7 @@ static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::st
     size_t b = 0;
     b += align256((size_t)L.n_regions * F_NCOMP * L.rsize * 8);
     b += align256((size_t)L.seg_max * 3 * L.tsz * rsz);
-    b += 5 * align256((size_t)(L.n_patch + 1) * 4) + 6 * align256((size_t)(L.seg_max + 1) * 4);
+    b += 5 * align256((size_t)(L.n_patch + 1) * 4) + 7 * align256((size_t)(L.seg_max + 1) * 4);
     b += 2 * (size_t)L.cap_total * per + align256((size_t)L.cap_total * 4);
     b += 2 * (size_t)std::max<long long>(L.n_total, 1) * (per + 4);
     b += 64 * 256;   // per-array rounding and the control block
@@ -566,7 +566,8 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     d.spatch = (int *)run_alloc(c, r, (size_t)std::max<long long>(L.n_total, 1) * 4);
     d.lopatch = (int *)run_alloc(c, r, (size_t)std::max<long long>(L.n_total, 1) * 4);
     d.nlv = (int *)run_alloc(c, r, sb);
-    ok = ok && d.lpatch && d.spatch && d.lopatch && d.nlv;
+    d.tflag = (int *)run_alloc(c, r, sb);
+    ok = ok && d.lpatch && d.spatch && d.lopatch && d.nlv && d.tflag;
     r.bytes = 0;
     for (auto &b : r.bufs) r.bytes += b.bytes;
     if (!ok) {
@@ -581,6 +582,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     HIPCHK(c, hipMemsetAsync(d.sseg, 0, sb, s));
     HIPCHK(c, hipMemsetAsync(d.scnt, 0, sb, s));
     HIPCHK(c, hipMemsetAsync(d.nlv, 0, sb, s));
+    HIPCHK(c, hipMemsetAsync(d.tflag, 0, sb, s));
     HIPCHK(c, hipMemsetAsync(d.ctl, 0, sizeof(Ctl), s));
     {
         Ctl init;

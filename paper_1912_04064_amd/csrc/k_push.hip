@@ -416,9 +416,13 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     constexpr int WN = (PC + 3) * (PC + 3) * (DIM == 3 ? PC + 3 : 1);
     constexpr int TN = (PC + 5) * (PC + 5) * (DIM == 3 ? PC + 5 : 1);
     constexpr int NW = BLOCK / 64;
+    constexpr int SPC = 1024;                          // spill entries scanned per round
+    constexpr int SPK = (SPC + BLOCK - 1) / BLOCK;
     __shared__ R s_win[6 * WN];
     __shared__ double s_tile[3 * TN];
     __shared__ int s_wsum[2][NW], s_lsum[2][NW];
+    __shared__ int s_sl[SPC];                          // this patch's parked particles found in a round
+    __shared__ int s_ns;
 
     // Work item l of a run runs on XCD l % 8 (workgroups are dealt to the
     // 8 XCDs in turn, and every run's items start at a multiple of 8).  The
@@ -445,6 +449,30 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     const int WS = W0 * W1 * W2;
     const int TS = (P[0] + 5) * (P[1] + 5) * (DIM == 3 ? P[2] + 5 : 1);
 
+    const SDMD_GLOBAL int *sseg = gp(rd.sseg);
+    const long long seg0 = sseg[sg];
+    const int cap = sseg[sg + 1] - (int)seg0;
+    int n = gp(rd.scnt)[sg];
+    n = n < cap ? n : cap;
+    // parked particles are pushed by the patch's first segment
+    const int nsp = sg == gp(rd.pseg)[q] ? min(rd.ctl->nspill, rd.n_total) : 0;
+    SDMD_GLOBAL int *tflag = gp(rd.tflag);
+    if (n == 0 && nsp == 0) {
+        // nothing to push (a vacuum patch): no window, no tile work; the
+        // tile in HBM is cleared only if an earlier step left current in it
+        const int dirty = tflag[sg];
+        if (dirty) {
+            SDMD_GLOBAL R *dst = gp((R *)rd.tiles) + (long long)sg * 3 * TS;
+            for (int idx = tid; idx < 3 * TS; idx += BLOCK) dst[idx] = R(0);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            tflag[sg] = 0;
+            gp(rd.nlv)[sg] = 0;
+        }
+        return;
+    }
+
     // transfer (ii): region E^n, Bm^n -> LDS window
     for (int idx = tid; idx < 6 * WS; idx += BLOCK) {
         const int c = idx / WS, rem = idx - c * WS;
@@ -456,10 +484,6 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     for (int idx = tid; idx < 3 * TS; idx += BLOCK) s_tile[idx] = 0.0;
     __syncthreads();
 
-    const long long seg0 = gp(rd.sseg)[sg];
-    const int cap = gp(rd.sseg)[sg + 1] - (int)seg0;
-    int n = gp(rd.scnt)[sg];
-    n = n < cap ? n : cap;
     int err = 0;
     int stay = 0, left = 0;   // stayers compacted / leavers written so far (uniform)
     int chunk = 0;
@@ -508,32 +532,57 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     }
 
     // particles parked in the spill store that belong to this patch re-enter
-    // through the overflow leaver store (pushed by the patch's first segment)
-    const int nsp = sg == rd.pseg[q] ? min(rd.ctl->nspill, rd.n_total) : 0;
-    for (int base = 0; base < nsp; base += BLOCK) {
-        const int i = base + tid;
-        const bool mine = i < nsp && gp(rd.spatch)[i] == q;
-        Part<T> pt;
-        int dest = q;
-        if (mine) {
-            load_part<DIM, T>(rd.sp, i, pt);
-            dest = push_one<DIM, T, PX>(rd, s_win, s_tile, p0, P, pt, err);
+    // through the overflow leaver store.  The spill store is scanned in
+    // rounds of SPC entries, all loads of a round in flight at once; the
+    // round's matches are listed in LDS and pushed.
+    for (int c0 = 0; c0 < nsp; c0 += SPC) {
+        if (tid == 0) s_ns = 0;
+        __syncthreads();
+        int pv[SPK];
+#pragma unroll
+        for (int k = 0; k < SPK; ++k) {
+            const int r = k * BLOCK + tid, i = c0 + r;
+            pv[k] = (r < SPC && i < nsp) ? gp(rd.spatch)[i] : -1;
         }
-        const unsigned long long ml = __ballot(mine);
-        int lbase = 0;
-        if (ml) {
-            if (lane == 0) lbase = atomicAdd(&rd.ctl->nleave, __popcll(ml));
-            lbase = __shfl(lbase, 0);
+#pragma unroll
+        for (int k = 0; k < SPK; ++k) {
+            const bool mine = pv[k] == q;
+            const unsigned long long mm = __ballot(mine);
+            int wb = 0;
+            if (mm) {
+                if (lane == 0) wb = atomicAdd(&s_ns, __popcll(mm));
+                wb = __shfl(wb, 0);
+            }
+            if (mine) s_sl[wb + __popcll(mm & lt)] = c0 + k * BLOCK + tid;
         }
-        if (mine) {
-            const int slot = lbase + __popcll(ml & lt);
-            if (slot < rd.n_total) {
-                store_part<DIM, T>(rd.lo, slot, pt, true);
-                gp(rd.lopatch)[slot] = dest;
-            } else {
-                err |= ERR_CAPACITY;
+        __syncthreads();
+        const int ns = s_ns;
+        for (int base = 0; base < ns; base += BLOCK) {
+            const int j = base + tid;
+            const bool mine = j < ns;
+            Part<T> pt;
+            int dest = q;
+            if (mine) {
+                load_part<DIM, T>(rd.sp, s_sl[j], pt);
+                dest = push_one<DIM, T, PX>(rd, s_win, s_tile, p0, P, pt, err);
+            }
+            const unsigned long long ml = __ballot(mine);
+            int lbase = 0;
+            if (ml) {
+                if (lane == 0) lbase = atomicAdd(&rd.ctl->nleave, __popcll(ml));
+                lbase = __shfl(lbase, 0);
+            }
+            if (mine) {
+                const int slot = lbase + __popcll(ml & lt);
+                if (slot < rd.n_total) {
+                    store_part<DIM, T>(rd.lo, slot, pt, true);
+                    gp(rd.lopatch)[slot] = dest;
+                } else {
+                    err |= ERR_CAPACITY;
+                }
             }
         }
+        __syncthreads();   // s_sl and s_ns are reused by the next round
     }
 
     if (err) atomicOr(&rd.ctl->err, err);
@@ -545,6 +594,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     // flush the tile in the tile precision (transfer (i) reads it)
     SDMD_GLOBAL R *dst = gp((R *)rd.tiles) + (long long)sg * 3 * TS;
     for (int idx = tid; idx < 3 * TS; idx += BLOCK) dst[idx] = (R)s_tile[idx];
+    if (tid == 0) tflag[sg] = 1;
 }
 
 #define PUSH_CASE(D, TT, PXV, PCV)                                                                  \

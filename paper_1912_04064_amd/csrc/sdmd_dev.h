@@ -124,6 +124,7 @@ struct RunDev {
     Store st, lv, sp;    // patch store, leaver / scratch store, spill store
     int *lpatch, *spatch;
     int *nlv;            // [seg_max] leavers of each segment this step, in lv at sseg[s]
+    int *tflag;          // [seg_max] 1 when the segment's tile in HBM may hold non-zero values
     Store lo;            // overflow leavers (parked particles re-entering)
     int *lopatch;
     Ctl *ctl;

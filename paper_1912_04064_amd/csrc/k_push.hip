@@ -108,7 +108,7 @@ __device__ __forceinline__ void esirkepov_axis_delta(R d0, R D, int ip, R S0[4],
 // product S0u (S0v + DSv/2) + DSu (S0v/2 + DSv/3).
 template <int NF, class R>
 __device__ __forceinline__ void deposit2d(double *Jb, int T0, int TS, const R S0[3][4], const R DS[3][4],
-                                          const R cj[3], R cz)
+                                          const R cj[3], R cz, bool mx, bool my)
 {
     const R third = R(1) / R(3);
     R hf[2][4], qf[2][4], cs[2][3];
@@ -125,25 +125,34 @@ __device__ __forceinline__ void deposit2d(double *Jb, int T0, int TS, const R S0
             }
         }
     }
+    // In the 4-slot frame, a lane that kept its node on an axis holds zeros
+    // in that axis's last slot (and its running sum ends one slot early):
+    // those adds are skipped lane by lane.  An LDS add costs bank cycles
+    // per active lane, so the masked lanes are free.
 #pragma unroll
     for (int n = 0; n < NF; ++n)
 #pragma unroll
-        for (int m = 0; m < NF - 1; ++m) atomicAdd(&Jb[n * T0 + m], (double)(cs[0][m] * hf[1][n]));
+        for (int m = 0; m < NF - 1; ++m)
+            if (NF == 3 || ((m < 2 || mx) && (n < 3 || my))) atomicAdd(&Jb[n * T0 + m], (double)(cs[0][m] * hf[1][n]));
 #pragma unroll
     for (int n = 0; n < NF - 1; ++n)
 #pragma unroll
-        for (int m = 0; m < NF; ++m) atomicAdd(&Jb[TS + n * T0 + m], (double)(cs[1][n] * hf[0][m]));
+        for (int m = 0; m < NF; ++m)
+            if (NF == 3 || ((n < 2 || my) && (m < 3 || mx)))
+                atomicAdd(&Jb[TS + n * T0 + m], (double)(cs[1][n] * hf[0][m]));
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
         const R a = cz * S0[0][m], b = cz * DS[0][m];
 #pragma unroll
-        for (int n = 0; n < NF; ++n) atomicAdd(&Jb[2 * TS + n * T0 + m], (double)(a * hf[1][n] + b * qf[1][n]));
+        for (int n = 0; n < NF; ++n)
+            if (NF == 3 || ((m < 3 || mx) && (n < 3 || my)))
+                atomicAdd(&Jb[2 * TS + n * T0 + m], (double)(a * hf[1][n] + b * qf[1][n]));
     }
 }
 
 template <int NF, class R>
 __device__ __forceinline__ void deposit3d(double *Jb, int T0, int T1, int TS, const R S0[3][4], const R DS[3][4],
-                                          const R cj[3])
+                                          const R cj[3], const bool mv[3])
 {
     const R third = R(1) / R(3);
     R hf[3][4], qf[3][4], cs[3][3];
@@ -173,7 +182,8 @@ __device__ __forceinline__ void deposit3d(double *Jb, int T0, int T1, int TS, co
                 const R tr = S0[u][i] * hf[v][j] + DS[u][i] * qf[v][j];
 #pragma unroll
                 for (int m = 0; m < NF - 1; ++m)
-                    atomicAdd(&Jb[c * TS + i * su + j * sv + m * sc], (double)(cs[c][m] * tr));
+                    if (NF == 3 || ((m < 2 || mv[c]) && (i < 3 || mv[u]) && (j < 3 || mv[v])))
+                        atomicAdd(&Jb[c * TS + i * su + j * sv + m * sc], (double)(cs[c][m] * tr));
             }
         }
     }
@@ -372,14 +382,14 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
     if constexpr (DIM == 2) {
         const R cz = (T::split ? (R)rd.f_q : (R)rd.q) * p.w * (un[2] * ig);
         if (__all(still))
-            deposit2d<3, R>(Jb, T0, TS, S0, DS, cj, cz);
+            deposit2d<3, R>(Jb, T0, TS, S0, DS, cj, cz, false, false);
         else
-            deposit2d<4, R>(Jb, T0, TS, S0, DS, cj, cz);
+            deposit2d<4, R>(Jb, T0, TS, S0, DS, cj, cz, mv[0], mv[1]);
     } else {
         if (__all(still))
-            deposit3d<3, R>(Jb, T0, T1, TS, S0, DS, cj);
+            deposit3d<3, R>(Jb, T0, T1, TS, S0, DS, cj, mv);
         else
-            deposit3d<4, R>(Jb, T0, T1, TS, S0, DS, cj);
+            deposit3d<4, R>(Jb, T0, T1, TS, S0, DS, cj, mv);
     }
 
     p.u[0] = un[0];

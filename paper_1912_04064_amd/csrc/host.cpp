@@ -280,7 +280,7 @@ static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::st
     size_t b = 0;
     b += align256((size_t)L.n_regions * F_NCOMP * L.rsize * 8);
     b += align256((size_t)L.seg_max * 3 * L.tsz * rsz);
-    b += 5 * align256((size_t)(L.n_patch + 1) * 4) + 7 * align256((size_t)(L.seg_max + 1) * 4);
+    b += 6 * align256((size_t)(L.n_patch + 1) * 4) + 7 * align256((size_t)(L.seg_max + 1) * 4);
     b += 2 * (size_t)L.cap_total * per + align256((size_t)L.cap_total * 4);
     b += 2 * (size_t)std::max<long long>(L.n_total, 1) * (per + 4);
     b += 64 * 256;   // per-array rounding and the control block
@@ -384,8 +384,9 @@ static int relayout_one(pic_ctx *c, int slot, int force)
     Run &r = c->runs[slot];
     HIPCHK(c, hipMemcpyAsync(c->d_slot1, &slot, sizeof(int), hipMemcpyHostToDevice, c->stream));
     const int nsb = std::max(1, std::min(1024, (int)(r.rd.n_total / (BLOCK * 64))));
+    const int mgx = move_chunk_blocks(r.rd.n_patch, r.rd.n_total) + nsb;
     int cb = (int)std::min<long long>(64, std::max<long long>(1, (r.rd.seg_max + BLOCK) / BLOCK));
-    HIPCHK(c, launch_relayout(r.dims, r.split, c->d_runs, c->d_slot1, 1, r.rd.n_patch + nsb, cb, force, c->stream));
+    HIPCHK(c, launch_relayout(r.dims, r.split, c->d_runs, c->d_slot1, 1, mgx, cb, force, c->stream));
     return PIC_OK;
 }
 
@@ -549,6 +550,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     d.tot = (int *)run_alloc(c, r, pb);
     d.preg = (int *)run_alloc(c, r, pb);
     d.fill = (int *)run_alloc(c, r, pb);
+    d.cpre = (int *)run_alloc(c, r, pb);
     d.sseg = (int *)run_alloc(c, r, sb);
     d.scnt = (int *)run_alloc(c, r, sb);
     d.spat = (int *)run_alloc(c, r, sb);
@@ -556,7 +558,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     d.scnt2 = (int *)run_alloc(c, r, sb);
     d.spat2 = (int *)run_alloc(c, r, sb);
     d.ctl = (Ctl *)run_alloc(c, r, sizeof(Ctl));
-    ok = d.fld && d.tiles && d.pseg && d.pseg2 && d.tot && d.preg && d.fill && d.sseg && d.scnt && d.spat &&
+    ok = d.fld && d.tiles && d.pseg && d.pseg2 && d.tot && d.preg && d.fill && d.cpre && d.sseg && d.scnt && d.spat &&
          d.sseg2 && d.scnt2 && d.spat2 && d.ctl;
     make_store(c, r, d.st, L.cap_total, L.split, L.dims, ids, ok);
     make_store(c, r, d.lv, L.cap_total, L.split, L.dims, ids, ok);
@@ -737,7 +739,7 @@ static int rebuild_items(pic_ctx *c)
         for (int b = 0; b < d.ins_blocks; ++b) fc->hp.push_back(make_int4(slot, 2, b, d.ins_blocks));
         fc->slots.push_back(slot);
         const int nsb = std::max(1, std::min(1024, (int)(d.n_total / (BLOCK * 64))));
-        fc->move_gx = std::max(fc->move_gx, d.n_patch + nsb);
+        fc->move_gx = std::max(fc->move_gx, move_chunk_blocks(d.n_patch, d.n_total) + nsb);
         fc->commit_gx = std::max(fc->commit_gx, std::min(64, std::max(1, (d.seg_max + BLOCK) / BLOCK)));
     }
     int rc;

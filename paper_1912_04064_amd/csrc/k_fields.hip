@@ -19,38 +19,86 @@
 namespace sdmd {
 
 // --------------------------------------------------------------- J gather
-// Current at global node g: for each component, the sum over the segment
-// tiles of the patches whose node range [p0-2, p0+P+2] covers g (periodic),
-// in a fixed order (patches by offset, then segments).  The three components
-// are read in one pass so their loads overlap.
-template <int DIM, class R>
-__device__ __forceinline__ void gather_J(const RunDev &rd, const SDMD_GLOBAL R *__restrict__ tiles, const int g[3],
-                                         double J[3])
+// The current at a node is the sum, over the segment tiles of every patch
+// whose node range [p0-2, p0+P+2] covers the node (periodic), in a fixed
+// order (patches by offset, then segments).  A workgroup gathers a box of
+// nodes; it first tabulates, per box column / row / layer, the offset of the
+// node inside its patch and the index of that patch among the patches that
+// cover the box (one division per axis entry instead of per node), and the
+// segment range of each covering patch, so the per-node work is LDS lookups
+// and the tile loads.
+__device__ __forceinline__ int floordiv(int g, int P) { return (g + 8 * P) / P - 8; }   // g >= -8P
+
+// i mod n for any i (table entries of tiny periodic grids wrap more than once)
+__device__ __forceinline__ int wrapm(int i, int n)
 {
-    int pa[3] = {0, 0, 0}, l[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// covering patches per axis over a box of extent E: at most (E-1)/P + 2
+// patches hold the box's nodes, plus one neighbour on each side (P >= 4)
+constexpr int cover_bound(int E) { return (E - 1) / 4 + 4; }
+
+struct GatherBox {
+    int org[3];   // global (unwrapped) coordinate of the box's first node per axis
+    int ext[3];   // box extent per axis
+    int pu0[3];   // first covering patch (unwrapped) per axis
+    int nc[3];    // covering patches per axis
+};
+
+template <int DIM, int AXM, int NCM>
+__device__ __forceinline__ void gather_tables(const RunDev &rd, const GatherBox &b, int2 (*s_ax)[AXM], int2 *s_rng,
+                                              int tid)
+{
+    const int P[3] = {rd.P[0], rd.P[1], DIM == 3 ? rd.P[2] : 1};
+    const int nax = b.ext[0] + b.ext[1] + (DIM == 3 ? b.ext[2] : 0);
+    for (int t = tid; t < nax; t += BLOCK) {
+        const int a = t < b.ext[0] ? 0 : (t < b.ext[0] + b.ext[1] ? 1 : 2);
+        const int e = t - (a == 0 ? 0 : (a == 1 ? b.ext[0] : b.ext[0] + b.ext[1]));
+        const int gu = b.org[a] + e;
+        const int pu = floordiv(gu, P[a]);
+        s_ax[a][e] = make_int2(gu - pu * P[a], pu - b.pu0[a]);
+    }
+    if (DIM == 2 && tid == 0) s_ax[2][0] = make_int2(0, 0);
+    const SDMD_GLOBAL int *pseg = gp(rd.pseg);
+    const int ncov = b.nc[0] * b.nc[1] * b.nc[2];
+    for (int t = tid; t < ncov; t += BLOCK) {
+        const int cx = t % b.nc[0], cy = (t / b.nc[0]) % b.nc[1], cz = t / (b.nc[0] * b.nc[1]);
+        const int qx = wrapm(b.pu0[0] + cx, rd.np[0]), qy = wrapm(b.pu0[1] + cy, rd.np[1]);
+        const int qz = DIM == 3 ? wrapm(b.pu0[2] + cz, rd.np[2]) : 0;
+        const int q = qx + rd.np[0] * (qy + rd.np[1] * qz);
+        s_rng[t] = make_int2(pseg[q], pseg[q + 1]);
+    }
+}
+
+// J at box node (ex, ey, ez)
+template <int DIM, int AXM, class R>
+__device__ __forceinline__ void gather_J(const RunDev &rd, const SDMD_GLOBAL R *__restrict__ tiles,
+                                         const GatherBox &b, const int2 (*s_ax)[AXM], const int2 *s_rng, int ex,
+                                         int ey, int ez, double J[3])
+{
+    const int P[3] = {rd.P[0], rd.P[1], DIM == 3 ? rd.P[2] : 1};
+    const int2 X = s_ax[0][ex], Y = s_ax[1][ey], Z = DIM == 3 ? s_ax[2][ez] : make_int2(0, 0);
+    const int l[3] = {X.x, Y.x, Z.x}, c[3] = {X.y, Y.y, Z.y};
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        pa[a] = g[a] / rd.P[a];
-        l[a] = g[a] - pa[a] * rd.P[a];
         lo[a] = l[a] <= 2 ? -1 : 0;
-        hi[a] = l[a] >= rd.P[a] - 2 ? 1 : 0;
+        hi[a] = l[a] >= P[a] - 2 ? 1 : 0;
     }
     const long long tsz = rd.tsz;
-    const SDMD_GLOBAL int *pseg = gp(rd.pseg);
+    const int TA0 = rd.TA[0], TA1 = rd.TA[1];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int oz = lo[2]; oz <= hi[2]; ++oz)
         for (int oy = lo[1]; oy <= hi[1]; ++oy)
             for (int ox = lo[0]; ox <= hi[0]; ++ox) {
-                const int qx = wrap1(pa[0] + ox, rd.np[0]);
-                const int qy = wrap1(pa[1] + oy, rd.np[1]);
-                const int qz = DIM == 3 ? wrap1(pa[2] + oz, rd.np[2]) : 0;
-                const int q = qx + rd.np[0] * (qy + rd.np[1] * qz);
-                const int tx = l[0] - ox * rd.P[0] + 2;
-                const int ty = l[1] - oy * rd.P[1] + 2;
-                const int tz = DIM == 3 ? l[2] - oz * rd.P[2] + 2 : 0;
-                const int off = (tz * rd.TA[1] + ty) * rd.TA[0] + tx;
-                const int e = pseg[q + 1];
-                for (int sg = pseg[q]; sg < e; ++sg) {
+                const int2 r = s_rng[((c[2] + oz) * b.nc[1] + (c[1] + oy)) * b.nc[0] + (c[0] + ox)];
+                const int tx = l[0] - ox * P[0] + 2;
+                const int ty = l[1] - oy * P[1] + 2;
+                const int tz = DIM == 3 ? l[2] - oz * P[2] + 2 : 0;
+                const int off = (tz * TA1 + ty) * TA0 + tx;
+                for (int sg = r.x; sg < r.y; ++sg) {
                     const SDMD_GLOBAL R *t = tiles + (long long)sg * 3 * tsz + off;
                     s0 += (double)t[0];
                     s1 += (double)t[tsz];
@@ -62,7 +110,6 @@ __device__ __forceinline__ void gather_J(const RunDev &rd, const SDMD_GLOBAL R *
     J[2] = s2;
 }
 
-// ------------------------------------------------------------ Yee kernel
 // Yee tile shapes: BLOCK nodes per workgroup, x extent TX chosen per run
 // from the region width (64 for wide regions; 32, 16 or 8 when regions are
 // as small as patches, so that a tile does not straddle mostly empty space).
@@ -101,8 +148,13 @@ __global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ r
     constexpr int KM = FilterMax<DIM, FILT>::K;
     constexpr int EXS = HX + 2 * KM, EYS = HY + 2 * KM, EZS = DIM == 3 ? HZ + 2 * KM : 1;
     constexpr int EN = FILT ? EXS * EYS * EZS : 1;
+    constexpr int AXM = EXS > EYS ? (EXS > EZS ? EXS : EZS) : (EYS > EZS ? EYS : EZS);
+    constexpr int NCM = cover_bound(EXS) * cover_bound(EYS) * (DIM == 3 ? cover_bound(EZS) : 1);
     __shared__ double sE[3][HN];
     __shared__ double sJ[FILT ? 4 : 1][EN];   // 3 components + one sweep buffer
+    __shared__ int2 s_ax[3][AXM];             // gather tables
+    __shared__ int2 s_rng[NCM];
+    static_assert(NCM <= 512, "gather table");
 
     const int4 it = items[blockIdx.x];
     const RunDev &rd = runs[it.x];
@@ -137,17 +189,37 @@ __global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ r
     const long long sx = 1, sy = rd.ra[0], sz = (long long)rd.ra[0] * rd.ra[1];
 
     int kf = 0;   // filter passes of this run
+    if constexpr (FILT) kf = min(max(rd.filter, 0), KM);
+    // the gathered box: tile + high halo, widened by kf nodes for the filter
+    GatherBox gb;
+    {
+        const int P[3] = {rd.P[0], rd.P[1], DIM == 3 ? rd.P[2] : 1};
+        const int o3[3] = {ro[0] + ox - kf, ro[1] + oy - kf, DIM == 3 ? ro[2] + oz - kf : 0};
+        const int e3[3] = {HX + 2 * kf, HY + 2 * kf, DIM == 3 ? HZ + 2 * kf : 1};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            gb.org[a] = o3[a];
+            gb.ext[a] = e3[a];
+            if (a < DIM) {
+                gb.pu0[a] = floordiv(o3[a], P[a]) - 1;
+                gb.nc[a] = floordiv(o3[a] + e3[a] - 1, P[a]) + 2 - gb.pu0[a];
+            } else {
+                gb.pu0[a] = 0;
+                gb.nc[a] = 1;
+            }
+        }
+    }
+    gather_tables<DIM, AXM, NCM>(rd, gb, s_ax, s_rng, tid);
+    __syncthreads();
+
     if constexpr (FILT) {
-        kf = min(max(rd.filter, 0), KM);
-        const int bx = HX + 2 * kf, by = HY + 2 * kf, bz = DIM == 3 ? HZ + 2 * kf : 1;
+        const int bx = gb.ext[0], by = gb.ext[1], bz = gb.ext[2];
         const int nb = bx * by * bz;
         // raw current on the widened box
         for (int h = tid; h < nb; h += BLOCK) {
             const int ex = h % bx, ey = (h / bx) % by, ez = h / (bx * by);
-            const int g[3] = {wrap1(ro[0] + ox - kf + ex, rd.n[0]), wrap1(ro[1] + oy - kf + ey, rd.n[1]),
-                              DIM == 3 ? wrap1(ro[2] + oz - kf + ez, rd.n[2]) : 0};
             double J[3];
-            gather_J<DIM, R>(rd, tiles, g, J);
+            gather_J<DIM, AXM, R>(rd, tiles, gb, s_ax, s_rng, ex, ey, ez, J);
             const int e = (ez * EYS + ey) * EXS + ex;
             sJ[0][e] = J[0];
             sJ[1][e] = J[1];
@@ -195,9 +267,7 @@ __global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ r
             J[1] = sJ[1][e];
             J[2] = sJ[2][e];
         } else {
-            const int g[3] = {wrap1(ro[0] + li, rd.n[0]), wrap1(ro[1] + lj, rd.n[1]),
-                              DIM == 3 ? wrap1(ro[2] + lk, rd.n[2]) : 0};
-            gather_J<DIM, R>(rd, tiles, g, J);
+            gather_J<DIM, AXM, R>(rd, tiles, gb, s_ax, s_rng, hx, hy, hz, J);
         }
         const long long p = rindex(rd, li, lj, DIM == 3 ? lk : 0);
         double e0, e1, e2;

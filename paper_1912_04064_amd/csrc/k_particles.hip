@@ -129,6 +129,20 @@ __global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev 
     __syncthreads();
     for (int p = tid; p < np; p += PLAN_BLOCK) rd.preg[p] = rd.tot[p];
     __syncthreads();
+    {
+        // move chunks of each patch's segment particles -> first chunk per patch
+        const int per = (np + PLAN_BLOCK - 1) / PLAN_BLOCK;
+        const int q0 = tid * per, q1 = min(np, q0 + per);
+        long long nc = 0;
+        for (int p = q0; p < q1; ++p) nc += (rd.preg[p] + MOVE_CHUNK - 1) / MOVE_CHUNK;
+        long long ncall;
+        long long o = block_exclusive_scan(nc, buf, ncall);
+        for (int p = q0; p < q1; ++p) {
+            rd.cpre[p] = (int)o;
+            o += (rd.preg[p] + MOVE_CHUNK - 1) / MOVE_CHUNK;
+        }
+        if (tid == 0) rd.cpre[np] = (int)ncall;
+    }
     // parked particles per patch: LDS histogram when the patch count fits
     if (np <= PLAN_LDS_PATCHES) {
         for (int p = tid; p < np; p += PLAN_BLOCK) s_hist[p] = 0;
@@ -251,21 +265,38 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
     const RunDev &rd = runs[slots[blockIdx.y]];
     if (!rd.ctl->relayout) return;
     const int np = rd.n_patch;
-    const int n_spill_blocks = (int)gridDim.x - np;   // >= 1 by construction
-    if ((int)blockIdx.x < np) {
-        // The patch's particles (from all its old segments) are sorted by
-        // cell (counting sort in LDS) and stored transposed: viewing the
-        // cell-sorted list as rows of M (~ particles per cell) entries,
-        // position = column * rows + row.  Consecutive positions -- the
-        // lanes of a wavefront -- then hold particles of consecutive cells,
-        // whose field-window reads and current-tile updates fall on
-        // different LDS banks.  Positions are then split evenly over the
-        // patch's new segments.
+    const int cb = move_chunk_blocks(np, rd.n_total);
+    const int n_spill_blocks = (int)gridDim.x - cb;   // >= 1 by construction
+    if ((int)blockIdx.x < cb) {
+        // One chunk of a patch's segment particles: with nch chunks, chunk
+        // k takes every nch-th particle of the old storage order starting at
+        // k (so that each chunk samples the whole patch), at most MOVE_CHUNK
+        // of them.  The chunk is sorted by cell (counting sort in LDS) and
+        // stored transposed: viewing the cell-sorted chunk as rows of M
+        // (~ particles per occupied cell) entries, position = column * rows
+        // + row.  Consecutive positions -- the lanes of a wavefront -- then
+        // hold particles of consecutive cells, whose field-window reads and
+        // current-tile updates fall on different LDS banks.  Chunks take
+        // consecutive ranges of the patch's positions, which are split
+        // evenly over its new segments.
         __shared__ int s_off[MAX_PATCH_CELLS];
         __shared__ int s_sum[BLOCK];
         __shared__ int s_seg[MAX_OLD_SEGS + 1];
-        const int p = blockIdx.x;
+        __shared__ int s_p, s_nocc;
+        const int b = blockIdx.x;
+        if (b >= rd.cpre[np]) return;        // more chunk blocks than chunks
         const int tid = threadIdx.x;
+        if (tid == 0) {
+            int lo = 0, hi = np;             // the patch p with cpre[p] <= b < cpre[p + 1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (rd.cpre[mid] <= b) lo = mid; else hi = mid;
+            }
+            s_p = lo;
+        }
+        __syncthreads();
+        const int p = s_p;
+        const int kc = b - rd.cpre[p], nch = rd.cpre[p + 1] - rd.cpre[p];
         const int k0 = rd.pseg[p], K = min(rd.pseg[p + 1] - k0, MAX_OLD_SEGS);
         // prefix of the old segments' live counts
         if (tid == 0) {
@@ -279,8 +310,11 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
         }
         const int ncell = rd.P[0] * rd.P[1] * (DIM == 3 ? rd.P[2] : 1);
         for (int k = tid; k < ncell; k += BLOCK) s_off[k] = 0;
+        if (tid == 0) s_nocc = 0;
         __syncthreads();
-        const int r = s_seg[K];
+        const int r = min(s_seg[K], rd.preg[p]);
+        const int m = r / nch + (kc < r % nch ? 1 : 0);                  // particles of this chunk
+        const int base = kc * (r / nch) + min(kc, r % nch);             // its first position
         const int t = rd.tot[p];
         auto src = [&](int i) -> long long {   // i-th live particle of the patch
             int lo = 0, hi = K;                // s_seg[lo] <= i < s_seg[hi]
@@ -290,14 +324,18 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
             }
             return (long long)rd.sseg[k0 + lo] + (i - s_seg[lo]);
         };
-        for (int i = tid; i < r; i += BLOCK) atomicAdd(&s_off[local_cell<DIM, T>(rd, rd.st, src(i), p)], 1);
+        for (int i = tid; i < m; i += BLOCK) atomicAdd(&s_off[local_cell<DIM, T>(rd, rd.st, src(kc + i * nch), p)], 1);
         __syncthreads();
         // exclusive scan of the cell counts: contiguous runs per thread
         const int per = (ncell + BLOCK - 1) / BLOCK;
         const int c0 = tid * per, c1 = min(ncell, c0 + per);
-        int run = 0;
-        for (int k = c0; k < c1; ++k) run += s_off[k];
+        int run = 0, occ = 0;
+        for (int k = c0; k < c1; ++k) {
+            run += s_off[k];
+            occ += s_off[k] > 0 ? 1 : 0;
+        }
         s_sum[tid] = run;
+        if (occ) atomicAdd(&s_nocc, occ);
         __syncthreads();
         for (int off = 1; off < BLOCK; off <<= 1) {
             const int v = tid >= off ? s_sum[tid - off] : 0;
@@ -312,21 +350,22 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
             acc += v;
         }
         __syncthreads();
-        const int M = max(1, (r + ncell / 2) / max(ncell, 1));
-        const int Rw = (r + M - 1) / M;
-        const int lastc = r - (Rw - 1) * M;
-        for (int i = tid; i < r; i += BLOCK) {
-            const long long si = src(i);
+        const int nocc = max(s_nocc, 1);
+        const int M = max(1, (m + nocc / 2) / nocc);
+        const int Rw = (m + M - 1) / M;
+        const int lastc = m - (Rw - 1) * M;
+        for (int i = tid; i < m; i += BLOCK) {
+            const long long si = src(kc + i * nch);
             const int j = atomicAdd(&s_off[local_cell<DIM, T>(rd, rd.st, si, p)], 1);
             const int row = j / M, col = j - row * M;
             const int pos = col * Rw - max(0, col - lastc) + row;
-            copy_part<DIM, T>(rd.st, si, rd.lv, new_slot(rd, p, t, pos));
+            copy_part<DIM, T>(rd.st, si, rd.lv, new_slot(rd, p, t, base + pos));
         }
         return;
     }
     // parked particles follow the patch-store ones in their patch's list
     const int nsp = min(rd.ctl->nspill, rd.n_total);
-    for (int i = (blockIdx.x - np) * BLOCK + threadIdx.x; i < nsp; i += n_spill_blocks * BLOCK) {
+    for (int i = (blockIdx.x - cb) * BLOCK + threadIdx.x; i < nsp; i += n_spill_blocks * BLOCK) {
         const int q = rd.spatch[i];
         const int pos = rd.preg[q] + atomicAdd(&rd.fill[q], 1);
         copy_part<DIM, T>(rd.sp, i, rd.lv, new_slot(rd, q, rd.tot[q], pos));

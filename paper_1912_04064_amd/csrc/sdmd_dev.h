@@ -44,6 +44,14 @@ __host__ __device__ inline int f_B(int par) { return F_B0 + 3 * par; }
 
 constexpr int BLOCK = 256;     // threads per workgroup of the step kernels
 
+// A re-layout moves each patch's particles in chunks of MOVE_CHUNK, one
+// workgroup per chunk; at most n_patch + ceil(N / MOVE_CHUNK) chunks exist.
+constexpr int MOVE_CHUNK = 4096;
+__host__ __device__ inline int move_chunk_blocks(int n_patch, long long n_total)
+{
+    return n_patch + (int)((n_total + MOVE_CHUNK - 1) / MOVE_CHUNK);
+}
+
 // error flag bits (Ctl::err)
 constexpr int ERR_NONFINITE = 1;
 constexpr int ERR_MOVE = 2;
@@ -121,6 +129,7 @@ struct RunDev {
     int *spat;           // [seg_max] patch of each segment
     int *pseg2, *sseg2, *scnt2, *spat2;   // re-layout: the new segment layout
     int *tot, *preg, *fill;               // re-layout: per-patch totals, patch-store part, spill fill
+    int *cpre;                            // re-layout: first move chunk of each patch [n_patch + 1]
     Store st, lv, sp;    // patch store, leaver / scratch store, spill store
     int *lpatch, *spatch;
     int *nlv;            // [seg_max] leavers of each segment this step, in lv at sseg[s]

@@ -527,7 +527,6 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     d.n_total = (int)L.n_total;
     d.ins_blocks = std::max(1, std::min(64, (int)(L.n_total / 65536)));
     d.ins_segs = 16;
-    d.post_blocks = (r.total_ghosts + BLOCK - 1) / BLOCK + (d.seg_max + d.ins_segs - 1) / d.ins_segs + d.ins_blocks;
     d.ghosts = L.ghosts;
     d.dt = cfg->dt;
     d.q = cfg->q;
@@ -589,7 +588,8 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     {
         Ctl init;
         memset(&init, 0, sizeof init);
-        init.remaining = cfg->max_steps > 0 ? (int)std::min<int64_t>(cfg->max_steps, (1LL << 30)) : -1;
+        init.remaining[0] = init.remaining[1] =
+            cfg->max_steps > 0 ? (int)std::min<int64_t>(cfg->max_steps, (1LL << 30)) : -1;
         HIPCHK(c, hipMemcpyAsync(d.ctl, &init, sizeof init, hipMemcpyHostToDevice, s));
         HIPCHK(c, hipStreamSynchronize(s));
     }

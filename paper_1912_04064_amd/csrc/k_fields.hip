@@ -11,6 +11,8 @@
 //   post_kernel  : region ghost synchronisation of the new E, B, Bm
 //                  (section 2.1 "Sync", between regions) and, in the same
 //                  launch, insertion of the particles that left their patch.
+//                  The per-run step bookkeeping (budget, overflow and spill
+//                  counters) is done by one workgroup of yee_kernel.
 //   init / readout helpers.
 #include "launch.h"
 #include "part.h"
@@ -159,10 +161,21 @@ __global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ r
     const int4 it = items[blockIdx.x];
     const RunDev &rd = runs[it.x];
     const int tid = threadIdx.x;
-    if (rd.ctl->remaining == 0) return;   // the run has taken all its steps
-    // one workgroup per run clears the spill counter: the particle phase of
-    // this step has consumed the spill store
-    if (it.w && tid == 0) rd.ctl->nspill = 0;
+    // One workgroup per run ends the bookkeeping of the previous step and
+    // prepares the next: the step budget of step s + 1, the overflow counter
+    // of step s - 1 (consumed by its post kernel), and the spill store,
+    // consumed by this step's particle phase.
+    const int rem = rd.ctl->remaining[par];
+    if (it.w && tid == 0) {
+        rd.ctl->remaining[1 - par] = rem > 0 ? rem - 1 : rem;
+        if (rem != 0) {
+            rd.ctl->nleave[1 - par] = 0;
+            const int ns = rd.ctl->nspill;
+            if (ns > rd.ctl->max_spill) rd.ctl->max_spill = ns;
+            rd.ctl->nspill = 0;
+        }
+    }
+    if (rem == 0) return;   // the run has taken all its steps
 
     const int region = it.y;
     const int rr[3] = {region % rd.nreg[0], (region / rd.nreg[0]) % rd.nreg[1],
@@ -391,10 +404,10 @@ __device__ __forceinline__ void ghost_copy(const RunDev &rd, int gk, const int *
 }
 
 // ------------------------------------------------------------ post kernel
-// Every workgroup of a run reads the run's step budget before it arrives at
-// the run's arrival counter; the last to arrive ends the step for the run
-// (clears the overflow counter, spends one step of the budget).  Kernels of
-// the next step see the new budget, so a run stops exactly on its last step.
+// Ghost synchronisation and leaver insertion of step s.  The step budget
+// and the overflow counter it reads are the entries of step s's parity; the
+// field kernel of step s has already prepared those of step s + 1 (so a run
+// stops exactly on its last step without any end-of-kernel arrival count).
 template <int DIM, class T>
 __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ runs, const int4 *__restrict__ items,
                                                      int par_new)
@@ -402,7 +415,8 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
     const int4 it = items[blockIdx.x];
     const RunDev &rd = runs[it.x];
     const int tid = threadIdx.x;
-    const bool active = rd.ctl->remaining != 0;
+    const int par = 1 - par_new;   // parity of this step
+    const bool active = rd.ctl->remaining[par] != 0;
     int err = 0;
     if (active && it.y == 0) {
         const int comps[9] = {f_E(par_new), f_E(par_new) + 1, f_E(par_new) + 2, f_B(par_new), f_B(par_new) + 1,
@@ -458,7 +472,7 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
             // overflow leavers (parked particles that re-entered): a few
             // workgroups stride over them
             const int nb = it.w;
-            const int nl = min(rd.ctl->nleave, rd.n_total);
+            const int nl = min(rd.ctl->nleave[par], rd.n_total);
             for (int i0 = it.z * BLOCK; i0 < nl; i0 += nb * BLOCK) {
                 const int i = i0 + tid;
                 const bool v = i < nl;
@@ -467,22 +481,6 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
         }
     }
     if (err) atomicOr(&rd.ctl->err, err);
-    __shared__ int s_last;
-    __syncthreads();
-    if (tid == 0) {
-        __threadfence();
-        s_last = atomicAdd(&rd.ctl->post_done, 1) == rd.post_blocks - 1;
-    }
-    __syncthreads();
-    if (s_last && tid == 0) {
-        if (active) {
-            const int ns = rd.ctl->nspill;
-            if (ns > rd.ctl->max_spill) rd.ctl->max_spill = ns;
-            rd.ctl->nleave = 0;
-            if (rd.ctl->remaining > 0) rd.ctl->remaining -= 1;
-        }
-        rd.ctl->post_done = 0;
-    }
 }
 
 // ------------------------------------------------------------ launchers

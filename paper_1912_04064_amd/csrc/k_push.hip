@@ -445,7 +445,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     const int band = (nseg + 7) >> 3;
     const int jb = item.y >> 3;
     const int sg = (item.y & 7) * band + jb;   // segment
-    if (jb >= band || sg >= nseg || rd.ctl->remaining == 0) return;   // slot unused, or run finished
+    if (jb >= band || sg >= nseg || rd.ctl->remaining[par] == 0) return;   // slot unused, or run finished
     const int q = rd.spat[sg];           // its patch
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
@@ -579,7 +579,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
             const unsigned long long ml = __ballot(mine);
             int lbase = 0;
             if (ml) {
-                if (lane == 0) lbase = atomicAdd(&rd.ctl->nleave, __popcll(ml));
+                if (lane == 0) lbase = atomicAdd(&rd.ctl->nleave[par], __popcll(ml));
                 lbase = __shfl(lbase, 0);
             }
             if (mine) {

@@ -80,17 +80,21 @@ struct Store {
 };
 
 // per-run device counters
+// Per-step counters are kept twice, indexed by the parity of the step (the
+// E/B buffer parity at its start): kernels of step s use entry s & 1 only,
+// and one workgroup of the field kernel of step s prepares entry 1 - (s & 1)
+// for step s + 1.  No kernel needs to know which of its workgroups ends last.
 struct Ctl {
-    int nleave;       // particles appended to the overflow leaver store this step
+    int nleave[2];    // particles appended to the overflow leaver store in the step
     int nspill;       // particles parked in the spill store
-    int post_done;    // post-kernel workgroups of this run finished this step
     int err;          // ERR_* bits, sticky
     int relayout;     // set by the re-layout planner when a re-layout runs
     int n_relayout;   // re-layouts done
     int max_spill;    // largest nspill seen
     int nseg;         // segments in use
-    int remaining;    // steps left (-1: unlimited); 0 makes every kernel skip the run
-    int pad[3];
+    int remaining[2]; // steps left at the start of the step (-1: unlimited);
+                      // 0 makes every kernel skip the run
+    int pad[2];
 };
 
 struct RunDev {
@@ -112,7 +116,6 @@ struct RunDev {
     int n_total;         // particles of the run
     int ins_blocks;      // workgroups inserting the overflow leavers
     int ins_segs;        // segments per leaver-insert workgroup
-    int post_blocks;     // post-kernel workgroups of this run per step
     int ghosts;          // ghost nodes per region
     int filter;          // binomial current filter passes (0 = off)
     double d[3], L[3];

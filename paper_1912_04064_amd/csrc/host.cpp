@@ -526,7 +526,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     d.seg_cap = L.seg_cap;
     d.n_total = (int)L.n_total;
     d.ins_blocks = std::max(1, std::min(64, (int)(L.n_total / 65536)));
-    d.ins_segs = 16;
+    d.ins_segs = 4;
     d.ghosts = L.ghosts;
     d.dt = cfg->dt;
     d.q = cfg->q;

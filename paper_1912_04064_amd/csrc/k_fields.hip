@@ -49,13 +49,13 @@ struct GatherBox {
     int nc[3];    // covering patches per axis
 };
 
-template <int DIM, int AXM, int NCM>
+template <int DIM, int AXM, int NCM, int NT>
 __device__ __forceinline__ void gather_tables(const RunDev &rd, const GatherBox &b, int2 (*s_ax)[AXM], int2 *s_rng,
                                               int tid)
 {
     const int P[3] = {rd.P[0], rd.P[1], DIM == 3 ? rd.P[2] : 1};
     const int nax = b.ext[0] + b.ext[1] + (DIM == 3 ? b.ext[2] : 0);
-    for (int t = tid; t < nax; t += BLOCK) {
+    for (int t = tid; t < nax; t += NT) {
         const int a = t < b.ext[0] ? 0 : (t < b.ext[0] + b.ext[1] ? 1 : 2);
         const int e = t - (a == 0 ? 0 : (a == 1 ? b.ext[0] : b.ext[0] + b.ext[1]));
         const int gu = b.org[a] + e;
@@ -65,7 +65,7 @@ __device__ __forceinline__ void gather_tables(const RunDev &rd, const GatherBox 
     if (DIM == 2 && tid == 0) s_ax[2][0] = make_int2(0, 0);
     const SDMD_GLOBAL int *pseg = gp(rd.pseg);
     const int ncov = b.nc[0] * b.nc[1] * b.nc[2];
-    for (int t = tid; t < ncov; t += BLOCK) {
+    for (int t = tid; t < ncov; t += NT) {
         const int cx = t % b.nc[0], cy = (t / b.nc[0]) % b.nc[1], cz = t / (b.nc[0] * b.nc[1]);
         const int qx = wrapm(b.pu0[0] + cx, rd.np[0]), qy = wrapm(b.pu0[1] + cy, rd.np[1]);
         const int qz = DIM == 3 ? wrapm(b.pu0[2] + cz, rd.np[2]) : 0;
@@ -112,17 +112,23 @@ __device__ __forceinline__ void gather_J(const RunDev &rd, const SDMD_GLOBAL R *
     J[2] = s2;
 }
 
-// Yee tile shapes: BLOCK nodes per workgroup, x extent TX chosen per run
-// from the region width (64 for wide regions; 32, 16 or 8 when regions are
-// as small as patches, so that a tile does not straddle mostly empty space).
+// Yee tile shapes: one node per thread, x extent TX chosen per run from the
+// region width (64 for wide regions; 32, 16 or 8 when regions are as small
+// as patches, so that a tile does not straddle mostly empty space).  Wide 2D
+// regions take 64 x 8 tiles of 512 threads (the recomputed high halo is 14 %
+// of the tile instead of 27 % at 64 x 4); the others use BLOCK threads.
+constexpr int yee_block(int dims, int tx) { return dims == 2 && tx == 64 ? 2 * BLOCK : BLOCK; }
+
 template <int DIM, int TX>
 struct YeeTile;
 template <int TX>
 struct YeeTile<2, TX> {
-    static constexpr int X = TX, Y = BLOCK / TX, Z = 1;
+    static constexpr int NT = yee_block(2, TX);
+    static constexpr int X = TX, Y = NT / TX, Z = 1;
 };
 template <int TX>
 struct YeeTile<3, TX> {
+    static constexpr int NT = BLOCK;
     static constexpr int X = TX, Y = TX == 32 ? 4 : TX == 16 ? 4 : 8, Z = BLOCK / (TX * Y);
 };
 
@@ -139,12 +145,13 @@ struct FilterMax {
 };
 
 template <int DIM, class T, int TXC, bool FILT>
-__global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ runs, const int4 *__restrict__ items,
-                                                    int par)
+__global__ __launch_bounds__((YeeTile<DIM, TXC>::NT)) void yee_kernel(const RunDev *__restrict__ runs,
+                                                                      const int4 *__restrict__ items, int par)
 {
     using R = typename T::real;
+    constexpr int NT = YeeTile<DIM, TXC>::NT;
     constexpr int TX = YeeTile<DIM, TXC>::X, TY = YeeTile<DIM, TXC>::Y, TZ = YeeTile<DIM, TXC>::Z;
-    static_assert(TX * TY * TZ == BLOCK, "one node per thread");
+    static_assert(TX * TY * TZ == NT, "one node per thread");
     constexpr int HX = TX + 1, HY = TY + 1, HZ = DIM == 3 ? TZ + 1 : 1;
     constexpr int HN = HX * HY * HZ;
     constexpr int KM = FilterMax<DIM, FILT>::K;
@@ -222,14 +229,14 @@ __global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ r
             }
         }
     }
-    gather_tables<DIM, AXM, NCM>(rd, gb, s_ax, s_rng, tid);
+    gather_tables<DIM, AXM, NCM, NT>(rd, gb, s_ax, s_rng, tid);
     __syncthreads();
 
     if constexpr (FILT) {
         const int bx = gb.ext[0], by = gb.ext[1], bz = gb.ext[2];
         const int nb = bx * by * bz;
         // raw current on the widened box
-        for (int h = tid; h < nb; h += BLOCK) {
+        for (int h = tid; h < nb; h += NT) {
             const int ex = h % bx, ey = (h / bx) % by, ez = h / (bx * by);
             double J[3];
             gather_J<DIM, AXM, R>(rd, tiles, gb, s_ax, s_rng, ex, ey, ez, J);
@@ -245,7 +252,7 @@ __global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ r
                 for (int axis = 0; axis < DIM; ++axis) {
                     const int st = axis == 0 ? 1 : axis == 1 ? EXS : EXS * EYS;
                     const int ext = axis == 0 ? bx : axis == 1 ? by : bz;
-                    for (int h = tid; h < nb; h += BLOCK) {
+                    for (int h = tid; h < nb; h += NT) {
                         const int ex = h % bx, ey = (h / bx) % by, ez = h / (bx * by);
                         const int co = axis == 0 ? ex : axis == 1 ? ey : ez;
                         if (co < 1 || co > ext - 2) continue;
@@ -258,7 +265,7 @@ __global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ r
                     b = t;
                 }
             if (a != sJ[c]) {
-                for (int h = tid; h < nb; h += BLOCK) {
+                for (int h = tid; h < nb; h += NT) {
                     const int ex = h % bx, ey = (h / bx) % by, ez = h / (bx * by);
                     const int e = (ez * EYS + ey) * EXS + ex;
                     sJ[c][e] = a[e];
@@ -269,7 +276,7 @@ __global__ __launch_bounds__(BLOCK) void yee_kernel(const RunDev *__restrict__ r
     }
 
     // phase 1: J (gathered, or filtered from LDS) and Ampere on tile + high halo
-    for (int h = tid; h < HN; h += BLOCK) {
+    for (int h = tid; h < HN; h += NT) {
         const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
         const int li = ox + hx, lj = oy + hy, lk = oz + hz;
         if (li > rs0 || lj > rs1 || (DIM == 3 && lk > rs2)) continue;
@@ -492,7 +499,7 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
 
 #define YEE_CASE(D, TT, X, FL)                                                                        \
     if (dims == D && split == TT::split && tx == X && filt == FL) {                                   \
-        yee_kernel<D, TT, X, FL><<<n_items, BLOCK, 0, s>>>(runs, items, par);                         \
+        yee_kernel<D, TT, X, FL><<<n_items, yee_block(D, X), 0, s>>>(runs, items, par);                \
         return hipGetLastError();                                                                     \
     }
 
@@ -509,7 +516,7 @@ void yee_tile_shape(int dims, int tx, int shape[3])
 {
     shape[0] = tx;
     if (dims == 2) {
-        shape[1] = BLOCK / tx;
+        shape[1] = yee_block(2, tx) / tx;
         shape[2] = 1;
     } else {
         shape[1] = tx >= 16 ? 4 : 8;

@@ -653,3 +653,157 @@ def test_gauss_residual_with_filter(nreg):
     # without filtering rho the residual drifts: the filter is really there
     r_unf = O.divE(g, F) - O.rho(g, P) - (0.0 - O.rho(g, _thermal_parts(wl)))
     assert np.abs(r_unf).max() > 1e-6 * scale
+
+
+# --------------------------------------------------------------------------
+# spectral (PSATD) field update
+# --------------------------------------------------------------------------
+from oracle import psatd as PS
+
+
+def _lattice_wave(g, m, e_dir, t):
+    """Plane wave of the semi-discrete Yee-lattice equations: E = e cos(k.x_E
+    - w t), B = (k~ x e / w) cos(k.x_B - w t) with w = |k~|, k~_a = 2 sin(k_a
+    d_a / 2) / d_a, each component at its staggered position."""
+    L = [g.n[a] * g.d[a] for a in range(3)]
+    k = np.array([2 * math.pi * m[a] / L[a] if a < g.dims else 0.0 for a in range(3)])
+    kt = np.array([2 * math.sin(k[a] * g.d[a] / 2) / g.d[a] if a < g.dims else 0.0 for a in range(3)])
+    w = math.sqrt(kt @ kt)
+    e = np.array(e_dir, float)
+    e = e - kt * (kt @ e) / (kt @ kt)
+    e /= np.linalg.norm(e)
+    b = np.cross(kt, e) / w
+    nz, ny, nx = g.shape
+    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    F = g.zeros_fields()
+    for c in range(6):
+        s = PS.STAG[c]
+        ph = k[0] * (ii + 0.5 * s[0]) * g.d[0] + k[1] * (jj + 0.5 * s[1]) * g.d[1]
+        if g.dims == 3:
+            ph = ph + k[2] * (kk + 0.5 * s[2]) * g.d[2]
+        amp = e[c] if c < 3 else b[c - 3]
+        F[c] = amp * np.cos(ph - w * t)
+    F[6:9] = F[3:6]
+    return F, w
+
+
+@pytest.mark.parametrize("dims,m,e_dir,cfl", [
+    (2, (3, 2, 0), (0, 0, 1), 0.5),
+    (2, (1, 4, 0), (1, 0, 0), 3.0),      # three times the Yee Courant limit
+    (3, (2, 1, 3), (1, -1, 0.5), 2.0),
+])
+def test_psatd_vacuum_wave_exact_for_any_dt(dims, m, e_dir, cfl):
+    """The spectral step integrates the lattice equations exactly in time:
+    a lattice plane wave after n steps is the closed form at t = n dt, for a
+    time step beyond the Yee stability limit too."""
+    n = (16, 12) if dims == 2 else (8, 6, 10)
+    d = (0.1, 0.15) if dims == 2 else (0.2, 0.1, 0.15)
+    g = O.Grid(dims, n, d, cfl * WL.cfl_dt(d, frac=1.0))
+    F, w = _lattice_wave(g, m, e_dir, 0.0)
+    for _ in range(40):
+        PS.step_fields(g, F)
+    ref, _ = _lattice_wave(g, m, e_dir, 40 * g.dt)
+    assert np.abs(F[0:6] - ref[0:6]).max() < 1e-12
+
+
+def _curl_h_of(g, A):
+    """Discrete curl on the Yee lattice: A at E positions -> B positions
+    (forward differences), a divergence-free B."""
+    dx, dy, dz = g.d
+    def fwd(a, ax):
+        return (np.roll(a, -1, axis=ax) - a) / [dz, dy, dx][ax]
+    zero = np.zeros_like(A[0])
+    dAz_dy, dAy_dz = fwd(A[2], 1), (fwd(A[1], 0) if g.dims == 3 else zero)
+    dAx_dz, dAz_dx = (fwd(A[0], 0) if g.dims == 3 else zero), fwd(A[2], 2)
+    dAy_dx, dAx_dy = fwd(A[1], 2), fwd(A[0], 1)
+    return np.stack([dAz_dy - dAy_dz, dAx_dz - dAz_dx, dAy_dx - dAx_dy])
+
+
+def test_psatd_vacuum_energy_and_uniform_current():
+    """In vacuum the step is a rotation of the transverse fields: the field
+    energy is conserved exactly (for a divergence-free B); a uniform current
+    (the k = 0 mode) only changes E, by -dt J."""
+    g = O.Grid(2, (16, 16), (0.1, 0.1), 0.2)
+    rng = np.random.default_rng(11)
+    F = g.zeros_fields()
+    F[0:3] = rng.standard_normal((3,) + g.shape)
+    F[3:6] = _curl_h_of(g, rng.standard_normal((3,) + g.shape))
+    U0 = (F[0:6] ** 2).sum()
+    for _ in range(30):
+        PS.step_fields(g, F)
+    assert (F[0:6] ** 2).sum() == pytest.approx(U0, rel=1e-12)
+    G = g.zeros_fields()
+    G[9:12] = np.array([0.3, -0.2, 0.7])[:, None, None, None]
+    PS.step_fields(g, G)
+    np.testing.assert_allclose(G[0:3], -g.dt * G[9:12], atol=1e-15)
+    assert np.abs(G[3:6]).max() < 1e-15
+
+
+def test_psatd_gauss_law_with_particles():
+    """Esirkepov's current satisfies the lattice continuity equation and the
+    spectral step keeps k~.E^{n+1} = k~.E^n - dt k~.J: div E - rho stays
+    constant."""
+    wl = WL.thermal_2d(n=(16, 16), ppc=4, vth=0.1)
+    g = O.Grid(2, wl.n, wl.d, wl.dt)
+    F = g.zeros_fields()
+    P = _thermal_parts(wl)
+    r0 = O.divE(g, F) - O.rho(g, P)
+    scale = np.abs(O.rho(g, P)).max()
+    for _ in range(60):
+        PS.step(g, F, P)
+    r1 = O.divE(g, F) - O.rho(g, P)
+    assert np.abs(r1 - r0).max() <= 1e-12 * scale
+    assert np.abs(F[0:3]).max() > 1e-4 * scale       # the plasma did drive fields
+
+
+def test_psatd_matches_yee_as_dt_goes_to_zero():
+    """Both integrate the same lattice equations; Yee's leapfrog is second
+    order in dt, so the difference at a fixed time falls 4x when dt halves."""
+    g0 = O.Grid(2, (16, 16), (0.1, 0.1), 0.02)
+    rng = np.random.default_rng(5)
+    E0 = 0.1 * rng.standard_normal((3,) + g0.shape)
+    A = rng.standard_normal((3,) + g0.shape)
+    errs = []
+    for dt in (0.02, 0.01, 0.005):
+        g = O.Grid(2, (16, 16), (0.1, 0.1), dt)
+        Fp = g.zeros_fields()
+        Fp[0:3] = E0
+        Fp[3:6] = _curl_h_of(g, A) * 0.01
+        Fy = Fp.copy()
+        PS.init_fields(Fp)
+        O.init_fields(g, Fy)
+        nsteps = int(round(0.4 / dt))
+        for _ in range(nsteps):
+            PS.step_fields(g, Fp)
+            O.yee(g, Fy)
+        errs.append(np.abs(Fp[0:3] - Fy[0:3]).max())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.5 < r1 < 4.5 and 3.5 < r2 < 4.5, errs
+
+
+@pytest.mark.parametrize("longitudinal", [False, True])
+def test_psatd_response_to_a_current_mode(longitudinal):
+    """From zero fields, a current mode held over one step gives, in closed
+    form: transverse J -> E = -(sin(w dt)/w) J and B = ((1 - cos(w dt))/w^2)
+    curl_h J; longitudinal J -> E = -dt J and B = 0."""
+    g = O.Grid(2, (16, 12), (0.1, 0.15), 0.07)
+    m = (3, 2)
+    L = [g.n[a] * g.d[a] for a in range(2)]
+    k = np.array([2 * math.pi * m[0] / L[0], 2 * math.pi * m[1] / L[1], 0.0])
+    kt = np.array([2 * math.sin(k[0] * g.d[0] / 2) / g.d[0], 2 * math.sin(k[1] * g.d[1] / 2) / g.d[1], 0.0])
+    w = math.sqrt(kt @ kt)
+    e = kt / w if longitudinal else np.array([-kt[1], kt[0], 0.0]) / w
+    nz, ny, nx = g.shape
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    F = g.zeros_fields()
+    for c in range(3):
+        s = PS.STAG[c]
+        F[9 + c, 0] = e[c] * np.cos(k[0] * (ii + 0.5 * s[0]) * g.d[0] + k[1] * (jj + 0.5 * s[1]) * g.d[1])
+    J = F[9:12].copy()
+    PS.step_fields(g, F)
+    if longitudinal:
+        np.testing.assert_allclose(F[0:3], -g.dt * J, atol=1e-14)
+        assert np.abs(F[3:6]).max() < 1e-14
+    else:
+        np.testing.assert_allclose(F[0:3], -math.sin(w * g.dt) / w * J, atol=1e-14)
+        np.testing.assert_allclose(F[3:6], (1 - math.cos(w * g.dt)) / w ** 2 * _curl_h_of(g, J), atol=1e-14)

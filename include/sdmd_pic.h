@@ -67,6 +67,16 @@ extern "C" {
                               region reduction and Maxwell in FP64           */
 #define PIC_BC_PERIODIC 0
 
+/* field solvers (pic_config.field_solver) */
+#define PIC_SOLVER_YEE   0  /* Yee finite-difference leapfrog (section 3.2):
+                               state E^n, B^{n+1/2}, Bm^n                   */
+#define PIC_SOLVER_PSATD 1  /* spectral: the Yee-lattice Maxwell equations
+                               integrated exactly in time over each step in
+                               Fourier space (the spectral solvers that
+                               motivate large regions, sections 1 and 2.2):
+                               state E^n, B^n (Bm^n = B^n); one periodic
+                               region                                        */
+
 /* pic_fields component mask bits */
 #define PIC_F_EX   (1u << 0)
 #define PIC_F_EY   (1u << 1)
@@ -74,7 +84,8 @@ extern "C" {
 #define PIC_F_BX   (1u << 3)   /* Bm: B time-centred at t^n                   */
 #define PIC_F_BY   (1u << 4)
 #define PIC_F_BZ   (1u << 5)
-#define PIC_F_BHX  (1u << 6)   /* B at t^{n+1/2} (needed to resume a run)    */
+#define PIC_F_BHX  (1u << 6)   /* B at t^{n+1/2} (needed to resume a run);
+                                  B^n with PIC_SOLVER_PSATD                  */
 #define PIC_F_BHY  (1u << 7)
 #define PIC_F_BHZ  (1u << 8)
 #define PIC_F_JX   (1u << 9)   /* J at t^{n-1/2}, from the last step, as the
@@ -127,7 +138,11 @@ typedef struct {
  *   regions are rectangular, of equal shape, and made of whole patches
  *     (section 2.2, rule B): n_regions[a] >= 1 divides n_cells[a]/patch[a];
  *   shape_order is 2; bc[a] is PIC_BC_PERIODIC; m > 0;
- *   0 <= filter_passes <= 4 (2D) or 2 (3D); reserved is 0.
+ *   0 <= filter_passes <= 4 (2D) or 2 (3D);
+ *   field_solver PIC_SOLVER_PSATD: one region (n_regions all 1), every
+ *     n_cells[a] of the run a power of two <= 4096, and dt < min d[a] (the
+ *     spectral step has no Courant limit; particles still move less than a
+ *     cell per step).
  * A patch of 0 on every axis lets the library choose: it times a few steps
  * of each admissible square patch (8, 16, 32 in 2D; 4, 8 in 3D) on this
  * config and keeps the fastest (cached per grid, precision and density). */
@@ -147,7 +162,7 @@ typedef struct {
                                    pass smooths each J component with the
                                    1-2-1 kernel along x, then y, then z;
                                    at most 4 passes in 2D, 2 in 3D          */
-    int32_t reserved;           /* must be 0                                */
+    int32_t field_solver;       /* PIC_SOLVER_YEE or PIC_SOLVER_PSATD       */
     double  q, m;               /* species charge and mass; electrons -1, 1 */
     int64_t max_steps;          /* steps this run takes, 0 = unlimited: once
                                    they are done the run is left untouched by

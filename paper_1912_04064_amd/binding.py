@@ -36,6 +36,7 @@ F_BX, F_BY, F_BZ = 1 << 3, 1 << 4, 1 << 5
 F_BHX, F_BHY, F_BHZ = 1 << 6, 1 << 7, 1 << 8
 F_JX, F_JY, F_JZ = 1 << 9, 1 << 10, 1 << 11
 F_RHO = 1 << 12
+SOLVERS = {"yee": 0, "psatd": 1}
 F_E = F_EX | F_EY | F_EZ
 F_B = F_BX | F_BY | F_BZ
 F_BH = F_BHX | F_BHY | F_BHZ
@@ -61,7 +62,7 @@ class PicConfig(C.Structure):
     _fields_ = [("dims", C.c_int32), ("n_cells", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double),
                 ("patch", C.c_int32 * 3), ("n_regions", C.c_int32 * 3), ("shape_order", C.c_int32),
                 ("precision", C.c_int32), ("bc", C.c_int32 * 3), ("track_ids", C.c_int32),
-                ("filter_passes", C.c_int32), ("reserved", C.c_int32), ("q", C.c_double),
+                ("filter_passes", C.c_int32), ("field_solver", C.c_int32), ("q", C.c_double),
                 ("m", C.c_double), ("max_steps", C.c_int64), ("particles", C.POINTER(PicParticlesIn)),
                 ("fields", C.POINTER(PicFieldsIn))]
 
@@ -173,7 +174,8 @@ class _CfgHolder:
         prec = PIC_FP64 if wl.precision == "fp64" else PIC_FP32_SPLIT
         self.cfg = PicConfig(dims, (C.c_int32 * 3)(*nc[:3]), (C.c_double * 3)(*d[:3]), wl.dt,
                              (C.c_int32 * 3)(*pt[:3]), (C.c_int32 * 3)(*nr[:3]), 2, prec, (C.c_int32 * 3)(0, 0, 0),
-                             1 if track_ids else 0, int(wl.filter), 0, wl.q, wl.m, int(max_steps),
+                             1 if track_ids else 0, int(wl.filter), SOLVERS[wl.solver], wl.q, wl.m,
+                             int(max_steps),
                              C.pointer(self.pin),
                              C.pointer(self.fin) if self.fin is not None else C.POINTER(PicFieldsIn)())
 

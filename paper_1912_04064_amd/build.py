@@ -22,7 +22,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsdmd.so")
-SOURCES = ["k_push.hip", "k_fields.hip", "k_particles.hip", "host.cpp"]
+SOURCES = ["k_push.hip", "k_fields.hip", "k_particles.hip", "k_spectral.hip", "host.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -68,6 +68,7 @@ struct FieldClass {
     bool split;
     int tx;      // Yee tile x extent
     bool filt;   // runs with the binomial current filter
+    int solver;  // PIC_SOLVER_*
     std::vector<int4> hy, hp;
     std::vector<int> slots;
     int4 *dy = nullptr, *dp = nullptr;
@@ -217,10 +218,22 @@ static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::st
         inv2 += 1.0 / (cfg->d[a] * cfg->d[a]);
     }
     if (dims == 2 && cfg->n_cells[2] != 1) return fail("n_cells[2] must be 1 in 2D");
-    if (!(cfg->dt > 0) || !(cfg->dt < 1.0 / std::sqrt(inv2))) return fail("dt must satisfy 0 < dt < 1/sqrt(sum 1/d^2)");
+    if (cfg->field_solver != PIC_SOLVER_YEE && cfg->field_solver != PIC_SOLVER_PSATD) return fail("unknown field solver");
+    if (cfg->field_solver == PIC_SOLVER_YEE) {
+        if (!(cfg->dt > 0) || !(cfg->dt < 1.0 / std::sqrt(inv2)))
+            return fail("dt must satisfy 0 < dt < 1/sqrt(sum 1/d^2)");
+    } else {
+        double dmin = cfg->d[0];
+        for (int a = 1; a < dims; ++a) dmin = std::min(dmin, cfg->d[a]);
+        if (!(cfg->dt > 0) || !(cfg->dt < dmin)) return fail("spectral solver: dt must satisfy 0 < dt < min d");
+        for (int a = 0; a < dims; ++a) {
+            const int n = cfg->n_cells[a];
+            if (n > 4096 || (n & (n - 1)) != 0) return fail("spectral solver: n_cells must be powers of two <= 4096");
+            if (cfg->n_regions[a] != 1) return fail("spectral solver: one region");
+        }
+    }
     if (cfg->filter_passes < 0 || cfg->filter_passes > (dims == 2 ? 4 : 2))
         return fail("filter_passes must be 0..4 in 2D, 0..2 in 3D");
-    if (cfg->reserved != 0) return fail("reserved must be 0");
     const int pmax = dims == 2 ? 32 : 8;
     L.dims = dims;
     L.split = cfg->precision == PIC_FP32_SPLIT;
@@ -283,6 +296,7 @@ static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::st
     b += 6 * align256((size_t)(L.n_patch + 1) * 4) + 7 * align256((size_t)(L.seg_max + 1) * 4);
     b += 2 * (size_t)L.cap_total * per + align256((size_t)L.cap_total * 4);
     b += 2 * (size_t)std::max<long long>(L.n_total, 1) * (per + 4);
+    if (cfg->field_solver == PIC_SOLVER_PSATD) b += align256((size_t)9 * ncell * 16);
     b += 64 * 256;   // per-array rounding and the control block
     L.bytes = b;
     return PIC_OK;
@@ -506,6 +520,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     d.dims = L.dims;
     d.prec = cfg->precision;
     d.filter = cfg->filter_passes;
+    d.solver = cfg->field_solver;
     for (int a = 0; a < 3; ++a) {
         d.n[a] = L.n[a];
         d.P[a] = L.P[a];
@@ -569,6 +584,11 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     d.nlv = (int *)run_alloc(c, r, sb);
     d.tflag = (int *)run_alloc(c, r, sb);
     ok = ok && d.lpatch && d.spatch && d.lopatch && d.nlv && d.tflag;
+    d.spec = nullptr;
+    if (d.solver == PIC_SOLVER_PSATD) {
+        d.spec = (double2 *)run_alloc(c, r, (size_t)9 * r.ncell * 16);
+        ok = ok && d.spec;
+    }
     r.bytes = 0;
     for (auto &b : r.bufs) r.bytes += b.bytes;
     if (!ok) {
@@ -613,14 +633,21 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
             return PIC_OK;
         };
         if ((rc = up(f->E, f_E(par)))) return rc;
-        if ((rc = up(f->B, f_B(par)))) return rc;
-        if (f->kind == 1) {
-            if ((rc = up(f->Bm ? f->Bm : f->B, F_BM))) return rc;
+        if (r.rd.solver == PIC_SOLVER_PSATD) {
+            // E and B at the same time: B^n = B^0 (kind 0) or Bm^n (kind 1)
+            const double *Bn = (f->kind == 1 && f->Bm) ? f->Bm : f->B;
+            if ((rc = up(Bn, f_B(par)))) return rc;
+            if ((rc = up(Bn, F_BM))) return rc;
+        } else {
+            if ((rc = up(f->B, f_B(par)))) return rc;
+            if (f->kind == 1) {
+                if ((rc = up(f->Bm ? f->Bm : f->B, F_BM))) return rc;
+            }
         }
         dev_free(c, sb);
         HIPCHK(c, launch_ghosts(c->d_runs, slot, r.total_ghosts, f_E(par), 3, s));
         HIPCHK(c, launch_ghosts(c->d_runs, slot, r.total_ghosts, f_B(par), 3, s));
-        if (f->kind == 0) HIPCHK(c, launch_half_faraday(c->d_runs, slot, ncell, par, s));
+        if (f->kind == 0 && r.rd.solver != PIC_SOLVER_PSATD) HIPCHK(c, launch_half_faraday(c->d_runs, slot, ncell, par, s));
         HIPCHK(c, launch_ghosts(c->d_runs, slot, r.total_ghosts, f_B(par), 3, s));
         HIPCHK(c, launch_ghosts(c->d_runs, slot, r.total_ghosts, F_BM, 3, s));
     }
@@ -710,9 +737,10 @@ static int rebuild_items(pic_ctx *c)
         const int ytx = yee_tile_x(r.dims, r.rd.rs[0], filt);
         FieldClass *fc = nullptr;
         for (auto &x : c->fcls)
-            if (x.dims == r.dims && x.split == r.split && x.tx == ytx && x.filt == filt) fc = &x;
+            if (x.dims == r.dims && x.split == r.split && x.tx == ytx && x.filt == filt && x.solver == r.rd.solver)
+                fc = &x;
         if (!fc) {
-            c->fcls.push_back(FieldClass{r.dims, r.split, ytx, filt});
+            c->fcls.push_back(FieldClass{r.dims, r.split, ytx, filt, r.rd.solver});
             fc = &c->fcls.back();
         }
         const RunDev &d = r.rd;
@@ -769,6 +797,11 @@ static hipError_t enqueue_yee(pic_ctx *c, int par, hipStream_t s)
     for (auto &fc : c->fcls) {
         hipError_t e = launch_yee(fc.dims, fc.split, fc.tx, fc.filt, c->d_runs, fc.dy, (int)fc.hy.size(), par, s);
         if (e != hipSuccess) return e;
+        if (fc.solver == PIC_SOLVER_PSATD)
+            for (int slot : fc.slots) {
+                e = launch_spectral(c->d_runs, slot, c->runs[slot].rd.dims, c->runs[slot].rd.n, par, s);
+                if (e != hipSuccess) return e;
+            }
     }
     return hipSuccess;
 }

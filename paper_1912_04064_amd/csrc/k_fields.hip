@@ -290,6 +290,16 @@ __global__ __launch_bounds__((YeeTile<DIM, TXC>::NT)) void yee_kernel(const RunD
             gather_J<DIM, AXM, R>(rd, tiles, gb, s_ax, s_rng, hx, hy, hz, J);
         }
         const long long p = rindex(rd, li, lj, DIM == 3 ? lk : 0);
+        if (rd.solver) {
+            // spectral solver: this kernel only provides J (the tiles' sum,
+            // filtered); E and B are advanced in Fourier space
+            if (hx < TX && hy < TY && (DIM == 2 || hz < TZ) && li < rs0 && lj < rs1 && (DIM == 2 || lk < rs2)) {
+                Jr[0][p] = J[0];
+                Jr[1][p] = J[1];
+                Jr[2][p] = J[2];
+            }
+            continue;
+        }
         double e0, e1, e2;
         if constexpr (DIM == 2) {
             e0 = Eo[0][p] + dt * ((Bo[2][p] - Bo[2][p - sy]) / dy - J[0]);
@@ -312,6 +322,7 @@ __global__ __launch_bounds__((YeeTile<DIM, TXC>::NT)) void yee_kernel(const RunD
             Jr[2][p] = J[2];
         }
     }
+    if (rd.solver) return;
     __syncthreads();
 
     // phase 2: Faraday and Bm on the tile

@@ -1,0 +1,214 @@
+// k_spectral.hip -- the spectral (PSATD) field phase of one step, for runs
+// with one periodic region and power-of-two grids.
+//
+// The field kernel has already summed the patch tiles into the region's J
+// (transfer (i) of section 2.2, and the current filter).  Then:
+//   pack     region E^n, B^n, J -> 9 complex arrays of the grid;
+//   fft      1D transforms along x, y (, z), one workgroup per grid line,
+//            the line held in LDS (iterative radix-2, bit-reversed load);
+//   kspace   per wavevector: move each component to its staggered position
+//            (phase e^{-i k.s}), advance E, B exactly over dt with J held at
+//            J^{n+1/2} (equations below), move back;
+//   ifft     inverse transforms of E, B;
+//   unpack   real parts / (nx ny nz) -> E^{n+1}, B^{n+1} and Bm^{n+1} =
+//            B^{n+1} in the other E/B buffer; the post kernel exchanges the
+//            ghost layers as for the Yee update.
+// With the lattice wavenumber k~_a = 2 sin(k_a d_a / 2) / d_a, w = |k~|,
+// kappa = k~ / w, C = cos(w dt), S = sin(w dt):
+//   E' = C E + (1 - C) kappa (kappa.E) + i S kappa x B - (S/w) J
+//        + kappa (kappa.J) (S/w - dt)
+//   B' = C B - i S kappa x E + i ((1 - C)/w) kappa x J
+// (w = 0: E' = E - dt J, B' = B): the exact solution of the Yee-lattice
+// Maxwell equations over one step, so the discrete Gauss law kept by the
+// Esirkepov deposition is kept here too.
+#include "launch.h"
+#include "sdmd_dev.h"
+
+namespace sdmd {
+
+constexpr int FFT_MAX = 4096;   // longest transform line (LDS: 64 KB of complex FP64)
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// staggering of E (0..2), B (3..5), J (6..8): 1 = half-integer position
+__device__ __forceinline__ int stag(int comp, int a)
+{
+    const int c = comp % 3;
+    if (comp < 3 || comp >= 6) return c == a ? 1 : 0;   // E, J: along their own axis
+    return c == a ? 0 : 1;                               // B: across the other two
+}
+
+// region <-> grid arrays (one region of the run: its interior is the grid)
+__global__ void spec_pack_kernel(const RunDev *__restrict__ runs, int run, int par)
+{
+    const RunDev &rd = runs[run];
+    if (rd.ctl->remaining[par] == 0) return;
+    const long long ncell = (long long)rd.n[0] * rd.n[1] * rd.n[2];
+    const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (gid >= ncell) return;
+    const int i = (int)(gid % rd.n[0]), j = (int)((gid / rd.n[0]) % rd.n[1]), k = (int)(gid / ((long long)rd.n[0] * rd.n[1]));
+    const long long p = rindex(rd, i, j, k);
+    const int src[9] = {f_E(par), f_E(par) + 1, f_E(par) + 2, f_B(par), f_B(par) + 1, f_B(par) + 2, F_J, F_J + 1, F_J + 2};
+#pragma unroll
+    for (int c = 0; c < 9; ++c) rd.spec[c * ncell + gid] = make_double2(rcomp(rd, 0, src[c])[p], 0.0);
+}
+
+__global__ void spec_unpack_kernel(const RunDev *__restrict__ runs, int run, int par)
+{
+    const RunDev &rd = runs[run];
+    if (rd.ctl->remaining[par] == 0) return;
+    const long long ncell = (long long)rd.n[0] * rd.n[1] * rd.n[2];
+    const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (gid >= ncell) return;
+    const int i = (int)(gid % rd.n[0]), j = (int)((gid / rd.n[0]) % rd.n[1]), k = (int)(gid / ((long long)rd.n[0] * rd.n[1]));
+    const long long p = rindex(rd, i, j, k);
+    const double inv = 1.0 / (double)ncell;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        rcomp(rd, 0, f_E(1 - par) + c)[p] = rd.spec[c * ncell + gid].x * inv;
+        const double b = rd.spec[(3 + c) * ncell + gid].x * inv;
+        rcomp(rd, 0, f_B(1 - par) + c)[p] = b;
+        rcomp(rd, 0, F_BM + c)[p] = b;
+    }
+}
+
+// 1D transforms of length N = n[axis] along `axis` of components [c0, c0+nc)
+// of the grid arrays; sign -1 forward, +1 inverse (unscaled).  Grid: x = line,
+// y = component.
+__global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restrict__ runs, int run, int par, int axis,
+                                                         int c0, int sign)
+{
+    __shared__ double2 buf[FFT_MAX];
+    const RunDev &rd = runs[run];
+    if (rd.ctl->remaining[par] == 0) return;
+    const int n0 = rd.n[0], n1 = rd.n[1], n2 = rd.n[2];
+    const long long ncell = (long long)n0 * n1 * n2;
+    const int N = rd.n[axis];
+    const long long lines = ncell / N;
+    const long long line = blockIdx.x;
+    if (line >= lines || N > FFT_MAX) return;
+    long long o, stride;
+    if (axis == 0) {
+        o = line * n0;
+        stride = 1;
+    } else if (axis == 1) {
+        o = (line % n0) + (line / n0) * (long long)n0 * n1;
+        stride = n0;
+    } else {
+        o = line;
+        stride = (long long)n0 * n1;
+    }
+    double2 *a = rd.spec + (long long)(c0 + blockIdx.y) * ncell + o;
+    int logn = 0;
+    while ((1 << logn) < N) ++logn;
+    const int tid = threadIdx.x;
+    for (int j = tid; j < N; j += BLOCK) {
+        const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
+        buf[r] = a[j * stride];
+    }
+    __syncthreads();
+    for (int len = 2; len <= N; len <<= 1) {
+        const int half = len >> 1;
+        for (int t = tid; t < N / 2; t += BLOCK) {
+            const int pos = t % half, i = (t / half) * len + pos;
+            double s, c;
+            sincospi((double)(sign * 2 * pos) / (double)len, &s, &c);
+            const double2 u = buf[i], v = cmul(buf[i + half], make_double2(c, s));
+            buf[i] = make_double2(u.x + v.x, u.y + v.y);
+            buf[i + half] = make_double2(u.x - v.x, u.y - v.y);
+        }
+        __syncthreads();
+    }
+    for (int j = tid; j < N; j += BLOCK) a[j * stride] = buf[j];
+}
+
+// exact step of every wavevector
+__global__ void spec_kspace_kernel(const RunDev *__restrict__ runs, int run, int par)
+{
+    const RunDev &rd = runs[run];
+    if (rd.ctl->remaining[par] == 0) return;
+    const long long ncell = (long long)rd.n[0] * rd.n[1] * rd.n[2];
+    const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (gid >= ncell) return;
+    const int idx[3] = {(int)(gid % rd.n[0]), (int)((gid / rd.n[0]) % rd.n[1]),
+                        (int)(gid / ((long long)rd.n[0] * rd.n[1]))};
+    double k[3] = {0, 0, 0}, kt[3] = {0, 0, 0};
+    for (int a = 0; a < rd.dims; ++a) {
+        const int m = idx[a] < (rd.n[a] + 1) / 2 ? idx[a] : idx[a] - rd.n[a];   // signed frequency
+        k[a] = 2.0 * M_PI * (double)m / rd.L[a];
+        kt[a] = 2.0 * sin(0.5 * k[a] * rd.d[a]) / rd.d[a];
+    }
+    // fields at their physical (staggered) positions
+    double2 F[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        double ph = 0.0;
+        for (int a = 0; a < rd.dims; ++a) ph += k[a] * 0.5 * stag(c, a) * rd.d[a];
+        double s, co;
+        sincos(-ph, &s, &co);
+        F[c] = cmul(rd.spec[c * ncell + gid], make_double2(co, s));
+    }
+    const double dt = rd.dt;
+    const double w = sqrt(kt[0] * kt[0] + kt[1] * kt[1] + kt[2] * kt[2]);
+    double2 En[3], Bn[3];
+    if (w == 0.0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            En[c] = make_double2(F[c].x - dt * F[6 + c].x, F[c].y - dt * F[6 + c].y);
+            Bn[c] = F[3 + c];
+        }
+    } else {
+        const double kap[3] = {kt[0] / w, kt[1] / w, kt[2] / w};
+        const double C = cos(w * dt), S = sin(w * dt), Sw = S / w, C1w = (1.0 - C) / w;
+        double2 kE = make_double2(0, 0), kJ = make_double2(0, 0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            kE.x += kap[a] * F[a].x;
+            kE.y += kap[a] * F[a].y;
+            kJ.x += kap[a] * F[6 + a].x;
+            kJ.y += kap[a] * F[6 + a].y;
+        }
+        auto crossc = [&](int b0, int c) -> double2 {   // (kappa x F[b0..b0+2])_c
+            const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+            return make_double2(kap[c1] * F[b0 + c2].x - kap[c2] * F[b0 + c1].x,
+                                kap[c1] * F[b0 + c2].y - kap[c2] * F[b0 + c1].y);
+        };
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double2 xB = crossc(3, c), xE = crossc(0, c), xJ = crossc(6, c);
+            // i * z = (-z.y, z.x)
+            En[c].x = C * F[c].x + (1.0 - C) * kap[c] * kE.x - S * xB.y - Sw * F[6 + c].x + kap[c] * kJ.x * (Sw - dt);
+            En[c].y = C * F[c].y + (1.0 - C) * kap[c] * kE.y + S * xB.x - Sw * F[6 + c].y + kap[c] * kJ.y * (Sw - dt);
+            Bn[c].x = C * F[3 + c].x + S * xE.y - C1w * xJ.y;
+            Bn[c].y = C * F[3 + c].y - S * xE.x + C1w * xJ.x;
+        }
+    }
+    // back to the grid positions
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        double ph = 0.0;
+        for (int a = 0; a < rd.dims; ++a) ph += k[a] * 0.5 * stag(c, a) * rd.d[a];
+        double s, co;
+        sincos(ph, &s, &co);
+        rd.spec[c * ncell + gid] = cmul(c < 3 ? En[c] : Bn[c - 3], make_double2(co, s));
+    }
+}
+
+hipError_t launch_spectral(const RunDev *runs, int run, int dims, const int n[3], int par, hipStream_t s)
+{
+    const long long ncell = (long long)n[0] * n[1] * n[2];
+    const unsigned nb = (unsigned)((ncell + BLOCK - 1) / BLOCK);
+    spec_pack_kernel<<<nb, BLOCK, 0, s>>>(runs, run, par);
+    for (int a = 0; a < dims; ++a)
+        spec_fft_kernel<<<dim3((unsigned)(ncell / n[a]), 9), BLOCK, 0, s>>>(runs, run, par, a, 0, -1);
+    spec_kspace_kernel<<<nb, BLOCK, 0, s>>>(runs, run, par);
+    for (int a = 0; a < dims; ++a)
+        spec_fft_kernel<<<dim3((unsigned)(ncell / n[a]), 6), BLOCK, 0, s>>>(runs, run, par, a, 0, +1);
+    spec_unpack_kernel<<<nb, BLOCK, 0, s>>>(runs, run, par);
+    return hipGetLastError();
+}
+
+}  // namespace sdmd

@@ -21,6 +21,11 @@ void yee_tile_shape(int dims, int tx, int shape[3]);
 hipError_t launch_yee(int dims, bool split, int tx, bool filt, const RunDev *runs, const int4 *items, int n_items,
                       int par, hipStream_t s);
 
+// spectral (PSATD) field phase of one run: pack, transforms, exact k-space
+// step, inverse transforms, unpack into the other E/B buffer (the field
+// kernel has already written J)
+hipError_t launch_spectral(const RunDev *runs, int run, int dims, const int n[3], int par, hipStream_t s);
+
 // ghost synchronisation of the new fields + insertion of the leavers:
 // items (run, kind, a, b); kind 0 ghost chunk starting at a, kind 1 insert
 // block a of b

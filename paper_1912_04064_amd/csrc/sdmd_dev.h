@@ -118,6 +118,7 @@ struct RunDev {
     int ins_segs;        // segments per leaver-insert workgroup
     int ghosts;          // ghost nodes per region
     int filter;          // binomial current filter passes (0 = off)
+    int solver;          // 0 Yee, 1 spectral (PSATD)
     double d[3], L[3];
     double dt, q, m;
     double qmh;          // (q/m) dt/2
@@ -137,6 +138,7 @@ struct RunDev {
     int *lpatch, *spatch;
     int *nlv;            // [seg_max] leavers of each segment this step, in lv at sseg[s]
     int *tflag;          // [seg_max] 1 when the segment's tile in HBM may hold non-zero values
+    double2 *spec;       // spectral solver: 9 complex arrays [E, B, J][z][y][x] of the grid
     Store lo;            // overflow leavers (parked particles re-entering)
     int *lopatch;
     Ctl *ctl;

@@ -58,6 +58,7 @@ class Workload:
     m: float = 1.0
     seed: int = 0
     filter: int = 0               # binomial current filter passes (0 = off)
+    solver: str = "yee"           # field solver: "yee" or "psatd"
 
     @property
     def n_particles(self) -> int:

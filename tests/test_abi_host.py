@@ -47,6 +47,10 @@ def _cfg(**over):
     (dict(dt=1.0), "dt must satisfy"),
     (dict(nreg=(3, 1)), "whole patches"),
     (dict(dims=4), "dims must be 2 or 3"),
+    (dict(filter=5), "filter_passes"),
+    (dict(solver="psatd", nreg=(2, 1)), "one region"),
+    (dict(solver="psatd", n=(48, 32)), "powers of two"),
+    (dict(solver="psatd", dt=0.2), "dt must satisfy 0 < dt < min d"),
 ])
 def test_config_validation(change, msg):
     wl = _cfg(**change)
@@ -54,6 +58,15 @@ def test_config_validation(change, msg):
         B.mem_bytes(wl)
     assert e.value.code == B.PIC_E_CONFIG
     assert msg in str(e.value)
+
+
+def test_spectral_solver_accepts_dt_beyond_the_yee_limit():
+    """The spectral step has no Courant limit; dt only has to keep particles
+    under a cell per step (dt < min d)."""
+    wl = _cfg(solver="psatd", dt=0.09)      # Yee limit here: 0.1/sqrt(2) = 0.0707
+    assert B.mem_bytes(wl) > B.mem_bytes(_cfg())
+    with pytest.raises(B.PicError):
+        B.mem_bytes(_cfg(dt=0.09))
 
 
 def test_mem_bytes_scales_with_particles():

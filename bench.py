@@ -33,6 +33,9 @@ def workload(name):
         return WL.lwfa_2d()
     if name == "lwfa64":
         return WL.lwfa_2d(precision="fp64")
+    if name == "lwfa_psatd":
+        import dataclasses
+        return dataclasses.replace(WL.lwfa_2d(nreg=(1, 1)), solver="psatd", name="lwfa2048x256_psatd")
     if name == "thermal64":
         return WL.thermal_2d()
     if name == "thermal2k":
@@ -287,7 +290,8 @@ def main():
         "dtype": "f32+f64" if wl.precision == "fp32s" else "f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "cells": list(wl.n), "particles": N, "patch": list(d["patch"][:wl.dims]),
-                   "regions": list(wl.nreg), "precision": wl.precision, "graph": not args.no_graph},
+                   "regions": list(wl.nreg), "precision": wl.precision, "solver": wl.solver, "filter": wl.filter,
+                   "graph": not args.no_graph},
         "step_hbm_GBps_algorithmic": step_bytes / (ms * 1e-3) / 1e9,
         "phase_ms": {"particles": push_avg, "reduce_maxwell": float(np.mean(yee_ms)),
                      "sync_rebin": float(np.mean(post_ms))},

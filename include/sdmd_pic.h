@@ -98,8 +98,6 @@ extern "C" {
 /* pic_runtime.flags */
 #define PIC_RT_NO_GRAPH   (1 << 0)  /* launch kernels one by one instead of
                                        replaying a captured hipGraph          */
-#define PIC_RT_PERSISTENT (1 << 1)  /* particle phase as one persistent launch
-                                       with work stealing over patches        */
 
 typedef struct pic_ctx pic_ctx;
 

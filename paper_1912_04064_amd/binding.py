@@ -29,7 +29,6 @@ PIC_E_STATE = -7
 PIC_FP64 = 0
 PIC_FP32_SPLIT = 1
 PIC_RT_NO_GRAPH = 1
-PIC_RT_PERSISTENT = 2
 
 F_EX, F_EY, F_EZ = 1 << 0, 1 << 1, 1 << 2
 F_BX, F_BY, F_BZ = 1 << 3, 1 << 4, 1 << 5

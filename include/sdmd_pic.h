@@ -138,7 +138,7 @@ typedef struct {
  *   shape_order is 2; bc[a] is PIC_BC_PERIODIC; m > 0;
  *   0 <= filter_passes <= 4 (2D) or 2 (3D);
  *   field_solver PIC_SOLVER_PSATD: one region (n_regions all 1), every
- *     n_cells[a] of the run a power of two <= 4096, and dt < min d[a] (the
+ *     n_cells[a] of the run a power of two <= 2048, and dt < min d[a] (the
  *     spectral step has no Courant limit; particles still move less than a
  *     cell per step).
  * A patch of 0 on every axis lets the library choose: it times a few steps

@@ -228,7 +228,7 @@ static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::st
         if (!(cfg->dt > 0) || !(cfg->dt < dmin)) return fail("spectral solver: dt must satisfy 0 < dt < min d");
         for (int a = 0; a < dims; ++a) {
             const int n = cfg->n_cells[a];
-            if (n > 4096 || (n & (n - 1)) != 0) return fail("spectral solver: n_cells must be powers of two <= 4096");
+            if (n > 2048 || (n & (n - 1)) != 0) return fail("spectral solver: n_cells must be powers of two <= 2048");
             if (cfg->n_regions[a] != 1) return fail("spectral solver: one region");
         }
     }

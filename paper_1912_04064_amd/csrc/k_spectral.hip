@@ -26,7 +26,7 @@
 
 namespace sdmd {
 
-constexpr int FFT_MAX = 4096;   // longest transform line (LDS: 64 KB of complex FP64)
+constexpr int FFT_MAX = 2048;   // longest transform line
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
@@ -76,53 +76,97 @@ __global__ void spec_unpack_kernel(const RunDev *__restrict__ runs, int run, int
 }
 
 // 1D transforms of length N = n[axis] along `axis` of components [c0, c0+nc)
-// of the grid arrays; sign -1 forward, +1 inverse (unscaled).  Grid: x = line,
-// y = component.
+// of the grid arrays; sign -1 forward, +1 inverse (unscaled).  A workgroup
+// transforms NL = max(1, FFT_BATCH / N) lines held in LDS (iterative
+// radix-2, bit-reversed load, one twiddle table per workgroup).  Lines along
+// y or z are taken NL adjacent in x, so every row of the batch is a
+// contiguous read.  Grid: x = batch of lines, y = component.
+constexpr int FFT_BATCH = 2048;   // complex values per workgroup: 32 KB of LDS + the twiddles
+
+__host__ __device__ inline int fft_lines_per_group(int N, int axis, const int n[3])
+{
+    int nl = N >= FFT_BATCH ? 1 : FFT_BATCH / N;
+    const int avail = axis == 0 ? n[1] * n[2] : n[0];
+    while (nl > avail) nl >>= 1;
+    return nl;
+}
+
 __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restrict__ runs, int run, int par, int axis,
                                                          int c0, int sign)
 {
-    __shared__ double2 buf[FFT_MAX];
+    extern __shared__ double2 sm[];
     const RunDev &rd = runs[run];
     if (rd.ctl->remaining[par] == 0) return;
     const int n0 = rd.n[0], n1 = rd.n[1], n2 = rd.n[2];
     const long long ncell = (long long)n0 * n1 * n2;
     const int N = rd.n[axis];
-    const long long lines = ncell / N;
-    const long long line = blockIdx.x;
-    if (line >= lines || N > FFT_MAX) return;
-    long long o, stride;
+    if (N > FFT_MAX) return;
+    const int NL = fft_lines_per_group(N, axis, rd.n);
+    const long long groups = ncell / N / NL;
+    const long long gidx = blockIdx.x;
+    if (gidx >= groups) return;
+    double2 *buf = sm, *tw = sm + NL * N;
+    // first line of the group and the offset between its lines
+    long long o, stride, lstep;
     if (axis == 0) {
-        o = line * n0;
+        o = gidx * NL * (long long)n0;
         stride = 1;
+        lstep = n0;
     } else if (axis == 1) {
-        o = (line % n0) + (line / n0) * (long long)n0 * n1;
+        const long long first = gidx * NL;                      // lines enumerate (x, z), x fastest
+        o = (first % n0) + (first / n0) * (long long)n0 * n1;
         stride = n0;
+        lstep = 1;
     } else {
-        o = line;
+        o = gidx * NL;                                          // lines enumerate (x, y), x fastest
         stride = (long long)n0 * n1;
+        lstep = 1;
     }
     double2 *a = rd.spec + (long long)(c0 + blockIdx.y) * ncell + o;
     int logn = 0;
     while ((1 << logn) < N) ++logn;
     const int tid = threadIdx.x;
-    for (int j = tid; j < N; j += BLOCK) {
+    for (int k = tid; k < N / 2; k += BLOCK) {
+        double sn, cs;
+        sincospi((double)(sign * 2 * k) / (double)N, &sn, &cs);
+        tw[k] = make_double2(cs, sn);
+    }
+    const int tot = NL * N;
+    for (int e = tid; e < tot; e += BLOCK) {
+        int l, j;
+        if (axis == 0) {
+            j = e % N;
+            l = e / N;
+        } else {
+            l = e % NL;
+            j = e / NL;
+        }
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
-        buf[r] = a[j * stride];
+        buf[l * N + r] = a[l * lstep + j * stride];
     }
     __syncthreads();
     for (int len = 2; len <= N; len <<= 1) {
-        const int half = len >> 1;
-        for (int t = tid; t < N / 2; t += BLOCK) {
-            const int pos = t % half, i = (t / half) * len + pos;
-            double s, c;
-            sincospi((double)(sign * 2 * pos) / (double)len, &s, &c);
-            const double2 u = buf[i], v = cmul(buf[i + half], make_double2(c, s));
+        const int half = len >> 1, step = N / len;
+        for (int t = tid; t < tot / 2; t += BLOCK) {
+            const int l = t / (N / 2), b = t - l * (N / 2);
+            const int pos = b % half, i = l * N + (b / half) * len + pos;
+            const double2 u = buf[i], v = cmul(buf[i + half], tw[pos * step]);
             buf[i] = make_double2(u.x + v.x, u.y + v.y);
             buf[i + half] = make_double2(u.x - v.x, u.y - v.y);
         }
         __syncthreads();
     }
-    for (int j = tid; j < N; j += BLOCK) a[j * stride] = buf[j];
+    for (int e = tid; e < tot; e += BLOCK) {
+        int l, j;
+        if (axis == 0) {
+            j = e % N;
+            l = e / N;
+        } else {
+            l = e % NL;
+            j = e / NL;
+        }
+        a[l * lstep + j * stride] = buf[l * N + j];
+    }
 }
 
 // exact step of every wavevector
@@ -141,15 +185,25 @@ __global__ void spec_kspace_kernel(const RunDev *__restrict__ runs, int run, int
         k[a] = 2.0 * M_PI * (double)m / rd.L[a];
         kt[a] = 2.0 * sin(0.5 * k[a] * rd.d[a]) / rd.d[a];
     }
-    // fields at their physical (staggered) positions
+    // fields at their physical (staggered) positions: a component shifted
+    // by half a cell along axis a picks up e^{-i k_a d_a / 2}
+    double2 hs[3] = {make_double2(1, 0), make_double2(1, 0), make_double2(1, 0)};
+    for (int a = 0; a < rd.dims; ++a) {
+        double sn, cs;
+        sincos(0.5 * k[a] * rd.d[a], &sn, &cs);
+        hs[a] = make_double2(cs, sn);                           // e^{+i k_a d_a / 2}
+    }
+    auto shift = [&](int c) {                                   // e^{+i k.s_c}
+        double2 z = make_double2(1, 0);
+        for (int a = 0; a < rd.dims; ++a)
+            if (stag(c, a)) z = cmul(z, hs[a]);
+        return z;
+    };
     double2 F[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
-        double ph = 0.0;
-        for (int a = 0; a < rd.dims; ++a) ph += k[a] * 0.5 * stag(c, a) * rd.d[a];
-        double s, co;
-        sincos(-ph, &s, &co);
-        F[c] = cmul(rd.spec[c * ncell + gid], make_double2(co, s));
+        const double2 z = shift(c);
+        F[c] = cmul(rd.spec[c * ncell + gid], make_double2(z.x, -z.y));
     }
     const double dt = rd.dt;
     const double w = sqrt(kt[0] * kt[0] + kt[1] * kt[1] + kt[2] * kt[2]);
@@ -188,13 +242,7 @@ __global__ void spec_kspace_kernel(const RunDev *__restrict__ runs, int run, int
     }
     // back to the grid positions
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        double ph = 0.0;
-        for (int a = 0; a < rd.dims; ++a) ph += k[a] * 0.5 * stag(c, a) * rd.d[a];
-        double s, co;
-        sincos(ph, &s, &co);
-        rd.spec[c * ncell + gid] = cmul(c < 3 ? En[c] : Bn[c - 3], make_double2(co, s));
-    }
+    for (int c = 0; c < 6; ++c) rd.spec[c * ncell + gid] = cmul(c < 3 ? En[c] : Bn[c - 3], shift(c));
 }
 
 hipError_t launch_spectral(const RunDev *runs, int run, int dims, const int n[3], int par, hipStream_t s)
@@ -202,11 +250,14 @@ hipError_t launch_spectral(const RunDev *runs, int run, int dims, const int n[3]
     const long long ncell = (long long)n[0] * n[1] * n[2];
     const unsigned nb = (unsigned)((ncell + BLOCK - 1) / BLOCK);
     spec_pack_kernel<<<nb, BLOCK, 0, s>>>(runs, run, par);
-    for (int a = 0; a < dims; ++a)
-        spec_fft_kernel<<<dim3((unsigned)(ncell / n[a]), 9), BLOCK, 0, s>>>(runs, run, par, a, 0, -1);
+    auto fft = [&](int a, int ncomp, int sign) {
+        const int nl = fft_lines_per_group(n[a], a, n);
+        const size_t lds = ((size_t)nl * n[a] + n[a] / 2) * sizeof(double2);
+        spec_fft_kernel<<<dim3((unsigned)(ncell / n[a] / nl), ncomp), BLOCK, lds, s>>>(runs, run, par, a, 0, sign);
+    };
+    for (int a = 0; a < dims; ++a) fft(a, 9, -1);
     spec_kspace_kernel<<<nb, BLOCK, 0, s>>>(runs, run, par);
-    for (int a = 0; a < dims; ++a)
-        spec_fft_kernel<<<dim3((unsigned)(ncell / n[a]), 6), BLOCK, 0, s>>>(runs, run, par, a, 0, +1);
+    for (int a = 0; a < dims; ++a) fft(a, 6, +1);
     spec_unpack_kernel<<<nb, BLOCK, 0, s>>>(runs, run, par);
     return hipGetLastError();
 }

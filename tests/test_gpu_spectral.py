@@ -121,3 +121,20 @@ def test_spectral_gauss_law_on_gpu_data():
     scale = np.abs(r0).max()
     say(f"gauss residual: {np.abs(divE - (r1 - r0)).max() / scale:.3e}")
     assert np.abs(divE - (r1 - r0)).max() < 1e-11 * scale
+
+
+def test_spectral_and_yee_runs_in_one_batch():
+    """A spectral run and a Yee run stepped together (separate field classes
+    in one context) give what each gives alone."""
+    say("case: batch spectral + yee")
+    a = dataclasses.replace(WL.thermal_2d(n=(64, 32), ppc=4, vth=0.05, patch=(8, 8), precision="fp64"),
+                            solver="psatd", dt=0.09)
+    b = WL.thermal_2d(n=(32, 32), ppc=4, vth=0.05, patch=(8, 8), precision="fp64")
+    with B.Context([a, b]) as ctx:
+        ctx.step(5)
+        Fa, Fb = ctx.fields(0, MASK), ctx.fields(1, MASK)
+    for wl, F in ((a, Fa), (b, Fb)):
+        with B.Context([wl]) as ctx:
+            ctx.step(5)
+            G = ctx.fields(0, MASK)
+        assert np.abs(F - G).max() <= 1e-12 * max(np.abs(G).max(), 1e-30)

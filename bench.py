@@ -68,20 +68,31 @@ def push_traffic(wl_name):
     """HBM bytes per particle-kernel launch from the committed FETCH_SIZE /
     WRITE_SIZE counter runs (scaled by a plain copy of known size), or None
     when the workload differs or the kernel sources changed since then."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get("push_kernel", {})
     if rec.get("workload") != {"lwfa": "lwfa2048x256"}.get(wl_name):
         return None
-    h = hashlib.sha256()
-    for f in ("k_push.hip", "part.h", "sdmd_dev.h"):
-        with open(os.path.join(ROOT, "paper_1912_04064_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest()[:16] != rec.get("source_sha"):
+    if kernel_source_hash() != rec.get("source_sha"):
         return None
     return float(rec["bytes_per_launch"])
+
+
+def kernel_source_hash():
+    """Hash of the particle kernel's sources with comments and whitespace
+    removed: a code change invalidates the stored counter figures, an edit
+    of a comment does not."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in ("k_push.hip", "part.h", "sdmd_dev.h"):
+        with open(os.path.join(ROOT, "paper_1912_04064_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(wl_name, budget_s=20.0):

@@ -4,9 +4,11 @@
 // Runs of the same dimensionality, precision and patch class share one
 // launch per phase, so a step is three launches per class whatever the
 // number of runs:
-//   push  (one workgroup per patch of every run)       -- particles phase
-//   yee   (one workgroup per region tile of every run) -- transfer (i) + Maxwell
-//   post  (ghost chunks + leaver insertion)            -- Sync
+//   push  (one workgroup per segment slot of every run)  -- particles phase
+//   yee   (one workgroup per region tile of every run)   -- transfer (i),
+//         current filter, Maxwell (or J only, followed by the spectral
+//         launches of each spectral run)
+//   post  (ghost chunks + leaver insertion)              -- Sync
 // and every `relayout_every` steps a re-layout check (three launches that
 // exit at once unless some patch overflowed).  The two-step sequence
 // (E/B buffer parity 0 then 1) is captured once in a hipGraph and replayed.

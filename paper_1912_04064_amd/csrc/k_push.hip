@@ -6,11 +6,14 @@
 //   1. transfer (ii) of section 2.2: the patch's window of E^n and Bm^n
 //      (nodes [p0-1, p0+P+1] per axis) is read from its region into LDS,
 //      converted to the particle precision;
-//   2. every particle of the patch (coalesced SoA loads, 256 at a time):
-//      quadratic B-spline interpolation from the LDS window, Boris push,
-//      position update, Esirkepov order-2 deposition (section 3.2) into the
-//      patch's LDS current tile with LDS float atomics (40 adds in 2D, 144 in
-//      3D: the 4-node sub-frame that holds both the old and new shapes);
+//   2. every particle of the segment (coalesced SoA loads, one chunk per
+//      workgroup width, the next chunk prefetched): quadratic B-spline
+//      interpolation from the LDS window, Boris push, position update,
+//      Esirkepov order-2 deposition (section 3.2) into the segment's LDS
+//      current tile with FP64 LDS atomics (at most 40 adds in 2D, 144 in 3D:
+//      the 4-node sub-frame that holds both the old and new shapes; a
+//      3-node frame when no particle of the wavefront changes node, and
+//      structurally zero slots masked lane by lane);
 //   3. particles that stay are compacted in place in the patch segment;
 //      particles that leave go to the leaver store with their new patch;
 //   4. the LDS tile is written to the segment's tile slot in HBM, where the
@@ -19,7 +22,8 @@
 // into several segments (the paper's task decomposition of one patch) that
 // load the same window and deposit into their own tiles.
 // Particles parked in the spill store that belong to this patch are pushed
-// here too and all re-enter through the leaver store.
+// here too (by the patch's first segment) and re-enter through the overflow
+// leaver store.  A segment with nothing to push skips all of this.
 #include "launch.h"
 #include "part.h"
 #include "sdmd_dev.h"

@@ -115,3 +115,75 @@ def test_lwfa_full_size_one_step_piecewise():
         assert near.max() < 1e-9
     say(f"binning: {len(bad)} of {N} particles on a patch face within round-off")
     assert len(bad) <= 1e-5 * N
+
+
+def test_cylinder_3d_full_size_one_step():
+    """The 3D cylinder at full size (512 x 128 x 128 cells, 116,998,144
+    particles, 8^3 patches): after 60 steps, one step is checked -- the push
+    of a sample of particles (ids divisible by 97) against the oracle, the
+    discrete continuity of the GPU's own rho and J over every node, the field
+    update against the oracle's Yee step on the GPU's state, and the binning
+    of the sample."""
+    say("case: cylinder 512x128x128 full size, step 60 -> 61")
+    wl = WL.cylinder_3d()
+    n0 = 60
+    with B.Context([wl], track_ids=True, graph=True) as ctx:
+        ctx.step(n0)
+        Fa = ctx.fields(0, MASK | B.F_RHO)
+        Pa = ctx.particles(0)
+        ctx.step(1)
+        Fb = ctx.fields(0, MASK | B.F_RHO)
+        Pb = ctx.particles(0)
+        diag = ctx.diag(0)
+    N = wl.n_particles
+    assert diag["n_particles"] == N and len(Pb["x"]) == N
+
+    def sample(P):
+        m = P["id"] % 97 == 0
+        o = np.argsort(P["id"][m], kind="stable")
+        return {k: v[m][o] for k, v in P.items()}
+
+    Sa, Sb = sample(Pa), sample(Pb)
+    del Pa, Pb
+    assert np.array_equal(Sa["id"], Sb["id"]) and len(Sa["id"]) > N // 100
+    g = O.Grid(3, wl.n, wl.d, wl.dt, patch=wl.patch)
+    L = np.array([wl.n[a] * wl.d[a] for a in range(3)])
+
+    # push of the sample through the GPU's fields at step n
+    F = g.zeros_fields()
+    F[0:3], F[6:9], F[3:6] = Fa[0:3], Fa[3:6], Fa[6:9]
+    P = O.Particles(x=Sa["x"], y=Sa["y"], z=Sa["z"], ux=Sa["ux"], uy=Sa["uy"], uz=Sa["uz"], w=Sa["w"])
+    O.push_only(g, F, P)
+    un = np.sqrt(P.ux ** 2 + P.uy ** 2 + P.uz ** 2)
+    uo = np.sqrt(Sa["ux"] ** 2 + Sa["uy"] ** 2 + Sa["uz"] ** 2)
+    du = np.max(np.abs(np.stack([Sb["ux"] - P.ux, Sb["uy"] - P.uy, Sb["uz"] - P.uz])), axis=0)
+    rel_u = du / (un + uo + 1e-30)
+    dpos = max(np.abs(wrapped(Sb[k] - getattr(P, k), L[a])).max() / wl.d[a] for a, k in enumerate("xyz"))
+    say(f"push sample {len(un)}: max |du| / (|u_old| + |u_new|) {rel_u.max():.2e}, position {dpos:.2e} cells")
+    assert rel_u.max() < 1e-5
+    assert dpos < 1e-5
+
+    # continuity of the GPU's own charge and current over every node
+    r0, r1 = Fa[12], Fb[12]
+    J = Fb[9:12]
+    dx, dy, dz = wl.d
+    divJ = ((J[0] - np.roll(J[0], 1, axis=2)) / dx + (J[1] - np.roll(J[1], 1, axis=1)) / dy
+            + (J[2] - np.roll(J[2], 1, axis=0)) / dz)
+    res = np.abs((r1 - r0) / wl.dt + divJ).max() / (np.abs(r0).max() / wl.dt)
+    say(f"continuity residual / (max rho / dt): {res:.2e}")
+    assert res < 2e-6
+
+    # field update from the GPU's state
+    G = g.zeros_fields()
+    G[0:3], G[3:6], G[6:9], G[9:12] = Fa[0:3], Fa[6:9], Fa[3:6], Fb[9:12]
+    O.yee(g, G)
+    errs = [max(family_errors(Fb[0:3], G[0:3])), max(family_errors(Fb[6:9], G[3:6])),
+            max(family_errors(Fb[3:6], G[6:9]))]
+    say(f"field update E, B, Bm: {errs}")
+    assert max(errs) < 1e-13
+
+    # binning of the sample
+    po = O.bin_patches(g, O.Particles(x=Sb["x"], y=Sb["y"], z=Sb["z"], w=Sb["w"]))
+    bad = int((po != Sb["patch"]).sum())
+    say(f"binning: {bad} of {len(po)} sampled particles differ")
+    assert bad <= 1e-5 * len(po)

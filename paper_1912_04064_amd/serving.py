@@ -50,6 +50,8 @@ class GpuBackend:
         self.B = binding
         self.ctx = binding.Context([], max_runs=max_runs, hbm_budget=hbm_budget, track_ids=track_ids)
         self.start = time.perf_counter()
+        self.admit_s = 0.0      # host time spent admitting runs (upload, binning, patch choice)
+        self.admits = 0
 
     def clock(self) -> float:
         return time.perf_counter() - self.start
@@ -63,7 +65,11 @@ class GpuBackend:
         return self.B.mem_bytes(wl)
 
     def admit(self, wl, steps: int) -> int:
-        return self.ctx.admit(wl, max_steps=steps)
+        t0 = time.perf_counter()
+        run = self.ctx.admit(wl, max_steps=steps)
+        self.admit_s += time.perf_counter() - t0
+        self.admits += 1
+        return run
 
     def step(self, k: int):
         self.ctx.step(k)

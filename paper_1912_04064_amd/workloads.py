@@ -81,26 +81,29 @@ def _empty_parts():
 def uniform_random_plasma(n, d, ppc, density, vth, rng, dims=2):
     """`ppc` particles per cell at uniform random in-cell positions, Maxwellian
     momenta of standard deviation `vth` per component, weight density/ppc.
-    `ppc` and `density` may be scalars or per-cell arrays of shape n[::-1]."""
-    ncell = int(np.prod(n))
-    ppc_a = np.broadcast_to(np.asarray(ppc, dtype=np.int64), tuple(n[::-1])).reshape(-1)
-    den_a = np.broadcast_to(np.asarray(density, dtype=np.float64), tuple(n[::-1])).reshape(-1)
-    cells = np.repeat(np.arange(ncell, dtype=np.int64), ppc_a)
-    N = len(cells)
-    ix = cells % n[0]
-    iy = (cells // n[0]) % n[1]
+    `ppc` and `density` may be scalars or per-cell arrays of shape n[::-1].
+    Particles are in cell order (x fastest)."""
+    shape = tuple(n[::-1])
+    ppc_a = np.broadcast_to(np.asarray(ppc, dtype=np.int64), shape).reshape(-1)
+    den_a = np.broadcast_to(np.asarray(density, dtype=np.float64), shape).reshape(-1)
+    # per-cell indices, repeated per particle (no per-particle division)
+    ix_c = np.broadcast_to(np.arange(n[0], dtype=np.int32)[None, :], (int(np.prod(n[1:])), n[0])).reshape(-1)
+    iy_c = np.broadcast_to(np.arange(n[1], dtype=np.int32)[:, None], (n[1], n[0])).reshape(-1)
+    if dims == 3:
+        iy_c = np.tile(iy_c, n[2])
+    N = int(ppc_a.sum())
     out = {
-        "x": (ix + rng.random(N)) * d[0],
-        "y": (iy + rng.random(N)) * d[1],
+        "x": (np.repeat(ix_c, ppc_a) + rng.random(N)) * d[0],
+        "y": (np.repeat(iy_c, ppc_a) + rng.random(N)) * d[1],
     }
     if dims == 3:
-        iz = cells // (n[0] * n[1])
-        out["z"] = (iz + rng.random(N)) * d[2]
+        iz_c = np.repeat(np.arange(n[2], dtype=np.int32), n[0] * n[1])
+        out["z"] = (np.repeat(iz_c, ppc_a) + rng.random(N)) * d[2]
     else:
         out["z"] = np.zeros(N)
-    u = rng.standard_normal((3, N)) * vth
+    u = rng.standard_normal((3, N), dtype=np.float32).astype(np.float64) * vth
     out["ux"], out["uy"], out["uz"] = u[0], u[1], u[2]
-    out["w"] = (den_a / np.maximum(ppc_a, 1))[cells]
+    out["w"] = np.repeat(den_a / np.maximum(ppc_a, 1), ppc_a)
     out["id"] = np.arange(N, dtype=np.uint32)
     return out
 

@@ -203,6 +203,12 @@ typedef struct {
     int32_t err_flags;                /* bit 0 non-finite, bit 1 move >= 1
                                          cell, bit 2 capacity overflow     */
     int32_t patch[3];                 /* patch shape in use                */
+    double  gauss_residual;           /* max over nodes of |(div E - rho)^n
+                                         - (div E - rho)^0| / max |rho^n|:
+                                         round-off for the charge-conserving
+                                         path (with the current filter the
+                                         conserved form involves the filtered
+                                         rho, and this figure drifts)       */
 } pic_diag_t;
 
 /* Particle export (host memory, caller owned).  capacity is the length of

@@ -79,7 +79,7 @@ class PicDiag(C.Structure):
     _fields_ = [("step", C.c_int64), ("t", C.c_double), ("n_particles", C.c_int64), ("patch_min", C.c_int64),
                 ("patch_max", C.c_int64), ("patch_mean", C.c_double), ("U_E", C.c_double), ("U_B", C.c_double),
                 ("K", C.c_double), ("t_ms", C.c_double * 4), ("n_relayout", C.c_int64), ("n_spill", C.c_int64),
-                ("err_flags", C.c_int32), ("patch", C.c_int32 * 3)]
+                ("err_flags", C.c_int32), ("patch", C.c_int32 * 3), ("gauss_residual", C.c_double)]
 
 
 class PicParticlesOut(C.Structure):

@@ -52,6 +52,7 @@ struct Run {
     int64_t issued = 0;    // steps enqueued since admission
     int64_t target = 0;    // max_steps (0 = unlimited)
     int par0 = 0;          // E/B buffer holding the state at admission
+    double *gauss0 = nullptr;   // div_h E - rho of the initial state, per node
     size_t bytes = 0;
     RunDev rd{};
     std::vector<DevBuf> bufs;
@@ -299,6 +300,7 @@ static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::st
     b += 2 * (size_t)L.cap_total * per + align256((size_t)L.cap_total * 4);
     b += 2 * (size_t)std::max<long long>(L.n_total, 1) * (per + 4);
     if (cfg->field_solver == PIC_SOLVER_PSATD) b += align256((size_t)9 * ncell * 16);
+    b += align256((size_t)ncell * 8);   // initial Gauss residual
     b += 64 * 256;   // per-array rounding and the control block
     L.bytes = b;
     return PIC_OK;
@@ -497,6 +499,8 @@ static void autotune_patch(pic_ctx *c, const pic_config *cfg, int P[3])
     P[2] = cfg->dims == 3 ? best : 1;
 }
 
+static int gauss_field(pic_ctx *c, int slot, double *g);
+
 static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
 {
     Run &r = c->runs[slot];
@@ -591,6 +595,8 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
         d.spec = (double2 *)run_alloc(c, r, (size_t)9 * r.ncell * 16);
         ok = ok && d.spec;
     }
+    r.gauss0 = (double *)run_alloc(c, r, (size_t)r.ncell * 8);
+    ok = ok && r.gauss0;
     r.bytes = 0;
     for (auto &b : r.bufs) r.bytes += b.bytes;
     if (!ok) {
@@ -692,6 +698,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
         return rc;
     }
     r.steps = 0;
+    if ((rc = gauss_field(c, slot, r.gauss0))) return rc;
     return PIC_OK;
 }
 
@@ -877,6 +884,25 @@ static bool any_active(pic_ctx *c)
 }
 
 static int run_par(const Run &r) { return r.par0 ^ (int)(r.steps & 1); }
+
+// div_h E - rho of a run's current state into g (device, ncell doubles)
+static int gauss_field(pic_ctx *c, int slot, double *g)
+{
+    Run &r = c->runs[slot];
+    double *rho = (double *)dev_alloc(c, (size_t)r.ncell * 8);
+    if (!rho) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
+    DevBuf rb{rho, align256((size_t)r.ncell * 8)};
+    hipError_t e;
+    Ctl ctl = read_ctl(c, slot, e);
+    if (e == hipSuccess)
+        e = launch_rho(r.dims, r.split, c->d_runs, slot, r.rd.seg_max, ctl.nspill, r.ncell, rho, c->stream);
+    if (e == hipSuccess) e = launch_gauss(c->d_runs, slot, r.ncell, run_par(r), rho, g, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dev_free(c, rb);
+    if (e != hipSuccess) return set_err(c, PIC_E_DEVICE, "Gauss residual: %s", hipGetErrorString(e));
+    return PIC_OK;
+}
+
 
 static void advance(pic_ctx *c, int nsteps)
 {
@@ -1181,6 +1207,34 @@ int pic_diag(pic_ctx *c, int32_t run, pic_diag_t *out)
     out->U_B = 0.5 * ub * dV;
     out->K = k * dV;
     for (int i = 0; i < 4; ++i) out->t_ms[i] = c->t_ms[i];
+    {
+        // Gauss-law residual against the initial state
+        double *gb = (double *)dev_alloc(c, (size_t)r.ncell * 8 + (size_t)2 * nb * 8);
+        if (!gb) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
+        DevBuf gbb{gb, align256((size_t)r.ncell * 8 + (size_t)2 * nb * 8)};
+        double *rho = (double *)dev_alloc(c, (size_t)r.ncell * 8);
+        if (!rho) {
+            dev_free(c, gbb);
+            return set_err(c, PIC_E_NOMEM, "staging allocation failed");
+        }
+        DevBuf rbb{rho, align256((size_t)r.ncell * 8)};
+        hipError_t e = launch_rho(r.dims, r.split, c->d_runs, run, d.seg_max, ctl.nspill, r.ncell, rho, c->stream);
+        if (e == hipSuccess) e = launch_gauss(c->d_runs, run, r.ncell, run_par(r), rho, gb, c->stream);
+        if (e == hipSuccess) e = launch_gauss_max(r.ncell, gb, r.gauss0, rho, gb + r.ncell, nb, c->stream);
+        std::vector<double> hm(2 * nb);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hm.data(), gb + r.ncell, (size_t)2 * nb * 8, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        dev_free(c, rbb);
+        dev_free(c, gbb);
+        if (e != hipSuccess) return set_err(c, PIC_E_DEVICE, "Gauss residual: %s", hipGetErrorString(e));
+        double dg = 0.0, rm = 0.0;
+        for (int i = 0; i < nb; ++i) {
+            dg = std::max(dg, hm[2 * i]);
+            rm = std::max(rm, hm[2 * i + 1]);
+        }
+        out->gauss_residual = rm > 0.0 ? dg / rm : dg;
+    }
     out->n_relayout = ctl.n_relayout;
     out->n_spill = ctl.nspill;
     out->err_flags = ctl.err;

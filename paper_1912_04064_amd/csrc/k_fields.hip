@@ -705,4 +705,64 @@ hipError_t launch_field_energy(const RunDev *runs, int run, int ncell, int par, 
     return hipGetLastError();
 }
 
+// Gauss-law residual g = div_h E - rho at every primal node (x fastest),
+// from E of buffer par (ghost layers hold the neighbours) and the deposited
+// electron density rho.
+__global__ void gauss_kernel(const RunDev *__restrict__ runs, int run, int ncell, int par,
+                             const double *__restrict__ rho, double *__restrict__ g)
+{
+    const RunDev &rd = runs[run];
+    const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (gid >= ncell) return;
+    int region;
+    long long p;
+    node_of(rd, gid, region, p);
+    const long long st[3] = {1, rd.ra[0], (long long)rd.ra[0] * rd.ra[1]};
+    double div = 0.0;
+    for (int a = 0; a < rd.dims; ++a) {
+        const double *E = rcomp(rd, region, f_E(par) + a);
+        div += (E[p] - E[p - st[a]]) / rd.d[a];
+    }
+    g[gid] = div - rho[gid];
+}
+
+// per-block maxima of |g - g0| and |rho|
+__global__ void gauss_max_kernel(int ncell, const double *__restrict__ g, const double *__restrict__ g0,
+                                 const double *__restrict__ rho, double *__restrict__ partial)
+{
+    __shared__ double sa[BLOCK], sb[BLOCK];
+    double a = 0.0, b = 0.0;
+    for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < ncell; i += (long long)gridDim.x * BLOCK) {
+        a = fmax(a, fabs(g[i] - g0[i]));
+        b = fmax(b, fabs(rho[i]));
+    }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sa[threadIdx.x] = fmax(sa[threadIdx.x], sa[threadIdx.x + w]);
+            sb[threadIdx.x] = fmax(sb[threadIdx.x], sb[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = sa[0];
+        partial[2 * blockIdx.x + 1] = sb[0];
+    }
+}
+
+hipError_t launch_gauss(const RunDev *runs, int run, int ncell, int par, const double *rho, double *g, hipStream_t s)
+{
+    gauss_kernel<<<(ncell + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(runs, run, ncell, par, rho, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauss_max(int ncell, const double *g, const double *g0, const double *rho, double *partial,
+                            int nblocks, hipStream_t s)
+{
+    gauss_max_kernel<<<nblocks, BLOCK, 0, s>>>(ncell, g, g0, rho, partial);
+    return hipGetLastError();
+}
+
 }  // namespace sdmd

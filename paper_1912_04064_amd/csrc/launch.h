@@ -59,6 +59,11 @@ hipError_t launch_export(int dims, bool split, const RunDev *runs, int run, int 
 // diagnostics: partial sums (field energy per block; kinetic per patch)
 hipError_t launch_field_energy(const RunDev *runs, int run, int ncell, int par, double *partial, int nblocks,
                                hipStream_t s);
+// Gauss-law residual g = div_h E (buffer par) - rho per node, and per-block
+// maxima of |g - g0| and |rho| (2 doubles per block)
+hipError_t launch_gauss(const RunDev *runs, int run, int ncell, int par, const double *rho, double *g, hipStream_t s);
+hipError_t launch_gauss_max(int ncell, const double *g, const double *g0, const double *rho, double *partial,
+                            int nblocks, hipStream_t s);
 hipError_t launch_kinetic(int dims, bool split, const RunDev *runs, int run, int seg_max, int nspill, double *partial,
                           hipStream_t s);
 // charge density (electrons) at primal nodes, global FP64 array (zeroed here)

@@ -218,6 +218,11 @@ def test_thermal64_100_steps(prec, tol1):
     assert max(e100.values()) < 1e-3
     assert diag["n_particles"] == wl.n_particles
     assert diag["K"] == pytest.approx(uo[2], rel=1e-3)
+    # the library's own Gauss-law diagnostic: charge-conserving deposition and
+    # Yee keep div E - rho at its initial value (FP32 split: to single-precision
+    # round-off accumulated over 100 steps)
+    say(f"{prec}: diag gauss residual after 100 steps {diag['gauss_residual']:.3e}")
+    assert diag["gauss_residual"] < (1e-11 if prec == "fp64" else 1e-4)
 
 
 @pytest.mark.parametrize("prec,tol1", [("fp64", 1e-12), ("fp32s", 1e-5)])

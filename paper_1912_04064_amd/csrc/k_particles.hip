@@ -208,34 +208,31 @@ __global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev 
     }
 }
 
-// Cell of a stored particle inside its patch (x fastest), for the in-patch
-// ordering of a re-layout.
+// Sort key of a stored particle's cell inside its patch, for the in-patch
+// ordering of a re-layout: x fastest, then y (2D); x, then z, then y (3D,
+// so that the 64 lanes of a wavefront take an x-z slice of an 8^3 patch,
+// the footprint the particle kernel's padded LDS planes are laid out for).
 template <int DIM, class T>
 __device__ __forceinline__ int local_cell(const RunDev &rd, const Store &s, long long i, int q)
 {
+    int v[3] = {0, 0, 0};
     if constexpr (T::split) {
         const int c = s.cell[i];
-        int lc = 0, mul = 1;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            int v = (c >> (5 * a)) & 31;
-            v = v < rd.P[a] ? v : rd.P[a] - 1;
-            lc += v * mul;
-            mul *= rd.P[a];
+            const int w = (c >> (5 * a)) & 31;
+            v[a] = w < rd.P[a] ? w : rd.P[a] - 1;
         }
-        return lc;
     } else {
         const int pq[3] = {q % rd.np[0], (q / rd.np[0]) % rd.np[1], DIM == 3 ? q / (rd.np[0] * rd.np[1]) : 0};
-        int lc = 0, mul = 1;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            int v = (int)floor(((const double *)s.pos[a])[i] / rd.d[a]) - pq[a] * rd.P[a];
-            v = v < 0 ? 0 : (v > rd.P[a] - 1 ? rd.P[a] - 1 : v);
-            lc += v * mul;
-            mul *= rd.P[a];
+            const int w = (int)floor(((const double *)s.pos[a])[i] / rd.d[a]) - pq[a] * rd.P[a];
+            v[a] = w < 0 ? 0 : (w > rd.P[a] - 1 ? rd.P[a] - 1 : w);
         }
-        return lc;
     }
+    if constexpr (DIM == 3) return v[0] + rd.P[0] * (v[2] + rd.P[2] * v[1]);
+    return v[0] + rd.P[0] * v[1];
 }
 
 // Sub-cell half of a stored particle: bit a is set when it lies in the upper

@@ -30,6 +30,22 @@
 
 namespace sdmd {
 
+// LDS plane stride (in elements) of the 3D window and tile: the smallest
+// value >= the plane size n that is 8 modulo 16.  A wavefront's 64 lanes
+// take the 8 x 8 cells of an x-z slice of an 8^3 patch (the relayout's
+// cell order is y-major), i.e. 8 rows of 8 nodes in consecutive planes.
+// With this stride the 8 rows of a window read start on 8 different groups
+// of 8 of the 64 LDS banks, and the 2 rows of each 16-lane group of an FP64
+// tile add on the 2 halves of the 16 eight-byte banks -- no bank conflicts
+// when the lanes' frames are shifted alike (the in-cell order by sub-cell
+// half).  Measured on gfx950: an FP64 LDS add with a 2-way bank conflict
+// costs 2x, an FP32 read 1.7x.  2D planes are not padded (one plane).
+template <int DIM>
+__host__ __device__ constexpr int lds_plane(int n)
+{
+    return DIM == 3 ? (n + 7) / 16 * 16 + 8 : n;
+}
+
 // Old/new shape factors of one axis on the 4-node sub-frame starting at
 // node ip + k0 (k0 = -2 or -1) of the 5-node Esirkepov frame centred on the
 // old primal node ip.  d0: old offset from ip in [-1/2, 1/2); d1: new
@@ -155,7 +171,7 @@ __device__ __forceinline__ void deposit2d(double *Jb, int T0, int TS, const R S0
 }
 
 template <int NF, class R>
-__device__ __forceinline__ void deposit3d(double *Jb, int T0, int T1, int TS, const R S0[3][4], const R DS[3][4],
+__device__ __forceinline__ void deposit3d(double *Jb, int T0, int TP, int TS, const R S0[3][4], const R DS[3][4],
                                           const R cj[3], const bool mv[3])
 {
     const R third = R(1) / R(3);
@@ -176,9 +192,9 @@ __device__ __forceinline__ void deposit3d(double *Jb, int T0, int T1, int TS, co
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const int u = c == 0 ? 1 : 0, v = c == 2 ? 1 : 2;
-        const int su = u == 0 ? 1 : (u == 1 ? T0 : T0 * T1);
-        const int sv = v == 1 ? T0 : T0 * T1;
-        const int sc = c == 0 ? 1 : (c == 1 ? T0 : T0 * T1);
+        const int su = u == 0 ? 1 : (u == 1 ? T0 : TP);
+        const int sv = v == 1 ? T0 : TP;
+        const int sc = c == 0 ? 1 : (c == 1 ? T0 : TP);
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
 #pragma unroll
@@ -213,8 +229,9 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
     using R = typename T::real;
     const int P0 = PX ? PX : Prt[0], P1 = PX ? PX : Prt[1], P2 = DIM == 3 ? (PX ? PX : Prt[2]) : 1;
     const int P[3] = {P0, P1, P2};
-    const int W0 = P0 + 3, W1 = P1 + 3, WS = W0 * W1 * (DIM == 3 ? P2 + 3 : 1);
-    const int T0 = P0 + 5, T1 = P1 + 5, TS = T0 * T1 * (DIM == 3 ? P2 + 5 : 1);
+    // LDS strides: rows of P0 + 3 (window) / P0 + 5 (tile) nodes, padded planes
+    const int W0 = P0 + 3, WP = lds_plane<DIM>(W0 * (P1 + 3)), WS = WP * (DIM == 3 ? P2 + 3 : 1);
+    const int T0 = P0 + 5, TP = lds_plane<DIM>(T0 * (P1 + 5)), TS = TP * (DIM == 3 ? P2 + 5 : 1);
 
     int lc[3] = {0, 0, 0}, ip[3] = {0, 0, 0};
     R wp[3][3], wd[3][3], dp[3];
@@ -266,14 +283,14 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
         B[2] = sum2(5, wd[0], lc[0], wd[1], lc[1]);
     } else {
         auto sum3 = [&](int c, const R *wx, int bx, const R *wy, int by, const R *wz, int bz) {
-            const R *A = win + c * WS + (bz * W1 + by) * W0 + bx;
+            const R *A = win + c * WS + bz * WP + by * W0 + bx;
             R s = R(0);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 R sk = R(0);
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
-                    const R *row = A + (k * W1 + b) * W0;
+                    const R *row = A + k * WP + b * W0;
                     sk += wy[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2]);
                 }
                 s += wz[k] * sk;
@@ -374,7 +391,7 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
     R cj[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int a = 0; a < DIM; ++a) cj[a] = (T::split ? (R)rd.f_cj[a] : (R)(-rd.q * rd.d[a] / rd.dt)) * p.w;
-    double *Jb = tile + (DIM == 3 ? (t0[2] * T1 + t0[1]) * T0 + t0[0] : t0[1] * T0 + t0[0]);
+    double *Jb = tile + (DIM == 3 ? t0[2] * TP + t0[1] * T0 + t0[0] : t0[1] * T0 + t0[0]);
     // When no particle of the wavefront changes its nearest primal node, the
     // last slot of every frame holds zeros (S0, DS) and the running sums end
     // at zero one slot earlier, so only a 3-slot frame is deposited: 21 LDS
@@ -391,9 +408,9 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
             deposit2d<4, R>(Jb, T0, TS, S0, DS, cj, cz, mv[0], mv[1]);
     } else {
         if (__all(still))
-            deposit3d<3, R>(Jb, T0, T1, TS, S0, DS, cj, mv);
+            deposit3d<3, R>(Jb, T0, TP, TS, S0, DS, cj, mv);
         else
-            deposit3d<4, R>(Jb, T0, T1, TS, S0, DS, cj, mv);
+            deposit3d<4, R>(Jb, T0, TP, TS, S0, DS, cj, mv);
     }
 
     p.u[0] = un[0];
@@ -427,8 +444,8 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
 {
     using R = typename T::real;
     constexpr int BLOCK = push_block<DIM, T>();
-    constexpr int WN = (PC + 3) * (PC + 3) * (DIM == 3 ? PC + 3 : 1);
-    constexpr int TN = (PC + 5) * (PC + 5) * (DIM == 3 ? PC + 5 : 1);
+    constexpr int WN = lds_plane<DIM>((PC + 3) * (PC + 3)) * (DIM == 3 ? PC + 3 : 1);
+    constexpr int TN = lds_plane<DIM>((PC + 5) * (PC + 5)) * (DIM == 3 ? PC + 5 : 1);
     constexpr int NW = BLOCK / 64;
     constexpr int SPC = 1024;                          // spill entries scanned per round
     constexpr int SPK = (SPC + BLOCK - 1) / BLOCK;
@@ -461,7 +478,9 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     const int o[3] = {p0[0] - rr[0] * rd.rs[0], p0[1] - rr[1] * rd.rs[1], DIM == 3 ? p0[2] - rr[2] * rd.rs[2] : 0};
     const int W0 = P[0] + 3, W1 = P[1] + 3, W2 = DIM == 3 ? P[2] + 3 : 1;
     const int WS = W0 * W1 * W2;
-    const int TS = (P[0] + 5) * (P[1] + 5) * (DIM == 3 ? P[2] + 5 : 1);
+    const int T0 = P[0] + 5, T1 = P[1] + 5, TS = T0 * T1 * (DIM == 3 ? P[2] + 5 : 1);   // tile in HBM
+    const int WPs = lds_plane<DIM>(W0 * W1), WSs = WPs * W2;                           // LDS layout
+    const int TPs = lds_plane<DIM>(T0 * T1), TSs = TPs * (DIM == 3 ? P[2] + 5 : 1);
 
     const SDMD_GLOBAL int *sseg = gp(rd.sseg);
     const long long seg0 = sseg[sg];
@@ -493,9 +512,10 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
         const int wx = rem % W0, tq = rem / W0, wy = tq % W1, wz = tq / W1;
         const int comp = c < 3 ? f_E(par) + c : F_BM + (c - 3);
         const SDMD_GLOBAL double *A = gp((const double *)rcomp(rd, region, comp));
-        s_win[idx] = (R)A[rindex(rd, o[0] - 1 + wx, o[1] - 1 + wy, DIM == 3 ? o[2] - 1 + wz : 0)];
+        s_win[c * WSs + wz * WPs + wy * W0 + wx] =
+            (R)A[rindex(rd, o[0] - 1 + wx, o[1] - 1 + wy, DIM == 3 ? o[2] - 1 + wz : 0)];
     }
-    for (int idx = tid; idx < 3 * TS; idx += BLOCK) s_tile[idx] = 0.0;
+    for (int idx = tid; idx < 3 * TSs; idx += BLOCK) s_tile[idx] = 0.0;
     __syncthreads();
 
     int err = 0;
@@ -607,7 +627,10 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     __syncthreads();
     // flush the tile in the tile precision (transfer (i) reads it)
     SDMD_GLOBAL R *dst = gp((R *)rd.tiles) + (long long)sg * 3 * TS;
-    for (int idx = tid; idx < 3 * TS; idx += BLOCK) dst[idx] = (R)s_tile[idx];
+    for (int idx = tid; idx < 3 * TS; idx += BLOCK) {
+        const int pl = idx / (T0 * T1), rem = idx - pl * (T0 * T1);   // plane (component and z), node in it
+        dst[idx] = (R)s_tile[pl * TPs + rem];
+    }
     if (tid == 0) tflag[sg] = 1;
 }
 

@@ -206,12 +206,9 @@ def bench_sdsd(args):
             ctx.step(args.steps)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            ph = []
-            for _ in range(max(1, args.phase_samples)):
-                ctx.time_phases()
-                ph.append(ctx.diag(0)["t_ms"][:3])
+            ctx.time_phases(max(1, args.phase_samples))
+            ph = np.array(ctx.diag(0)["t_ms"][:3])
             ctx.close()
-            ph = np.mean(np.array(ph), axis=0)
             row = {"patch": P, "mode": mode, "regions": nreg[0] * nreg[1], "ms_per_step": dt * 1e3 / args.steps,
                    "pushes_per_s": wl.n_particles * args.steps / dt, "particles_ms": float(ph[0]),
                    "fields_ms": float(ph[1]), "sync_ms": float(ph[2])}
@@ -285,21 +282,17 @@ def main():
 
     d = ctx.diag(0)
     ctx.close()
-    # Dominant kernel: the same trajectory replayed from the same input, every
-    # step's kernels bracketed by HIP events on the library's stream, so the
-    # averages cover all launches of the timed steps (as a kernel trace of
-    # the run does).
-    push_ms, yee_ms, post_ms = [], [], []
+    # Dominant kernel: the same trajectory replayed from the same input, the
+    # kernels of every step separated by HIP events on the library's stream
+    # and enqueued back to back (one synchronisation at the end), so the
+    # averages cover all launches of the timed steps, as a kernel trace of
+    # the run does.
     nph = args.steps if args.phase_samples <= 0 else min(args.steps, args.phase_samples)
     ctx = B.Context([wl], graph=not args.no_graph)
     ctx.step(args.warmup)
-    for _ in range(nph):
-        ctx.time_phases()
-        t = ctx.diag(0)["t_ms"]
-        push_ms.append(t[0])
-        yee_ms.append(t[1])
-        post_ms.append(t[2])
-    push_avg = float(np.mean(push_ms))
+    ctx.time_phases(nph)
+    t = ctx.diag(0)["t_ms"]
+    push_avg, yee_avg, post_avg = float(t[0]), float(t[1]), float(t[2])
     pb = particle_bytes(wl)
     alg_push = N * pb + ncell * 48          # particles + the FP64 E, Bm window (transfer ii)
     achieved = alg_push / (push_avg * 1e-3) / 1e9
@@ -323,8 +316,7 @@ def main():
                    "regions": list(wl.nreg), "precision": wl.precision, "solver": wl.solver, "filter": wl.filter,
                    "graph": not args.no_graph},
         "step_hbm_GBps_algorithmic": step_bytes / (ms * 1e-3) / 1e9,
-        "phase_ms": {"particles": push_avg, "reduce_maxwell": float(np.mean(yee_ms)),
-                     "sync_rebin": float(np.mean(post_ms))},
+        "phase_ms": {"particles": push_avg, "reduce_maxwell": yee_avg, "sync_rebin": post_avg},
         "roofline": {"bound": "hbm", "kernel": "push_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": push_traffic(args.workload),
                      "bytes_per_launch": alg_push},

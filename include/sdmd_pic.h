@@ -184,8 +184,8 @@ typedef struct {
     int32_t flags;              /* PIC_RT_* */
 } pic_runtime;
 
-/* Diagnostics of one run at its current step.  t_ms: wall time of the
- * phases of the last timed step (pic_time_phases), order Particles,
+/* Diagnostics of one run at its current step.  t_ms: time per step of the
+ * phases over the last pic_time_phases call, order Particles,
  * SyncDec-i + Fields (fused), Sync (ghosts + re-binning), Relayout. */
 typedef struct {
     int64_t step;
@@ -262,9 +262,12 @@ int pic_retire(pic_ctx *ctx, int32_t run);
  * completes (host counter, no synchronisation; capped at max_steps). */
 int pic_run_steps(pic_ctx *ctx, int32_t run, int64_t *steps);
 
-/* Time one step phase by phase with HIP events (synchronising, for the
- * diagnostics' t_ms); the step is a normal step of every active run. */
-int pic_time_phases(pic_ctx *ctx);
+/* Take n_steps (>= 1) normal steps of every active run, enqueued phase by
+ * phase with a HIP event between phases and one synchronisation at the end
+ * (the device waits ~200 us first while the host enqueues, so the kernels
+ * run back to back); the diagnostics' t_ms then hold each phase's average
+ * time per step over these steps.  PIC_E_INVAL for n_steps < 1. */
+int pic_time_phases(pic_ctx *ctx, int32_t n_steps);
 
 /* Release everything.  Null is allowed. */
 void pic_free(pic_ctx *ctx);

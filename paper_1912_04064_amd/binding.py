@@ -120,7 +120,7 @@ def load(path: str = LIB_PATH):
     L.pic_admit.argtypes = [C.c_void_p, C.POINTER(PicConfig), C.POINTER(C.c_int32)]
     L.pic_retire.argtypes = [C.c_void_p, C.c_int32]
     L.pic_run_steps.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]
-    L.pic_time_phases.argtypes = [C.c_void_p]
+    L.pic_time_phases.argtypes = [C.c_void_p, C.c_int32]
     L.pic_free.argtypes = [C.c_void_p]
     L.pic_free.restype = None
     L.pic_strerror.argtypes = [C.c_int]
@@ -267,8 +267,10 @@ class Context:
     def step(self, n: int = 1):
         _check(self.L, self.ctx, self.L.pic_step(self.ctx, int(n)), "pic_step")
 
-    def time_phases(self):
-        _check(self.L, self.ctx, self.L.pic_time_phases(self.ctx), "pic_time_phases")
+    def time_phases(self, n: int = 1):
+        """Take n steps timed phase by phase; diag()["t_ms"] then holds the
+        per-step average of each phase over them."""
+        _check(self.L, self.ctx, self.L.pic_time_phases(self.ctx, int(n)), "pic_time_phases")
 
     def fields(self, run: int = 0, mask: int = F_ALL, check=True) -> np.ndarray:
         w = self.workloads[run]

@@ -1080,30 +1080,52 @@ int pic_run_steps(pic_ctx *c, int32_t run, int64_t *steps)
     return PIC_OK;
 }
 
-int pic_time_phases(pic_ctx *c)
+int pic_time_phases(pic_ctx *c, int32_t n_steps)
 {
-    if (!c) return PIC_E_INVAL;
+    if (!c || n_steps < 1) return PIC_E_INVAL;
     if (!any_active(c)) return PIC_OK;
-    hipEvent_t ev[5];
-    for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
-    HIPCHK(c, hipEventRecord(ev[0], c->stream));
-    HIPCHK(c, enqueue_push(c, c->par, c->stream));
-    HIPCHK(c, hipEventRecord(ev[1], c->stream));
-    HIPCHK(c, enqueue_yee(c, c->par, c->stream));
-    HIPCHK(c, hipEventRecord(ev[2], c->stream));
-    HIPCHK(c, enqueue_post(c, c->par, c->stream));
-    HIPCHK(c, hipEventRecord(ev[3], c->stream));
-    advance(c, 1);
-    if (c->step % c->relayout_every == 0) HIPCHK(c, enqueue_relayout(c, c->stream));
-    HIPCHK(c, hipEventRecord(ev[4], c->stream));
-    HIPCHK(c, hipEventSynchronize(ev[4]));
-    for (int i = 0; i < 4; ++i) {
-        float ms = 0;
-        hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
-        c->t_ms[i] = ms;
+    // n steps enqueued phase by phase with an event between phases and one
+    // synchronisation at the end: the kernels run back to back as in a
+    // normal step (the host stays ahead of the device), and the stream
+    // waits ~200 us first while the host enqueues the opening steps, so
+    // each interval holds its kernels only
+    std::vector<hipEvent_t> ev(4 * (size_t)n_steps + 1);
+    size_t made = 0;
+    int rc = PIC_OK;
+    for (; made < ev.size(); ++made)
+        if (hipEventCreate(&ev[made]) != hipSuccess) break;
+    auto fail_dev = [&](hipError_t e) { return set_err(c, PIC_E_DEVICE, "HIP: %s", hipGetErrorString(e)); };
+    hipError_t e = made == ev.size() ? hipSuccess : hipErrorOutOfMemory;
+    if (e == hipSuccess) e = launch_gate(200, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], c->stream);
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
+        hipEvent_t *q = &ev[4 * (size_t)k];
+        e = enqueue_push(c, c->par, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(q[1], c->stream);
+        if (e == hipSuccess) e = enqueue_yee(c, c->par, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(q[2], c->stream);
+        if (e == hipSuccess) e = enqueue_post(c, c->par, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(q[3], c->stream);
+        if (e != hipSuccess) break;
+        advance(c, 1);
+        if (c->step % c->relayout_every == 0) e = enqueue_relayout(c, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(q[4], c->stream);
     }
-    for (auto &e : ev) hipEventDestroy(e);
-    return PIC_OK;
+    if (e == hipSuccess) e = hipEventSynchronize(ev.back());
+    if (e == hipSuccess) {
+        double sum[4] = {0, 0, 0, 0};
+        for (int k = 0; k < n_steps; ++k)
+            for (int i = 0; i < 4; ++i) {
+                float ms = 0;
+                hipEventElapsedTime(&ms, ev[4 * (size_t)k + i], ev[4 * (size_t)k + i + 1]);
+                sum[i] += ms;
+            }
+        for (int i = 0; i < 4; ++i) c->t_ms[i] = sum[i] / n_steps;
+    } else {
+        rc = fail_dev(e);
+    }
+    for (size_t i = 0; i < made; ++i) hipEventDestroy(ev[i]);
+    return rc;
 }
 
 static int field_comp(int bit, int par)

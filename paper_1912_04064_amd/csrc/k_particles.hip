@@ -650,4 +650,27 @@ hipError_t launch_rho(int dims, bool split, const RunDev *runs, int run, int seg
     DISPATCH_ALL(RHO_BODY)
 }
 
+// One thread that waits about `us` microseconds on the device wall clock
+// (at most 2^24 polls, whatever the clock does).  Queued ahead of a timed
+// sequence, it holds the stream until the host has enqueued the whole
+// sequence, so that the events between the kernels measure the kernels and
+// not the host's launch latency.
+__global__ void gate_kernel(long long ticks)
+{
+    const long long t0 = wall_clock64();
+    for (int i = 0; i < (1 << 24); ++i)
+        if (wall_clock64() - t0 >= ticks) break;
+}
+
+hipError_t launch_gate(int us, hipStream_t s)
+{
+    int dev = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return e;
+    if (khz <= 0) khz = 100000;
+    gate_kernel<<<1, 1, 0, s>>>((long long)(us > 0 ? us : 0) * khz / 1000);
+    return hipGetLastError();
+}
+
 }  // namespace sdmd

@@ -69,5 +69,7 @@ hipError_t launch_kinetic(int dims, bool split, const RunDev *runs, int run, int
 // charge density (electrons) at primal nodes, global FP64 array (zeroed here)
 hipError_t launch_rho(int dims, bool split, const RunDev *runs, int run, int seg_max, int nspill, int ncell,
                       double *rho, hipStream_t s);
+// a short wait on the device that holds the stream while the host enqueues
+hipError_t launch_gate(int us, hipStream_t s);
 
 }  // namespace sdmd

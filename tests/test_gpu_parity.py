@@ -182,6 +182,30 @@ def test_sdsd_regions_equal_patches(dims, precision):
             assert np.minimum(d, L[a] - d).max() <= (1e-12 if precision == "fp64" else 1e-4), k
 
 
+def test_timed_steps_are_normal_steps():
+    """pic_time_phases(n) takes n ordinary steps (with the re-layout cadence
+    and the step count of pic_step) and reports positive per-phase times."""
+    say("case: time_phases(20) vs step(20), thermal 64x64 fp64")
+    wl = WL.thermal_2d(n=(64, 64), ppc=4, vth=0.05, patch=(8, 8), precision="fp64")
+    ref, pref, dref = gpu_run(wl, 20)
+    with B.Context([wl], track_ids=True) as ctx:
+        ctx.time_phases(7)
+        t7 = ctx.diag(0)["t_ms"]
+        ctx.time_phases(13)
+        F = ctx.fields(0, MASK)
+        parts = B.sort_by_id(ctx.particles(0))
+        d = ctx.diag(0)
+        with pytest.raises(B.PicError):
+            ctx.time_phases(0)
+    got = {"E": F[0:3], "Bm": F[3:6], "BH": F[6:9], "J": F[9:12]}
+    assert d["step"] == dref["step"] == 20
+    assert d["n_relayout"] == dref["n_relayout"]
+    _same_run(ref, got, 1e-12)
+    assert np.array_equal(pref["id"], parts["id"])
+    for t in (t7, d["t_ms"]):
+        assert all(x > 0 for x in t[:3]), t
+
+
 # ---------------------------------------------------------------- full steps
 @pytest.mark.parametrize("graph", [True, False])
 def test_fp64_one_step_matches_oracle(graph):

@@ -296,17 +296,24 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
         // k takes every nch-th particle of the old storage order starting at
         // k (so that each chunk samples the whole patch), at most MOVE_CHUNK
         // of them.  The chunk is sorted by cell and, inside a cell, by
-        // sub-cell half (counting sort in LDS) and stored transposed: viewing the cell-sorted chunk as rows of M
-        // (~ particles per occupied cell) entries, position = column * rows
-        // + row.  Consecutive positions -- the lanes of a wavefront -- then
-        // hold particles of consecutive cells, whose field-window reads and
-        // current-tile updates fall on different LDS banks.  Chunks take
-        // consecutive ranges of the patch's positions, which are split
-        // evenly over its new segments.
+        // sub-cell half (counting sort in LDS), which gives every particle
+        // its rank r inside its cell.  It is stored round-robin over the
+        // cells: all rank-0 particles in cell order, then all rank-1
+        // particles, ...; the particle of rank r in cell k goes to position
+        // base[r] + (cells before k holding more than r particles), with
+        // base[r] the number of particles of rank < r.  Consecutive
+        // positions -- the lanes of a wavefront -- then hold distinct
+        // neighbouring cells whatever the occupancy (uneven cells of a
+        // plasma wake included), so their field-window reads and tile
+        // updates fall on different LDS addresses.  Chunks take consecutive
+        // ranges of the patch's positions, which are split evenly over its
+        // new segments.
         __shared__ int s_off[MAX_SORT_BINS];
+        __shared__ int s_pos[MOVE_CHUNK];    // sorted index -> position in the chunk
         __shared__ int s_sum[BLOCK];
+        __shared__ int s_ws[2][BLOCK / 64];
         __shared__ int s_seg[MAX_OLD_SEGS + 1];
-        __shared__ int s_p, s_nocc;
+        __shared__ int s_p, s_cmax;
         const int b = blockIdx.x;
         if (b >= rd.cpre[np]) return;        // more chunk blocks than chunks
         const int tid = threadIdx.x;
@@ -335,7 +342,7 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
         const int ncell = rd.P[0] * rd.P[1] * (DIM == 3 ? rd.P[2] : 1);
         constexpr int Q = 1 << DIM;                                      // bins per cell
         for (int k = tid; k < ncell * Q; k += BLOCK) s_off[k] = 0;
-        if (tid == 0) s_nocc = 0;
+        if (tid == 0) s_cmax = 0;
         __syncthreads();
         const int r = min(s_seg[K], rd.preg[p]);
         const int m = r / nch + (kc < r % nch ? 1 : 0);                  // particles of this chunk
@@ -355,19 +362,12 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
         for (int i = tid; i < m; i += BLOCK) atomicAdd(&s_off[bin(src(kc + i * nch))], 1);
         __syncthreads();
         // exclusive scan of the bin counts: contiguous runs of whole cells
-        // per thread; occupied cells counted
+        // per thread
         const int per = (ncell + BLOCK - 1) / BLOCK;
         const int c0 = tid * per * Q, c1 = min(ncell, tid * per + per) * Q;
-        int run = 0, occ = 0;
-        for (int k = c0; k < c1; k += Q) {
-            int n = 0;
-#pragma unroll
-            for (int h = 0; h < Q; ++h) n += s_off[k + h];
-            run += n;
-            occ += n > 0 ? 1 : 0;
-        }
+        int run = 0;
+        for (int k = c0; k < c1; ++k) run += s_off[k];
         s_sum[tid] = run;
-        if (occ) atomicAdd(&s_nocc, occ);
         __syncthreads();
         for (int off = 1; off < BLOCK; off <<= 1) {
             const int v = tid >= off ? s_sum[tid - off] : 0;
@@ -382,16 +382,54 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
             acc += v;
         }
         __syncthreads();
-        const int nocc = max(s_nocc, 1);
-        const int M = max(1, (m + nocc / 2) / nocc);
-        const int Rw = (m + M - 1) / M;
-        const int lastc = m - (Rw - 1) * M;
+        // cells of this thread (the same contiguous run): first sorted
+        // index and particle count
+        constexpr int CPT = MAX_PATCH_CELLS / BLOCK;
+        const int lane = tid & 63, wave = tid >> 6;
+        int cst[CPT], ccnt[CPT];
+        int cmax = 0;
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int k = tid * per + u;
+            const bool own = u < per && k < ncell;
+            cst[u] = own ? s_off[k * Q] : 0;
+            ccnt[u] = own ? (k + 1 < ncell ? s_off[(k + 1) * Q] : m) - cst[u] : 0;
+            cmax = max(cmax, ccnt[u]);
+        }
+        if (cmax) atomicMax(&s_cmax, cmax);
+        __syncthreads();
+        const int rmax = s_cmax;
+        int rb = 0;   // base[r]
+        for (int rk = 0; rk < rmax; ++rk) {
+            int f = 0;
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) f += ccnt[u] > rk ? 1 : 0;
+            int x = f;   // inclusive scan over the wavefront
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o);
+                if (lane >= o) x += y;
+            }
+            if (lane == 63) s_ws[rk & 1][wave] = x;
+            __syncthreads();   // s_ws[rk & 1] is rewritten two ranks later, after the next barrier
+            int pre = 0, tot = 0;
+#pragma unroll
+            for (int w = 0; w < BLOCK / 64; ++w) {
+                const int v = s_ws[rk & 1][w];
+                pre += w < wave ? v : 0;
+                tot += v;
+            }
+            int ex = rb + pre + x - f;
+#pragma unroll
+            for (int u = 0; u < CPT; ++u)
+                if (ccnt[u] > rk) s_pos[cst[u] + rk] = ex++;
+            rb += tot;
+        }
+        __syncthreads();
         for (int i = tid; i < m; i += BLOCK) {
             const long long si = src(kc + i * nch);
             const int j = atomicAdd(&s_off[bin(si)], 1);
-            const int row = j / M, col = j - row * M;
-            const int pos = col * Rw - max(0, col - lastc) + row;
-            copy_part<DIM, T>(rd.st, si, rd.lv, new_slot(rd, p, t, base + pos));
+            copy_part<DIM, T>(rd.st, si, rd.lv, new_slot(rd, p, t, base + s_pos[j]));
         }
         return;
     }

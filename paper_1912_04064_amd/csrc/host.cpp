@@ -302,7 +302,7 @@ static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::st
     size_t b = 0;
     b += align256((size_t)L.n_regions * F_NCOMP * L.rsize * 8);
     b += align256((size_t)L.seg_max * 3 * L.tsz * rsz);
-    b += 6 * align256((size_t)(L.n_patch + 1) * 4) + 7 * align256((size_t)(L.seg_max + 1) * 4);
+    b += 7 * align256((size_t)(L.n_patch + 1) * 4) + 7 * align256((size_t)(L.seg_max + 1) * 4);
     b += 2 * (size_t)L.cap_total * per + align256((size_t)L.cap_total * 4);
     b += 2 * (size_t)std::max<long long>(L.n_total, 1) * (per + 4);
     if (cfg->field_solver == PIC_SOLVER_PSATD) b += align256((size_t)9 * ncell * 16);
@@ -577,6 +577,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     d.preg = (int *)run_alloc(c, r, pb);
     d.fill = (int *)run_alloc(c, r, pb);
     d.cpre = (int *)run_alloc(c, r, pb);
+    d.spcnt = (int *)run_alloc(c, r, pb);
     d.sseg = (int *)run_alloc(c, r, sb);
     d.scnt = (int *)run_alloc(c, r, sb);
     d.spat = (int *)run_alloc(c, r, sb);
@@ -584,7 +585,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     d.scnt2 = (int *)run_alloc(c, r, sb);
     d.spat2 = (int *)run_alloc(c, r, sb);
     d.ctl = (Ctl *)run_alloc(c, r, sizeof(Ctl));
-    ok = d.fld && d.tiles && d.pseg && d.pseg2 && d.tot && d.preg && d.fill && d.cpre && d.sseg && d.scnt && d.spat &&
+    ok = d.fld && d.tiles && d.pseg && d.pseg2 && d.tot && d.preg && d.fill && d.cpre && d.spcnt && d.sseg && d.scnt && d.spat &&
          d.sseg2 && d.scnt2 && d.spat2 && d.ctl;
     make_store(c, r, d.st, L.cap_total, L.split, L.dims, ids, ok);
     make_store(c, r, d.lv, L.cap_total, L.split, L.dims, ids, ok);
@@ -614,6 +615,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     HIPCHK(c, hipMemsetAsync(d.fld, 0, (size_t)L.n_regions * F_NCOMP * L.rsize * 8, s));
     HIPCHK(c, hipMemsetAsync(d.tiles, 0, (size_t)L.seg_max * 3 * L.tsz * rsz, s));
     HIPCHK(c, hipMemsetAsync(d.pseg, 0, pb, s));
+    HIPCHK(c, hipMemsetAsync(d.spcnt, 0, pb, s));
     HIPCHK(c, hipMemsetAsync(d.sseg, 0, sb, s));
     HIPCHK(c, hipMemsetAsync(d.scnt, 0, sb, s));
     HIPCHK(c, hipMemsetAsync(d.nlv, 0, sb, s));

@@ -467,6 +467,7 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
                 if (s < rd.n_total) {
                     copy_part<DIM, T>(src, i, rd.sp, s);
                     rd.spatch[s] = (int)(-1ll - dst);
+                    atomicAdd(&rd.spcnt[-1ll - dst], 1);
                 } else {
                     err |= ERR_CAPACITY;
                 }

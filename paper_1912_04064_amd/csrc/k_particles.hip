@@ -464,7 +464,10 @@ __global__ __launch_bounds__(BLOCK) void relayout_commit_kernel(RunDev *__restri
     // every tile slot may now hold another patch's stale current: the next
     // particle phase rewrites all of them
     for (int k = blockIdx.x * BLOCK + threadIdx.x; k < rd.seg_max; k += stride) rd.tflag[k] = 1;
-    for (int p = blockIdx.x * BLOCK + threadIdx.x; p <= np; p += stride) rd.pseg[p] = rd.pseg2[p];
+    for (int p = blockIdx.x * BLOCK + threadIdx.x; p <= np; p += stride) {
+        rd.pseg[p] = rd.pseg2[p];
+        rd.spcnt[p] = 0;   // the parked particles are in the patch store now
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const Store t = rd.st;
         rd.st = rd.lv;

@@ -487,8 +487,10 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     const int cap = sseg[sg + 1] - (int)seg0;
     int n = gp(rd.scnt)[sg];
     n = n < cap ? n : cap;
-    // parked particles are pushed by the patch's first segment
-    const int nsp = sg == gp(rd.pseg)[q] ? min(rd.ctl->nspill, rd.n_total) : 0;
+    // parked particles are pushed by the patch's first segment, which scans
+    // the spill store only when some are parked for its patch
+    const int want = sg == gp(rd.pseg)[q] ? gp(rd.spcnt)[q] : 0;
+    const int nsp = want > 0 ? min(rd.ctl->nspill, rd.n_total) : 0;
     SDMD_GLOBAL int *tflag = gp(rd.tflag);
     if (n == 0 && nsp == 0) {
         // nothing to push (a vacuum patch): no window, no tile work; the
@@ -569,7 +571,8 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     // through the overflow leaver store.  The spill store is scanned in
     // rounds of SPC entries, all loads of a round in flight at once; the
     // round's matches are listed in LDS and pushed.
-    for (int c0 = 0; c0 < nsp; c0 += SPC) {
+    int found = 0;   // parked particles of this patch pushed so far (uniform)
+    for (int c0 = 0; c0 < nsp && found < want; c0 += SPC) {
         if (tid == 0) s_ns = 0;
         __syncthreads();
         int pv[SPK];
@@ -591,6 +594,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
         }
         __syncthreads();
         const int ns = s_ns;
+        found += ns;
         for (int base = 0; base < ns; base += BLOCK) {
             const int j = base + tid;
             const bool mine = j < ns;
@@ -623,6 +627,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     if (tid == 0) {
         gp(rd.scnt)[sg] = stay;
         gp(rd.nlv)[sg] = left;
+        if (want > 0) gp(rd.spcnt)[q] = 0;   // consumed; this step's post kernel parks anew
     }
     __syncthreads();
     // flush the tile in the tile precision (transfer (i) reads it)

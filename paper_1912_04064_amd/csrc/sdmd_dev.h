@@ -133,6 +133,7 @@ struct RunDev {
     int *spat;           // [seg_max] patch of each segment
     int *pseg2, *sseg2, *scnt2, *spat2;   // re-layout: the new segment layout
     int *tot, *preg, *fill;               // re-layout: per-patch totals, patch-store part, spill fill
+    int *spcnt;                           // [n_patch] particles parked in the spill store for the patch
     int *cpre;                            // re-layout: first move chunk of each patch [n_patch + 1]
     Store st, lv, sp;    // patch store, leaver / scratch store, spill store
     int *lpatch, *spatch;

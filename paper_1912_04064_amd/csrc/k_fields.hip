@@ -160,6 +160,7 @@ __global__ __launch_bounds__((YeeTile<DIM, TXC>::NT)) void yee_kernel(const RunD
     constexpr int AXM = EXS > EYS ? (EXS > EZS ? EXS : EZS) : (EYS > EZS ? EYS : EZS);
     constexpr int NCM = cover_bound(EXS) * cover_bound(EYS) * (DIM == 3 ? cover_bound(EZS) : 1);
     __shared__ double sE[3][HN];
+    __shared__ double sB[3][HN];   // B^{n+1/2} on tile + halo, read again by Faraday
     __shared__ double sJ[FILT ? 4 : 1][EN];   // 3 components + one sweep buffer
     __shared__ int2 s_ax[3][AXM];             // gather tables
     __shared__ int2 s_rng[NCM];
@@ -301,14 +302,18 @@ __global__ __launch_bounds__((YeeTile<DIM, TXC>::NT)) void yee_kernel(const RunD
             continue;
         }
         double e0, e1, e2;
+        const double b0 = Bo[0][p], b1 = Bo[1][p], b2 = Bo[2][p];
+        sB[0][h] = b0;
+        sB[1][h] = b1;
+        sB[2][h] = b2;
         if constexpr (DIM == 2) {
-            e0 = Eo[0][p] + dt * ((Bo[2][p] - Bo[2][p - sy]) / dy - J[0]);
-            e1 = Eo[1][p] + dt * (-((Bo[2][p] - Bo[2][p - sx]) / dx) - J[1]);
-            e2 = Eo[2][p] + dt * ((Bo[1][p] - Bo[1][p - sx]) / dx - (Bo[0][p] - Bo[0][p - sy]) / dy - J[2]);
+            e0 = Eo[0][p] + dt * ((b2 - Bo[2][p - sy]) / dy - J[0]);
+            e1 = Eo[1][p] + dt * (-((b2 - Bo[2][p - sx]) / dx) - J[1]);
+            e2 = Eo[2][p] + dt * ((b1 - Bo[1][p - sx]) / dx - (b0 - Bo[0][p - sy]) / dy - J[2]);
         } else {
-            e0 = Eo[0][p] + dt * ((Bo[2][p] - Bo[2][p - sy]) / dy - (Bo[1][p] - Bo[1][p - sz]) / dz - J[0]);
-            e1 = Eo[1][p] + dt * ((Bo[0][p] - Bo[0][p - sz]) / dz - (Bo[2][p] - Bo[2][p - sx]) / dx - J[1]);
-            e2 = Eo[2][p] + dt * ((Bo[1][p] - Bo[1][p - sx]) / dx - (Bo[0][p] - Bo[0][p - sy]) / dy - J[2]);
+            e0 = Eo[0][p] + dt * ((b2 - Bo[2][p - sy]) / dy - (b1 - Bo[1][p - sz]) / dz - J[0]);
+            e1 = Eo[1][p] + dt * ((b0 - Bo[0][p - sz]) / dz - (b2 - Bo[2][p - sx]) / dx - J[1]);
+            e2 = Eo[2][p] + dt * ((b1 - Bo[1][p - sx]) / dx - (b0 - Bo[0][p - sy]) / dy - J[2]);
         }
         sE[0][h] = e0;
         sE[1][h] = e1;
@@ -333,7 +338,7 @@ __global__ __launch_bounds__((YeeTile<DIM, TXC>::NT)) void yee_kernel(const RunD
             const int h = (tz * HY + ty) * HX + tx;
             const int hxp = h + 1, hyp = h + HX, hzp = h + HX * HY;
             const long long p = rindex(rd, li, lj, DIM == 3 ? lk : 0);
-            const double bx = Bo[0][p], by = Bo[1][p], bz = Bo[2][p];
+            const double bx = sB[0][h], by = sB[1][h], bz = sB[2][h];
             double nbx, nby, nbz;
             if constexpr (DIM == 2) {
                 nbx = bx - dt * ((sE[2][hyp] - sE[2][h]) / dy);

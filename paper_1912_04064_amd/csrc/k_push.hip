@@ -483,9 +483,11 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     const int TPs = lds_plane<DIM>(T0 * T1), TSs = TPs * (DIM == 3 ? P[2] + 5 : 1);
 
     const SDMD_GLOBAL int *sseg = gp(rd.sseg);
-    const long long seg0 = sseg[sg];
-    const int cap = sseg[sg + 1] - (int)seg0;
-    int n = gp(rd.scnt)[sg];
+    // segment bounds and count: uniform values, kept in scalar registers so
+    // that the particle addresses below are scalar bases + 32-bit offsets
+    const long long seg0 = __builtin_amdgcn_readfirstlane(sseg[sg]);
+    const int cap = __builtin_amdgcn_readfirstlane(sseg[sg + 1]) - (int)seg0;
+    int n = __builtin_amdgcn_readfirstlane(gp(rd.scnt)[sg]);
     n = n < cap ? n : cap;
     // parked particles are pushed by the patch's first segment, which scans
     // the spill store only when some are parked for its patch
@@ -527,13 +529,15 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
 
     // the next chunk's particles are loaded before this chunk is pushed: its
     // slots lie above every slot this chunk's stores can reach
+    const SegStore sst = seg_store<T>(rd.st, seg0), slv = seg_store<T>(rd.lv, seg0);
+    SDMD_GLOBAL int *lpatch = gp(rd.lpatch) + seg0;
     Part<T> nxt;
-    if (tid < n) load_part<DIM, T>(rd.st, seg0 + tid, nxt);
+    if (tid < n) load_part<DIM, T>(sst, (uint32_t)tid, nxt);
     for (int base = 0; base < n; base += BLOCK, ++chunk) {
         const int i = base + tid;
         const bool valid = i < n;
         Part<T> pt = nxt;
-        if (i + BLOCK < n) load_part<DIM, T>(rd.st, seg0 + i + BLOCK, nxt);
+        if (i + BLOCK < n) load_part<DIM, T>(sst, (uint32_t)(i + BLOCK), nxt);
         int dest = q;
         if (valid) dest = push_one<DIM, T, PX>(rd, s_win, s_tile, p0, P, pt, err);
         const bool st = valid && dest == q;
@@ -555,13 +559,13 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
         }
         if (st) {
             const int slot = wb + __popcll(ms & lt);
-            store_part<DIM, T>(rd.st, seg0 + slot, pt, slot != i);
+            store_part<DIM, T>(sst, (uint32_t)slot, pt, slot != i);
         }
         if (lv) {
             // the patch's own leaver region: stayers + leavers <= n <= capacity
-            const long long slot = seg0 + lb + __popcll(ml & lt);
-            store_part<DIM, T>(rd.lv, slot, pt, true);
-            gp(rd.lpatch)[slot] = dest;
+            const int slot = lb + __popcll(ml & lt);
+            store_part<DIM, T>(slv, (uint32_t)slot, pt, true);
+            lpatch[slot] = dest;
         }
         stay += tot;
         left += ltot;

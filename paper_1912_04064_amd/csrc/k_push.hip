@@ -147,8 +147,9 @@ __device__ __forceinline__ void deposit2d(double *Jb, int T0, int TS, const R S0
     }
     // In the 4-slot frame, a lane that kept its node on an axis holds zeros
     // in that axis's last slot (and its running sum ends one slot early):
-    // those adds are skipped lane by lane.  An LDS add costs bank cycles
-    // per active lane, so the masked lanes are free.
+    // those adds are masked lane by lane.  A masked lane takes no part in
+    // the same-address collisions that serialise an LDS add, and an add no
+    // lane needs is branched over.
 #pragma unroll
     for (int n = 0; n < NF; ++n)
 #pragma unroll
@@ -219,9 +220,9 @@ __device__ __forceinline__ void deposit3d(double *Jb, int T0, int TP, int TS, co
 // sizes read from the run descriptor.
 //
 // The current tile accumulates in FP64 in both precision forms: on gfx950
-// ds_add_f64 sustains ~23x the rate of ds_add_f32 (measured: 7.5 vs 0.33
-// lane-atomics per clock per CU); contributions are still computed in the
-// particle precision.
+// a wavefront's ds_add_f64 takes ~8.6 clocks of a CU's LDS and a
+// ds_add_f32 ~193 (measured, consecutive addresses); contributions are
+// still computed in the particle precision.
 template <int DIM, class T, int PX>
 __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real *__restrict__ win, double *tile,
                                         const int p0[3], const int Prt[3], Part<T> &p, int &err)

@@ -183,6 +183,44 @@ def bench_serve(args):
                        "slots": args.slots, "budget_gb": args.budget_gb}}
 
 
+def bench_precision(args):
+    """The precision forms side by side on the same GPU: the LWFA input run
+    in FP64 and in the FP32 split form from the same particles and fields;
+    throughput of each and the FP32 form's relative L2 difference from the
+    FP64 run (fields per family, particle momenta) after the same steps."""
+    import dataclasses
+    import torch
+    from paper_1912_04064_amd import binding as B
+    base = workload(args.workload)
+    res, state = {}, {}
+    for prec in ("fp64", "fp32s"):
+        wl = dataclasses.replace(base, precision=prec)
+        ctx = B.Context([wl], track_ids=True, graph=not args.no_graph)
+        d0 = ctx.diag(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(args.steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        F = ctx.fields(0, B.F_E | B.F_B | B.F_J)
+        parts = B.sort_by_id(ctx.particles(0))
+        d = ctx.diag(0)
+        ctx.close()
+        u0 = d0["U_E"] + d0["U_B"] + d0["K"]
+        res[prec] = {"pushes_per_s": wl.n_particles * args.steps / dt, "ms_per_step": dt * 1e3 / args.steps,
+                     "energy_rel_change": (d["U_E"] + d["U_B"] + d["K"]) / u0 - 1.0,
+                     "gauss_residual": d["gauss_residual"]}
+        state[prec] = (F, parts)
+        print(f"[bench] {prec}: {res[prec]}", file=sys.stderr, flush=True)
+    (F64, p64), (F32, p32) = state["fp64"], state["fp32s"]
+    rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    diff = {"E": rel(F32[0:3], F64[0:3]), "B": rel(F32[3:6], F64[3:6]), "J": rel(F32[6:9], F64[6:9]),
+            "u": rel(np.stack([p32["ux"], p32["uy"], p32["uz"]]), np.stack([p64["ux"], p64["uy"], p64["uz"]]))}
+    return {"metric": "FP32 split vs FP64 on the same GPU", "unit": "relative L2 difference", "n_gpus": 1,
+            "steps": args.steps, "higher_is_better": False, "vs_baseline": None, "data": "synthetic",
+            "config": {"workload": base.name}, "forms": res, "fp32s_vs_fp64": diff}
+
+
 def bench_sdsd(args):
     """The paper's central comparison on one GPU: the LWFA input with fields
     on regions (SDMD, 4 regions of 512 x 256) against fields on the patches
@@ -236,6 +274,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--compare-sdsd", action="store_true",
                     help="fields on regions (SDMD) vs on patches (SDSD) for patch sizes 8, 16, 32")
+    ap.add_argument("--compare-precision", action="store_true",
+                    help="the workload in FP64 and in the FP32 split form: throughput and their difference")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 512 MiB device copy first (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -253,6 +293,9 @@ def main():
         return
     if args.compare_sdsd:
         print(json.dumps(bench_sdsd(args)), flush=True)
+        return
+    if args.compare_precision:
+        print(json.dumps(bench_precision(args)), flush=True)
         return
     if args.workload == "scan":
         print(json.dumps(bench_scan(args)), flush=True)
@@ -272,6 +315,8 @@ def main():
     ctx.step(args.warmup)
     torch.cuda.synchronize()
     print(f"[bench] warmup {args.warmup} steps done", file=sys.stderr, flush=True)
+    d0 = ctx.diag(0)   # energies before the timed steps (synchronising, outside the timing)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.step(args.steps)
     torch.cuda.synchronize()
@@ -321,6 +366,11 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": push_traffic(args.workload),
                      "bytes_per_launch": alg_push},
         "relayouts": d["n_relayout"],
+        # total energy (fields + electrons) over the timed steps, and the
+        # Gauss-law residual div_h E - rho against the initial state
+        "energy": {"start": d0["U_E"] + d0["U_B"] + d0["K"], "end": d["U_E"] + d["U_B"] + d["K"],
+                   "rel_change": (d["U_E"] + d["U_B"] + d["K"]) / (d0["U_E"] + d0["U_B"] + d0["K"]) - 1.0,
+                   "gauss_residual": d["gauss_residual"]},
     }
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

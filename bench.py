@@ -281,7 +281,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
-              "(one region per GPU) is a design, not part of this build", file=sys.stderr)
+              "(one region per GPU) is described, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

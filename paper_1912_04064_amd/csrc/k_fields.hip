@@ -70,7 +70,10 @@ __device__ __forceinline__ void gather_tables(const RunDev &rd, const GatherBox 
         const int qx = wrapm(b.pu0[0] + cx, rd.np[0]), qy = wrapm(b.pu0[1] + cy, rd.np[1]);
         const int qz = DIM == 3 ? wrapm(b.pu0[2] + cz, rd.np[2]) : 0;
         const int q = qx + rd.np[0] * (qy + rd.np[1] * qz);
-        s_rng[t] = make_int2(pseg[q], pseg[q + 1]);
+        // a patch whose one segment holds no current this step (a vacuum
+        // patch: the particle kernel left its tile at zero) is skipped
+        const int k0 = pseg[q], k1 = pseg[q + 1];
+        s_rng[t] = make_int2(k0, (k1 - k0 == 1 && gp(rd.tflag)[k0] == 0) ? k0 : k1);
     }
 }
 

@@ -413,7 +413,7 @@ __device__ __forceinline__ void ghost_coords(const RunDev &rd, int k, int &li, i
 
 // copy components [c0, c0+nc) of ghost node gk (run-global ghost index)
 // from the interior of the region that owns the wrapped node
-__device__ __forceinline__ void ghost_copy(const RunDev &rd, int gk, const int *comps, int nc)
+__device__ __forceinline__ void ghost_copy(const RunDev &rd, int gk, const int *comps, int nc)   // nc <= 9
 {
     const int region = gk / rd.ghosts;
     int li, lj, lk;
@@ -426,7 +426,15 @@ __device__ __forceinline__ void ghost_copy(const RunDev &rd, int gk, const int *
     const long long ps = rindex(rd, g[0] - sr[0] * rd.rs[0], g[1] - sr[1] * rd.rs[1],
                                 rd.dims == 3 ? g[2] - sr[2] * rd.rs[2] : 0);
     const long long pd = rindex(rd, li, lj, lk);
-    for (int i = 0; i < nc; ++i) rcomp(rd, region, comps[i])[pd] = rcomp(rd, src, comps[i])[ps];
+    // all loads, then all stores: a ghost node is never an interior node, so
+    // one round trip to memory replaces nc dependent ones
+    double v[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        if (i < nc) v[i] = gp((const double *)rcomp(rd, src, comps[i]))[ps];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        if (i < nc) gp(rcomp(rd, region, comps[i]))[pd] = v[i];
 }
 
 // ------------------------------------------------------------ post kernel

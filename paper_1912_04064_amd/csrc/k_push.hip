@@ -452,7 +452,8 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     constexpr int SPK = (SPC + BLOCK - 1) / BLOCK;
     __shared__ R s_win[6 * WN];
     __shared__ double s_tile[3 * TN];
-    __shared__ int s_wsum[2][NW], s_lsum[2][NW];
+    __shared__ int s_wsum[NW], s_left, s_sw[NW];
+    __shared__ int s_hole[BLOCK];
     __shared__ int s_sl[SPC];                          // this patch's parked particles found in a round
     __shared__ int s_ns;
 
@@ -521,20 +522,27 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
             (R)A[rindex(rd, o[0] - 1 + wx, o[1] - 1 + wy, DIM == 3 ? o[2] - 1 + wz : 0)];
     }
     for (int idx = tid; idx < 3 * TSs; idx += BLOCK) s_tile[idx] = 0.0;
+    if (tid == 0) s_left = 0;
     __syncthreads();
 
     int err = 0;
-    int stay = 0, left = 0;   // stayers compacted / leavers written so far (uniform)
-    int chunk = 0;
+    int sw = 0;   // stayers of this wavefront so far (uniform over the wavefront)
     const unsigned long long lt = (1ull << lane) - 1ull;
+    // slot k of wavefront w's sequence (the slots it visits, chunk by chunk)
+    auto wslot = [&](int w, int k) { return (k >> 6) * BLOCK + (w << 6) + (k & 63); };
 
-    // the next chunk's particles are loaded before this chunk is pushed: its
-    // slots lie above every slot this chunk's stores can reach
+    // Each wavefront compacts its stayers into its own sequence of slots: its
+    // k-th stayer goes to wslot(w, k), never above the slot it was read from,
+    // so no wavefront overwrites a particle another has not read yet and the
+    // chunks need no barrier.  Leavers take slots of the segment's leaver
+    // region from an LDS counter.  The stayers left at or above the final
+    // count then fill the holes below it.  The next chunk's particles are
+    // loaded before this chunk is pushed.
     const SegStore sst = seg_store<T>(rd.st, seg0), slv = seg_store<T>(rd.lv, seg0);
     SDMD_GLOBAL int *lpatch = gp(rd.lpatch) + seg0;
     Part<T> nxt;
     if (tid < n) load_part<DIM, T>(sst, (uint32_t)tid, nxt);
-    for (int base = 0; base < n; base += BLOCK, ++chunk) {
+    for (int base = 0; base < n; base += BLOCK) {
         const int i = base + tid;
         const bool valid = i < n;
         Part<T> pt = nxt;
@@ -544,32 +552,77 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
         const bool st = valid && dest == q;
         const bool lv = valid && dest != q;
         const unsigned long long ms = __ballot(st), ml = __ballot(lv);
-        if (lane == 0) {
-            s_wsum[chunk & 1][wave] = __popcll(ms);
-            s_lsum[chunk & 1][wave] = __popcll(ml);
-        }
-        __syncthreads();   // every particle of the chunk is loaded before any store
-        int wb = stay, lb = left, tot = 0, ltot = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            const int c = s_wsum[chunk & 1][w], l = s_lsum[chunk & 1][w];
-            wb += w < wave ? c : 0;
-            lb += w < wave ? l : 0;
-            tot += c;
-            ltot += l;
-        }
         if (st) {
-            const int slot = wb + __popcll(ms & lt);
+            const int slot = wslot(wave, sw + __popcll(ms & lt));
             store_part<DIM, T>(sst, (uint32_t)slot, pt, slot != i);
         }
-        if (lv) {
-            // the patch's own leaver region: stayers + leavers <= n <= capacity
-            const int slot = lb + __popcll(ml & lt);
-            store_part<DIM, T>(slv, (uint32_t)slot, pt, true);
-            lpatch[slot] = dest;
+        sw += __popcll(ms);
+        if (ml) {
+            // the segment's own leaver region: stayers + leavers <= n <= capacity
+            int lb = 0;
+            if (lane == 0) lb = atomicAdd(&s_left, __popcll(ml));
+            lb = __shfl(lb, 0);
+            if (lv) {
+                const int slot = lb + __popcll(ml & lt);
+                store_part<DIM, T>(slv, (uint32_t)slot, pt, true);
+                lpatch[slot] = dest;
+            }
         }
-        stay += tot;
-        left += ltot;
+    }
+    if (lane == 0) s_sw[wave] = sw;
+    __syncthreads();   // every stayer is in its wavefront's sequence
+    const int left = s_left;
+    const int stay = n - left;
+    if (left > 0) {
+        // Slot p < n is a hole when its wavefront kept fewer stayers than p's
+        // rank in that wavefront's sequence.  The holes below `stay` and the
+        // stayers at or above it are equally many; the r-th of each are
+        // paired (slot order), BLOCK pairs per round.
+        auto hole = [&](int p) { return (p / BLOCK) * 64 + (p & 63) >= s_sw[(p % BLOCK) >> 6]; };
+        int lo = stay;   // the first hole
+#pragma unroll
+        for (int w = 0; w < NW; ++w) lo = min(lo, wslot(w, s_sw[w]));
+        // rank of each flagged slot of the block starting at b among the flagged slots so far
+        auto rank_in = [&](bool f, int &run, int &tot) {
+            const unsigned long long m = __ballot(f);
+            if (lane == 0) s_wsum[wave] = __popcll(m);
+            __syncthreads();
+            int before = run;
+            tot = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                before += w < wave ? s_wsum[w] : 0;
+                tot += s_wsum[w];
+            }
+            __syncthreads();   // s_wsum is reused by the next block
+            run += tot;
+            return before + __popcll(m & lt);
+        };
+        for (int r0 = 0;; r0 += BLOCK) {
+            int run = 0, tot = 0;
+            for (int b = lo; b < stay; b += BLOCK) {
+                const int pz = b + tid;
+                const bool f = pz < stay && hole(pz);
+                const int rk = rank_in(f, run, tot);
+                if (f && rk >= r0 && rk < r0 + BLOCK) s_hole[rk - r0] = pz;
+            }
+            const int nh = min(run - r0, BLOCK);   // run: all holes below `stay`
+            if (nh <= 0) break;
+            __syncthreads();
+            int run2 = 0;
+            for (int b = stay; b < n; b += BLOCK) {
+                const int pz = b + tid;
+                const bool f = pz < n && !hole(pz);
+                const int rk = rank_in(f, run2, tot);
+                if (f && rk >= r0 && rk < r0 + nh) {
+                    Part<T> mv;
+                    load_part<DIM, T>(sst, (uint32_t)pz, mv);
+                    store_part<DIM, T>(sst, (uint32_t)s_hole[rk - r0], mv, true);
+                }
+            }
+            if (run <= r0 + BLOCK) break;
+            __syncthreads();   // s_hole is rewritten by the next round
+        }
     }
 
     // particles parked in the spill store that belong to this patch re-enter

@@ -414,6 +414,39 @@ def test_converging_flow_spills_and_relayouts():
         assert max(errs.values()) < (1e-9 if prec == "fp64" else 1e-3), errs
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32s"])
+def test_streaming_plasma_many_leavers(prec):
+    """A dense plasma streaming diagonally at relativistic speed: every step
+    several per cent of each patch's particles leave it, from every chunk of
+    its segments (each 8x8 patch holds two segments of ~1300): the stayers'
+    compaction and the filling of the holes they leave are exercised
+    throughout.  Results match the oracle particle by particle."""
+    say(f"case: streaming plasma {prec}")
+    n, d = (32, 32), (1.0, 1.0)
+    rng = np.random.default_rng(11)
+    N = 32 * 32 * 40
+    x = rng.uniform(0, 32, N)
+    y = rng.uniform(0, 32, N)
+    ux = 2.0 + rng.normal(0, 0.2, N)          # ~0.9 c along x
+    uy = 0.6 + rng.normal(0, 0.2, N)
+    parts = {"x": x, "y": y, "z": np.zeros(N), "ux": ux, "uy": uy, "uz": np.zeros(N), "w": np.full(N, 0.025),
+             "id": np.arange(N, dtype=np.uint32)}
+    wl = WL.Workload(name="stream", dims=2, n=n, d=d, dt=0.6, patch=(8, 8), nreg=(2, 2), steps=0, precision=prec,
+                     parts=parts, q=-1e-3)
+    Fg, gp, diag = gpu_run(wl, 30)
+    Fo, P, g = oracle_run(wl, 30)
+    say(f"{prec}: relayouts {diag['n_relayout']} spill {diag['n_spill']} patch min/max "
+        f"{diag['patch_min']}/{diag['patch_max']}")
+    assert diag["n_particles"] == N
+    assert np.array_equal(gp["id"], np.arange(N))
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    assert wrapped_diff(gp["x"], P.x, 32.0).max() < tol
+    assert wrapped_diff(gp["y"], P.y, 32.0).max() < tol
+    assert np.abs(gp["ux"] - P.ux).max() < (1e-9 if prec == "fp64" else 1e-4)
+    errs = max_family_error(Fg, Fo)
+    assert max(errs.values()) < (1e-9 if prec == "fp64" else 1e-3), errs
+
+
 def test_empty_run_and_ragged_grid():
     say("case: empty + ragged")
     parts = {k: np.zeros(0) for k in ("x", "y", "z", "ux", "uy", "uz", "w")}

@@ -77,8 +77,17 @@ __device__ __forceinline__ void gather_tables(const RunDev &rd, const GatherBox 
     }
 }
 
-// J at box node (ex, ey, ez)
-template <int DIM, int AXM, class R>
+// J at box node (ex, ey, ez): the sum over the covering patches (z, y, x
+// ascending) and their segments (ascending) of the segment tiles.
+//
+// With patches of at least 5 cells a node lies within two nodes of at most
+// one edge of its patch per axis, so at most two patches per axis cover it.
+// The first SEGU segments of each of those 2^DIM candidates are loaded
+// before any is summed -- an absent one reads the first word of the tile
+// store instead and is discarded -- so the whole sum waits on memory once
+// rather than once per segment; further segments of a heavy patch follow
+// in a loop.  The order of the additions is the same in both forms.
+template <int DIM, int AXM, int SEGU, class R>
 __device__ __forceinline__ void gather_J(const RunDev &rd, const SDMD_GLOBAL R *__restrict__ tiles,
                                          const GatherBox &b, const int2 (*s_ax)[AXM], const int2 *s_rng, int ex,
                                          int ey, int ez, double J[3])
@@ -95,21 +104,66 @@ __device__ __forceinline__ void gather_J(const RunDev &rd, const SDMD_GLOBAL R *
     const long long tsz = rd.tsz;
     const int TA0 = rd.TA[0], TA1 = rd.TA[1];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int oz = lo[2]; oz <= hi[2]; ++oz)
-        for (int oy = lo[1]; oy <= hi[1]; ++oy)
-            for (int ox = lo[0]; ox <= hi[0]; ++ox) {
-                const int2 r = s_rng[((c[2] + oz) * b.nc[1] + (c[1] + oy)) * b.nc[0] + (c[0] + ox)];
-                const int tx = l[0] - ox * P[0] + 2;
-                const int ty = l[1] - oy * P[1] + 2;
-                const int tz = DIM == 3 ? l[2] - oz * P[2] + 2 : 0;
-                const int off = (tz * TA1 + ty) * TA0 + tx;
-                for (int sg = r.x; sg < r.y; ++sg) {
-                    const SDMD_GLOBAL R *t = tiles + (long long)sg * 3 * tsz + off;
+    const bool wide = SEGU > 0 && P[0] >= 5 && P[1] >= 5 && (DIM == 2 || P[2] >= 5);
+    if (wide) {
+        if constexpr (SEGU > 0) {
+            constexpr int NC = 1 << DIM;
+            int2 rg[NC];
+            int off[NC];
+            R v[NC][SEGU][3];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                const int o[3] = {lo[0] + (k & 1), lo[1] + ((k >> 1) & 1), DIM == 3 ? lo[2] + ((k >> 2) & 1) : 0};
+                const bool in = o[0] <= hi[0] && o[1] <= hi[1] && (DIM == 2 || o[2] <= hi[2]);
+                // o is in [-1, 1] per axis: the table holds one patch beyond the
+                // box on every side, so the read is in range even when !in
+                const int2 r = s_rng[((c[2] + o[2]) * b.nc[1] + (c[1] + o[1])) * b.nc[0] + (c[0] + o[0])];
+                rg[k] = make_int2(r.x, in ? r.y : r.x);
+                off[k] = ((DIM == 3 ? l[2] - o[2] * P[2] + 2 : 0) * TA1 + (l[1] - o[1] * P[1] + 2)) * TA0 +
+                         (l[0] - o[0] * P[0] + 2);
+#pragma unroll
+                for (int j = 0; j < SEGU; ++j) {
+                    const bool ok = rg[k].x + j < rg[k].y;
+                    const SDMD_GLOBAL R *t = tiles + (ok ? (long long)(rg[k].x + j) * 3 * tsz + off[k] : 0ll);
+                    v[k][j][0] = t[0];
+                    v[k][j][1] = t[tsz];
+                    v[k][j][2] = t[2 * tsz];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+#pragma unroll
+                for (int j = 0; j < SEGU; ++j)
+                    if (rg[k].x + j < rg[k].y) {
+                        s0 += (double)v[k][j][0];
+                        s1 += (double)v[k][j][1];
+                        s2 += (double)v[k][j][2];
+                    }
+                for (int sg = rg[k].x + SEGU; sg < rg[k].y; ++sg) {
+                    const SDMD_GLOBAL R *t = tiles + (long long)sg * 3 * tsz + off[k];
                     s0 += (double)t[0];
                     s1 += (double)t[tsz];
                     s2 += (double)t[2 * tsz];
                 }
             }
+        }
+    } else {
+        for (int oz = lo[2]; oz <= hi[2]; ++oz)
+            for (int oy = lo[1]; oy <= hi[1]; ++oy)
+                for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+                    const int2 r = s_rng[((c[2] + oz) * b.nc[1] + (c[1] + oy)) * b.nc[0] + (c[0] + ox)];
+                    const int tx = l[0] - ox * P[0] + 2;
+                    const int ty = l[1] - oy * P[1] + 2;
+                    const int tz = DIM == 3 ? l[2] - oz * P[2] + 2 : 0;
+                    const int of = (tz * TA1 + ty) * TA0 + tx;
+                    for (int sg = r.x; sg < r.y; ++sg) {
+                        const SDMD_GLOBAL R *t = tiles + (long long)sg * 3 * tsz + of;
+                        s0 += (double)t[0];
+                        s1 += (double)t[tsz];
+                        s2 += (double)t[2 * tsz];
+                    }
+                }
+    }
     J[0] = s0;
     J[1] = s1;
     J[2] = s2;
@@ -146,6 +200,12 @@ template <int DIM, bool FILT>
 struct FilterMax {
     static constexpr int K = FILT ? (DIM == 2 ? 4 : 2) : 0;
 };
+
+// segments per covering patch that the gather of the Ampere step loads
+// before summing (the filter's gather of its widened box, two nodes per
+// thread, keeps the plain loop: measured faster there)
+template <int DIM, class T>
+constexpr int GATHER_SEGU = DIM == 2 ? 2 : 1;
 
 template <int DIM, class T, int TXC, bool FILT>
 __global__ __launch_bounds__((YeeTile<DIM, TXC>::NT)) void yee_kernel(const RunDev *__restrict__ runs,
@@ -243,7 +303,7 @@ __global__ __launch_bounds__((YeeTile<DIM, TXC>::NT)) void yee_kernel(const RunD
         for (int h = tid; h < nb; h += NT) {
             const int ex = h % bx, ey = (h / bx) % by, ez = h / (bx * by);
             double J[3];
-            gather_J<DIM, AXM, R>(rd, tiles, gb, s_ax, s_rng, ex, ey, ez, J);
+            gather_J<DIM, AXM, 0, R>(rd, tiles, gb, s_ax, s_rng, ex, ey, ez, J);
             const int e = (ez * EYS + ey) * EXS + ex;
             sJ[0][e] = J[0];
             sJ[1][e] = J[1];
@@ -284,6 +344,25 @@ __global__ __launch_bounds__((YeeTile<DIM, TXC>::NT)) void yee_kernel(const RunD
         const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
         const int li = ox + hx, lj = oy + hy, lk = oz + hz;
         if (li > rs0 || lj > rs1 || (DIM == 3 && lk > rs2)) continue;
+        const long long p = rindex(rd, li, lj, DIM == 3 ? lk : 0);
+        // E^n, B^{n+1/2} and the B neighbours Ampere needs are loaded before
+        // the current, so their latency overlaps the gather's
+        double fe[3] = {0, 0, 0}, fb[3] = {0, 0, 0}, fn[6] = {0, 0, 0, 0, 0, 0};
+        if (!rd.solver) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                fb[c] = Bo[c][p];
+                fe[c] = Eo[c][p];
+            }
+            fn[0] = Bo[2][p - sy];
+            fn[1] = Bo[2][p - sx];
+            fn[2] = Bo[1][p - sx];
+            fn[3] = Bo[0][p - sy];
+            if constexpr (DIM == 3) {
+                fn[4] = Bo[1][p - sz];
+                fn[5] = Bo[0][p - sz];
+            }
+        }
         double J[3];
         if constexpr (FILT) {
             const int e = ((DIM == 3 ? hz + kf : 0) * EYS + hy + kf) * EXS + hx + kf;
@@ -291,9 +370,8 @@ __global__ __launch_bounds__((YeeTile<DIM, TXC>::NT)) void yee_kernel(const RunD
             J[1] = sJ[1][e];
             J[2] = sJ[2][e];
         } else {
-            gather_J<DIM, AXM, R>(rd, tiles, gb, s_ax, s_rng, hx, hy, hz, J);
+            gather_J<DIM, AXM, GATHER_SEGU<DIM, T>, R>(rd, tiles, gb, s_ax, s_rng, hx, hy, hz, J);
         }
-        const long long p = rindex(rd, li, lj, DIM == 3 ? lk : 0);
         if (rd.solver) {
             // spectral solver: this kernel only provides J (the tiles' sum,
             // filtered); E and B are advanced in Fourier space
@@ -305,18 +383,18 @@ __global__ __launch_bounds__((YeeTile<DIM, TXC>::NT)) void yee_kernel(const RunD
             continue;
         }
         double e0, e1, e2;
-        const double b0 = Bo[0][p], b1 = Bo[1][p], b2 = Bo[2][p];
+        const double b0 = fb[0], b1 = fb[1], b2 = fb[2];
         sB[0][h] = b0;
         sB[1][h] = b1;
         sB[2][h] = b2;
         if constexpr (DIM == 2) {
-            e0 = Eo[0][p] + dt * ((b2 - Bo[2][p - sy]) / dy - J[0]);
-            e1 = Eo[1][p] + dt * (-((b2 - Bo[2][p - sx]) / dx) - J[1]);
-            e2 = Eo[2][p] + dt * ((b1 - Bo[1][p - sx]) / dx - (b0 - Bo[0][p - sy]) / dy - J[2]);
+            e0 = fe[0] + dt * ((b2 - fn[0]) / dy - J[0]);
+            e1 = fe[1] + dt * (-((b2 - fn[1]) / dx) - J[1]);
+            e2 = fe[2] + dt * ((b1 - fn[2]) / dx - (b0 - fn[3]) / dy - J[2]);
         } else {
-            e0 = Eo[0][p] + dt * ((b2 - Bo[2][p - sy]) / dy - (b1 - Bo[1][p - sz]) / dz - J[0]);
-            e1 = Eo[1][p] + dt * ((b0 - Bo[0][p - sz]) / dz - (b2 - Bo[2][p - sx]) / dx - J[1]);
-            e2 = Eo[2][p] + dt * ((b1 - Bo[1][p - sx]) / dx - (b0 - Bo[0][p - sy]) / dy - J[2]);
+            e0 = fe[0] + dt * ((b2 - fn[0]) / dy - (b1 - fn[4]) / dz - J[0]);
+            e1 = fe[1] + dt * ((b0 - fn[5]) / dz - (b2 - fn[1]) / dx - J[1]);
+            e2 = fe[2] + dt * ((b1 - fn[2]) / dx - (b0 - fn[3]) / dy - J[2]);
         }
         sE[0][h] = e0;
         sE[1][h] = e1;

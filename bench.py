@@ -64,6 +64,17 @@ def particle_bytes(wl):
     return rd + wr
 
 
+VALU_PEAK = 256 * 2.4e9   # wavefront VALU instructions per second (no packed FP32)
+
+
+def valu_line(insts, launch_ms):
+    if insts is None:
+        return None
+    rate = insts / (launch_ms * 1e-3)
+    return {"insts_per_launch": insts, "achieved": rate, "peak": VALU_PEAK, "unit": "wave-instr/s",
+            "frac": rate / VALU_PEAK}
+
+
 def push_traffic(wl_name):
     """HBM bytes per particle-kernel launch from the committed FETCH_SIZE /
     WRITE_SIZE counter runs (scaled by a plain copy of known size), or None
@@ -77,6 +88,21 @@ def push_traffic(wl_name):
     if kernel_source_hash() != rec.get("source_sha"):
         return None
     return float(rec["bytes_per_launch"])
+
+
+def push_valu(wl_name):
+    """VALU wavefront-instructions per particle-kernel launch, averaged over
+    every launch of a full benchmark run (SQ_INSTS_VALU counter run), or
+    None when the workload differs or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get("push_kernel", {})
+    if rec.get("workload") != {"lwfa": "lwfa2048x256"}.get(wl_name) or "valu_insts_per_launch" not in rec:
+        return None
+    if kernel_source_hash() != rec.get("source_sha"):
+        return None
+    return float(rec["valu_insts_per_launch"])
 
 
 def kernel_source_hash():
@@ -365,6 +391,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "push_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": push_traffic(args.workload),
                      "bytes_per_launch": alg_push},
+        # the particle kernel's VALU issue rate: the chip issues one
+        # wavefront VALU instruction per CU per clock when packed FP32 is
+        # not used (256 CUs x 2.4 GHz); counts from the committed counter run
+        "valu": valu_line(push_valu(args.workload), push_avg),
         "relayouts": d["n_relayout"],
         # total energy (fields + electrons) over the timed steps, and the
         # Gauss-law residual div_h E - rho against the initial state

@@ -447,6 +447,28 @@ def test_streaming_plasma_many_leavers(prec):
     assert max(errs.values()) < (1e-9 if prec == "fp64" else 1e-3), errs
 
 
+@pytest.mark.parametrize("prec,tol1", [("fp64", 1e-12), ("fp32s", 1e-5)])
+def test_odd_patch_edges(prec, tol1):
+    """Patches of 5 x 6 cells (the smallest edges for which at most two
+    patches per axis cover a node's current) in two regions: one step and
+    20 steps against the oracle."""
+    say(f"case: 5x6 patches {prec}")
+    wl = WL.thermal_2d(n=(40, 36), ppc=4, vth=0.05, patch=(5, 6), nreg=(2, 1), precision=prec)
+    g, F, P = oracle_state(wl)
+    O.step_sdsd(g, F, P)
+    Fg1, _, _ = gpu_run(wl, 1, track_ids=False)
+    e1 = max_family_error(Fg1, {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]})
+    for _ in range(19):
+        O.step_sdsd(g, F, P)
+    Fg, gp, diag = gpu_run(wl, 20)
+    e20 = max_family_error(Fg, {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]})
+    say(f"{prec}: 1-step {e1}; 20-step {e20}")
+    assert max(e1.values()) < tol1
+    assert max(e20.values()) < (1e-10 if prec == "fp64" else 1e-4)
+    assert np.array_equal(gp["id"], np.arange(wl.n_particles))
+    assert wrapped_diff(gp["x"], P.x, 40 * 0.1).max() < (1e-12 if prec == "fp64" else 1e-6)
+
+
 def test_empty_run_and_ragged_grid():
     say("case: empty + ragged")
     parts = {k: np.zeros(0) for k in ("x", "y", "z", "ux", "uy", "uz", "w")}

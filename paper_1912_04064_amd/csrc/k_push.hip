@@ -419,13 +419,15 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
     p.u[2] = un[2];
 
     // ---- destination patch and cell inside it
+    // (gcell is in [0, n): unsigned division, a shift for power-of-two patches)
     int dest = 0, mul = 1, packed = 0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        const int pa = gcell[a] / P[a];
-        dest += pa * mul;
+        const unsigned g = (unsigned)gcell[a], pe = (unsigned)P[a];
+        const unsigned pa = g / pe;
+        dest += (int)pa * mul;
         mul *= rd.np[a];
-        packed |= (gcell[a] - pa * P[a]) << (5 * a);
+        packed |= (int)(g - pa * pe) << (5 * a);
     }
     p.cell = packed;
     return dest;
@@ -512,14 +514,30 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
         return;
     }
 
-    // transfer (ii): region E^n, Bm^n -> LDS window
-    for (int idx = tid; idx < 6 * WS; idx += BLOCK) {
-        const int c = idx / WS, rem = idx - c * WS;
-        const int wx = rem % W0, tq = rem / W0, wy = tq % W1, wz = tq / W1;
-        const int comp = c < 3 ? f_E(par) + c : F_BM + (c - 3);
-        const SDMD_GLOBAL double *A = gp((const double *)rcomp(rd, region, comp));
-        s_win[c * WSs + wz * WPs + wy * W0 + wx] =
-            (R)A[rindex(rd, o[0] - 1 + wx, o[1] - 1 + wy, DIM == 3 ? o[2] - 1 + wz : 0)];
+    // transfer (ii): region E^n, Bm^n -> LDS window.  Each thread loads up
+    // to WB nodes before storing any, so the fill of a 16 x 16 (2D) or 8^3
+    // (3D) patch's window waits on memory once instead of once per node.
+    constexpr int WB = 9;
+    for (int i0 = 0; i0 < 6 * WS; i0 += WB * BLOCK) {
+        double wv[WB];
+        int wd[WB];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) {
+            const int idx = i0 + u * BLOCK + tid;
+            wd[u] = -1;
+            wv[u] = 0.0;
+            if (idx < 6 * WS) {
+                const int c = idx / WS, rem = idx - c * WS;
+                const int wx = rem % W0, tq = rem / W0, wy = tq % W1, wz = tq / W1;
+                const int comp = c < 3 ? f_E(par) + c : F_BM + (c - 3);
+                const SDMD_GLOBAL double *A = gp((const double *)rcomp(rd, region, comp));
+                wd[u] = c * WSs + wz * WPs + wy * W0 + wx;
+                wv[u] = A[rindex(rd, o[0] - 1 + wx, o[1] - 1 + wy, DIM == 3 ? o[2] - 1 + wz : 0)];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < WB; ++u)
+            if (wd[u] >= 0) s_win[wd[u]] = (R)wv[u];
     }
     for (int idx = tid; idx < 3 * TSs; idx += BLOCK) s_tile[idx] = 0.0;
     if (tid == 0) s_left = 0;

@@ -359,7 +359,21 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
         auto bin = [&](long long si) {
             return local_cell<DIM, T>(rd, rd.st, si, p) * Q + half_bits<DIM, T>(rd, rd.st, si);
         };
-        for (int i = tid; i < m; i += BLOCK) atomicAdd(&s_off[bin(src(kc + i * nch))], 1);
+        // Both passes over the chunk take MU particles per thread per round
+        // and issue all their loads before the first LDS update, so a round
+        // waits on memory once rather than once per particle.
+        constexpr int MU = 4;
+        for (int i0 = 0; i0 < m; i0 += MU * BLOCK) {
+            int bn[MU];
+#pragma unroll
+            for (int u = 0; u < MU; ++u) {
+                const int i = i0 + u * BLOCK + tid;
+                bn[u] = i < m ? bin(src(kc + i * nch)) : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < MU; ++u)
+                if (bn[u] >= 0) atomicAdd(&s_off[bn[u]], 1);
+        }
         __syncthreads();
         // exclusive scan of the bin counts: contiguous runs of whole cells
         // per thread
@@ -426,10 +440,25 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
             rb += tot;
         }
         __syncthreads();
-        for (int i = tid; i < m; i += BLOCK) {
-            const long long si = src(kc + i * nch);
-            const int j = atomicAdd(&s_off[bin(si)], 1);
-            copy_part<DIM, T>(rd.st, si, rd.lv, new_slot(rd, p, t, base + s_pos[j]));
+        for (int i0 = 0; i0 < m; i0 += MU * BLOCK) {
+            Part<T> pt[MU];
+            int bn[MU];
+#pragma unroll
+            for (int u = 0; u < MU; ++u) {
+                const int i = i0 + u * BLOCK + tid;
+                bn[u] = -1;
+                if (i < m) {
+                    const long long si = src(kc + i * nch);
+                    bn[u] = bin(si);
+                    load_part<DIM, T>(rd.st, si, pt[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < MU; ++u)
+                if (bn[u] >= 0) {
+                    const int j = atomicAdd(&s_off[bn[u]], 1);
+                    store_part<DIM, T>(rd.lv, new_slot(rd, p, t, base + s_pos[j]), pt[u], true);
+                }
         }
         return;
     }

@@ -546,6 +546,38 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
             const int cap = rd.sseg[t + 1] - rd.sseg[t];
             return slot < cap ? (long long)rd.sseg[t] + slot : -1ll - q;
         };
+        // The same with the slot claims of a wavefront aggregated: the lanes
+        // bound for one destination segment share one atomic (claims on one
+        // counter serialise), and the claims for all its destinations are in
+        // flight together.  Called by every lane of the wavefront.
+        auto insert_wave = [&](const int *srcpatch, long long i, bool valid) -> long long {
+            const int lane = tid & 63;
+            int q = 0, t = -1;
+            if (valid) {
+                q = srcpatch[i];
+                const int k0 = rd.pseg[q], nk = rd.pseg[q + 1] - k0;
+                t = k0 + (nk > 1 ? (int)(i % nk) : 0);
+            }
+            unsigned long long todo = __ballot(valid), mine = 0;
+            bool lead = false;
+            while (todo) {
+                const int l = __builtin_ctzll(todo);
+                const int tl = __shfl(t, l);
+                const unsigned long long same = __ballot(valid && t == tl);
+                if (valid && t == tl) {
+                    mine = same;
+                    lead = lane == l;
+                }
+                todo &= ~same;
+            }
+            int base = 0;
+            if (lead) base = atomicAdd(&rd.scnt[t], __popcll(mine));
+            base = __shfl(base, valid ? __builtin_ctzll(mine) : lane);
+            if (!valid) return 0;
+            const int slot = base + __popcll(mine & ((1ull << lane) - 1ull));
+            const int cap = rd.sseg[t + 1] - rd.sseg[t];
+            return slot < cap ? (long long)rd.sseg[t] + slot : -1ll - q;
+        };
         // parking (full destination segment) claims its slots once per wavefront
         auto place = [&](const Store &src, long long i, bool valid, long long dst) {
             const bool park = valid && dst < 0;
@@ -578,7 +610,7 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
                 for (int k0 = 0; k0 < nl; k0 += 64) {
                     const int k = k0 + lane;
                     const bool v = k < nl;
-                    place(rd.lv, b + k, v, v ? insert(rd.lpatch, b + k) : 0);
+                    place(rd.lv, b + k, v, insert_wave(rd.lpatch, b + k, v));
                 }
             }
         } else {

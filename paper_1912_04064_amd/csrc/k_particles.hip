@@ -462,12 +462,35 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
         }
         return;
     }
-    // parked particles follow the patch-store ones in their patch's list
+    // parked particles follow the patch-store ones in their patch's list;
+    // the lanes of a wavefront bound for one patch share one position claim
+    // (claims on one counter serialise, and parked particles crowd into the
+    // few patches that overflowed)
     const int nsp = min(rd.ctl->nspill, rd.n_total);
-    for (int i = (blockIdx.x - cb) * BLOCK + threadIdx.x; i < nsp; i += n_spill_blocks * BLOCK) {
-        const int q = rd.spatch[i];
-        const int pos = rd.preg[q] + atomicAdd(&rd.fill[q], 1);
-        copy_part<DIM, T>(rd.sp, i, rd.lv, new_slot(rd, q, rd.tot[q], pos));
+    const int lane = threadIdx.x & 63;
+    for (int i0 = (blockIdx.x - cb) * BLOCK; i0 < nsp; i0 += n_spill_blocks * BLOCK) {
+        const int i = i0 + (int)threadIdx.x;
+        const bool valid = i < nsp;
+        const int q = valid ? rd.spatch[i] : -1;
+        unsigned long long todo = __ballot(valid), mine = 0;
+        bool lead = false;
+        while (todo) {
+            const int l = __builtin_ctzll(todo);
+            const int ql = __shfl(q, l);
+            const unsigned long long same = __ballot(valid && q == ql);
+            if (valid && q == ql) {
+                mine = same;
+                lead = lane == l;
+            }
+            todo &= ~same;
+        }
+        int b = 0;
+        if (lead) b = atomicAdd(&rd.fill[q], __popcll(mine));
+        b = __shfl(b, valid ? __builtin_ctzll(mine) : lane);
+        if (valid) {
+            const int pos = rd.preg[q] + b + __popcll(mine & ((1ull << lane) - 1ull));
+            copy_part<DIM, T>(rd.sp, i, rd.lv, new_slot(rd, q, rd.tot[q], pos));
+        }
     }
 }
 

@@ -280,6 +280,7 @@ __device__ __forceinline__ long long new_slot(const RunDev &rd, int p, int t, in
 }
 
 constexpr int MAX_PATCH_CELLS = 1024;   // 32 x 32 (2D) / 8 x 8 x 8 (3D)
+constexpr int NEW_SEGS_LDS = 64;        // new segments of a patch whose first slots the move kernel keeps in LDS
 constexpr int MAX_SORT_BINS = 4096;     // cells x sub-cell halves (32 x 32 x 4, 8^3 x 8)
 
 template <int DIM, class T>
@@ -314,16 +315,20 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
         __shared__ int s_ws[2][BLOCK / 64];
         __shared__ int s_seg[MAX_OLD_SEGS + 1];
         __shared__ int s_p, s_cmax;
+        __shared__ int s_new[NEW_SEGS_LDS];
         const int b = blockIdx.x;
         if (b >= rd.cpre[np]) return;        // more chunk blocks than chunks
         const int tid = threadIdx.x;
-        if (tid == 0) {
-            int lo = 0, hi = np;             // the patch p with cpre[p] <= b < cpre[p + 1]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (rd.cpre[mid] <= b) lo = mid; else hi = mid;
-            }
-            s_p = lo;
+        // the patch p with cpre[p] <= b < cpre[p + 1]: cpre is nondecreasing
+        // and cpre[0] = 0, so p + 1 is the number of entries <= b, counted
+        // by all threads with their loads in flight together
+        if (tid == 0) s_p = -1;
+        __syncthreads();
+        {
+            int c = 0;
+#pragma unroll 8
+            for (int k = tid; k < np; k += BLOCK) c += rd.cpre[k] <= b ? 1 : 0;
+            if (c) atomicAdd(&s_p, c);
         }
         __syncthreads();
         const int p = s_p;
@@ -348,6 +353,25 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
         const int m = r / nch + (kc < r % nch ? 1 : 0);                  // particles of this chunk
         const int base = kc * (r / nch) + min(kc, r % nch);             // its first position
         const int t = rd.tot[p];
+        // the patch's new segments: their first slots in LDS when they are
+        // few (the usual case), so placing a particle needs no dependent load
+        const int kn0 = rd.pseg2[p], Kn = rd.pseg2[p + 1] - kn0;
+        const bool new_lds = Kn <= NEW_SEGS_LDS;
+        if (new_lds)
+            for (int k = tid; k < Kn; k += BLOCK) s_new[k] = rd.sseg2[kn0 + k];
+        const int nbase = Kn > 0 ? t / Kn : 0, nextra = Kn > 0 ? t % Kn : 0;
+        auto slot_of = [&](int j) -> long long {   // as new_slot(rd, p, t, j)
+            int k, o;
+            if (j < nextra * (nbase + 1)) {
+                k = j / (nbase + 1);
+                o = j - k * (nbase + 1);
+            } else {
+                const int jj = j - nextra * (nbase + 1);
+                k = nextra + (nbase > 0 ? jj / nbase : 0);
+                o = jj - (k - nextra) * nbase;
+            }
+            return (long long)(new_lds ? s_new[k] : rd.sseg2[kn0 + k]) + o;
+        };
         auto src = [&](int i) -> long long {   // i-th live particle of the patch
             int lo = 0, hi = K;                // s_seg[lo] <= i < s_seg[hi]
             while (hi - lo > 1) {
@@ -457,7 +481,7 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
             for (int u = 0; u < MU; ++u)
                 if (bn[u] >= 0) {
                     const int j = atomicAdd(&s_off[bn[u]], 1);
-                    store_part<DIM, T>(rd.lv, new_slot(rd, p, t, base + s_pos[j]), pt[u], true);
+                    store_part<DIM, T>(rd.lv, slot_of(base + s_pos[j]), pt[u], true);
                 }
         }
         return;

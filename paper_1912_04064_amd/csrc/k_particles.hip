@@ -147,7 +147,32 @@ __global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev 
     if (np <= PLAN_LDS_PATCHES) {
         for (int p = tid; p < np; p += PLAN_BLOCK) s_hist[p] = 0;
         __syncthreads();
-        for (int i = tid; i < nsp; i += PLAN_BLOCK) atomicAdd(&s_hist[rd.spatch[i]], 1);
+        // a wavefront whose parked particles all belong to one patch (the
+        // usual case at set-up, when every particle is parked in input
+        // order) adds once: 64 lanes on one LDS counter would serialise
+        // (eight rounds of loads in flight per thread)
+        const int lane = tid & 63;
+        constexpr int HU = 8;
+        for (int i0 = 0; i0 < nsp; i0 += HU * PLAN_BLOCK) {
+            int qv[HU];
+#pragma unroll
+            for (int u = 0; u < HU; ++u) {
+                const int i = i0 + u * PLAN_BLOCK + tid;
+                qv[u] = i < nsp ? gp(rd.spatch)[i] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < HU; ++u) {
+                const int q = qv[u];
+                const bool v = q >= 0;
+                const int q0 = __shfl(q, 0);
+                if (__all(!v || q == q0)) {
+                    const unsigned long long mv = __ballot(v);
+                    if (lane == 0 && mv) atomicAdd(&s_hist[q0], __popcll(mv));
+                } else if (v) {
+                    atomicAdd(&s_hist[q], 1);
+                }
+            }
+        }
         __syncthreads();
         for (int p = tid; p < np; p += PLAN_BLOCK) rd.tot[p] += s_hist[p];
     } else {

@@ -408,9 +408,9 @@ __global__ __launch_bounds__(BLOCK) void relayout_move_kernel(const RunDev *__re
         auto bin = [&](long long si) {
             return local_cell<DIM, T>(rd, rd.st, si, p) * Q + half_bits<DIM, T>(rd, rd.st, si);
         };
-        // Both passes over the chunk take MU particles per thread per round
-        // and issue all their loads before the first LDS update, so a round
-        // waits on memory once rather than once per particle.
+        // Both passes over the chunk take MU particles per thread per round,
+        // the round's loads written ahead of its LDS updates so that they
+        // can be in flight together.
         constexpr int MU = 4;
         for (int i0 = 0; i0 < m; i0 += MU * BLOCK) {
             int bn[MU];

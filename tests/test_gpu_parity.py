@@ -469,6 +469,34 @@ def test_odd_patch_edges(prec, tol1):
     assert wrapped_diff(gp["x"], P.x, 40 * 0.1).max() < (1e-12 if prec == "fp64" else 1e-6)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32s"])
+def test_very_dense_patch_many_segments(prec):
+    """One 8x8 patch holding 140,000 particles: 69 segments of 2048, more
+    than the re-layout keeps in LDS per patch (its fallback path), beside a
+    sparse background.  Three steps against the oracle."""
+    say(f"case: very dense patch {prec}")
+    rng = np.random.default_rng(5)
+    nd, nb = 140000, 32 * 32 * 2
+    x = np.concatenate([rng.uniform(8, 16, nd), rng.uniform(0, 32, nb)])
+    y = np.concatenate([rng.uniform(8, 16, nd), rng.uniform(0, 32, nb)])
+    N = nd + nb
+    parts = {"x": x, "y": y, "z": np.zeros(N), "ux": rng.normal(0, 0.05, N), "uy": rng.normal(0, 0.05, N),
+             "uz": rng.normal(0, 0.05, N), "w": np.full(N, 1e-3), "id": np.arange(N, dtype=np.uint32)}
+    wl = WL.Workload(name="dense1", dims=2, n=(32, 32), d=(1.0, 1.0), dt=0.6, patch=(8, 8), nreg=(1, 1), steps=0,
+                     precision=prec, parts=parts, q=-1e-3)
+    Fg, gp, diag = gpu_run(wl, 3)
+    Fo, P, g = oracle_run(wl, 3)
+    errs = max_family_error(Fg, Fo)
+    say(f"{prec}: patch max {diag['patch_max']} relayouts {diag['n_relayout']} errors {errs}")
+    assert diag["patch_max"] > 64 * 2048
+    assert diag["n_particles"] == N
+    assert np.array_equal(gp["id"], np.arange(N))
+    tol = 1e-11 if prec == "fp64" else 1e-5
+    assert wrapped_diff(gp["x"], P.x, 32.0).max() < tol
+    assert wrapped_diff(gp["y"], P.y, 32.0).max() < tol
+    assert max(errs.values()) < (1e-10 if prec == "fp64" else 1e-4), errs
+
+
 def test_empty_run_and_ragged_grid():
     say("case: empty + ragged")
     parts = {k: np.zeros(0) for k in ("x", "y", "z", "ux", "uy", "uz", "w")}

@@ -160,6 +160,74 @@ def test_boris_exb_drift():
     assert abs(mean_v[1]) < 1e-4
 
 
+def _rodrigues(u, k, theta):
+    """u rotated by theta about the unit vector k (right-hand rule)."""
+    return u * math.cos(theta) + np.cross(k, u) * math.sin(theta) + k * (k @ u) * (1.0 - math.cos(theta))
+
+
+@pytest.mark.parametrize("qm", [-1.0, 1.0, -3.0])
+def test_boris_oblique_b_is_a_rotation_about_b(qm):
+    """E = 0, B along a random oblique direction: one Boris step is the exact
+    rotation of u about B by theta = 2 atan(|q/m| |B| dt / (2 gamma)), in the
+    sense of d u/dt = (q/m) u x B / gamma (about +B for q < 0, about -B for
+    q > 0).  Every component of t enters, so a wrong sign or index in any of
+    the cross-product terms moves the result off the rotation."""
+    rng = np.random.default_rng(11)
+    dt = 0.17
+    for _ in range(25):
+        B = rng.normal(size=3) * rng.uniform(0.2, 3.0)
+        Bn = math.sqrt(B @ B)
+        b = B / Bn
+        u = rng.normal(size=3) * rng.uniform(0.05, 2.0)
+        g = math.sqrt(1 + u @ u)
+        theta = 2.0 * math.atan(abs(qm) * Bn * dt / (2.0 * g))
+        k = b if qm < 0 else -b
+        expect = _rodrigues(u, k, theta)
+        got = O.boris(qm, dt, np.r_[0.0, 0.0, 0.0, B], u)
+        np.testing.assert_allclose(got, expect, rtol=0, atol=2e-15 * max(1.0, math.sqrt(u @ u)))
+        # invariants: |u| and u . b
+        assert math.sqrt(got @ got) == pytest.approx(math.sqrt(u @ u), rel=1e-14)
+        assert got @ b == pytest.approx(u @ b, rel=1e-13, abs=1e-15)
+
+
+def test_boris_parallel_momentum_grows_linearly_with_oblique_fields():
+    """E with a component along an oblique B: the rotation leaves u . b
+    unchanged and each half kick adds (q/m) (dt/2) E . b, so after n steps
+    u . b = u0 . b + n (q/m) dt E . b (round-off only)."""
+    qm, dt = -1.0, 0.09
+    B = np.array([0.6, -0.8, 1.1])
+    b = B / math.sqrt(B @ B)
+    E = np.array([0.02, 0.05, -0.03])
+    u0 = np.array([0.1, 0.2, -0.05])
+    u = u0.copy()
+    for n in range(1, 201):
+        u = O.boris(qm, dt, np.r_[E, B], u)
+        if n % 50 == 0:
+            assert u @ b == pytest.approx(u0 @ b + n * qm * dt * (E @ b), rel=1e-12)
+
+
+def test_boris_exb_drift_oblique():
+    """E perpendicular to an oblique B, |E| << |B|: the guiding centre drifts
+    at E x B / B^2 in all three components and not at all along B."""
+    qm, dt = -1.0, 0.05
+    B = np.array([0.3, -0.5, 0.8])
+    B = B / math.sqrt(B @ B)
+    e = np.cross(B, np.array([1.0, 0.0, 0.0]))
+    E = 0.01 * e / math.sqrt(e @ e)
+    u = np.zeros(3)
+    x = np.zeros(3)
+    steps = int(round(40 * 2 * math.pi / dt))
+    for k in range(steps):
+        u = O.boris(qm, dt, np.r_[E, B], u)
+        x = x + dt * u / math.sqrt(1 + u @ u)
+        if k == 0:
+            x_first = x.copy()
+    vd = np.cross(E, B) / (B @ B)
+    mean_v = (x - x_first) / ((steps - 1) * dt)
+    np.testing.assert_allclose(mean_v, vd, rtol=0, atol=2e-3 * math.sqrt(vd @ vd))
+    assert abs(mean_v @ B) < 1e-6
+
+
 # --------------------------------------------------------------------------
 # Esirkepov deposition
 # --------------------------------------------------------------------------

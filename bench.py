@@ -194,8 +194,9 @@ def bench_serve(args):
     pre = {r.rid: WL.request_workload(r) for r in reqs}
     print(f"[bench] serve: {len(reqs)} requests at {args.serve}/s over {args.window} s "
           f"(inputs made in {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
-    be = S.GpuBackend(max_runs=args.slots, hbm_budget=0)
-    srv = S.Server(be, hbm_budget=int(args.budget_gb * 2 ** 30), max_runs=args.slots, steps_per_call=20)
+    budget = int(args.budget_gb * 2 ** 30)
+    be = S.GpuBackend(max_runs=args.slots, hbm_budget=budget)
+    srv = S.Server(be, hbm_budget=budget, max_runs=args.slots, steps_per_call=20)
     recs = srv.serve(reqs, lambda r: pre[r.rid])
     admit_ms = be.admit_s * 1e3 / max(be.admits, 1)
     be.close()

@@ -59,6 +59,10 @@ extern "C" {
 #define PIC_E_NUMERIC  -5  /* non-finite value or a move of >= 1 cell a step */
 #define PIC_E_CAPACITY -6  /* no free run slot                               */
 #define PIC_E_STATE    -7  /* call not valid in the current state            */
+#define PIC_E_OVERFLOW -8  /* a particle store of the run overflowed (more
+                              particles reached it than it holds); the run's
+                              state is no longer valid and it should be
+                              retired                                        */
 
 /* ---- enums -------------------------------------------------------------- */
 #define PIC_FP64        0  /* everything in FP64                             */
@@ -209,6 +213,17 @@ typedef struct {
                                          path (with the current filter the
                                          conserved form involves the filtered
                                          rho, and this figure drifts)       */
+    int32_t kernel_path[4];           /* compiled paths the run's steps take:
+                                         particle kernel patch edge (0 = the
+                                         generic path reading the patch shape
+                                         at run time), its LDS sizing class
+                                         (8, 16, 32), field kernel tile width
+                                         along x, 1 if deterministic       */
+    int64_t device_bytes;             /* device bytes the context holds now
+                                         (all runs and context buffers)    */
+    int64_t device_bytes_peak;        /* the most it has held since pic_init;
+                                         never above pic_runtime.hbm_budget
+                                         when a budget is set              */
 } pic_diag_t;
 
 /* Particle export (host memory, caller owned).  capacity is the length of

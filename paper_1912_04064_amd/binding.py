@@ -26,6 +26,7 @@ PIC_E_DEVICE = -4
 PIC_E_NUMERIC = -5
 PIC_E_CAPACITY = -6
 PIC_E_STATE = -7
+PIC_E_OVERFLOW = -8
 PIC_FP64 = 0
 PIC_FP32_SPLIT = 1
 PIC_RT_NO_GRAPH = 1
@@ -79,7 +80,8 @@ class PicDiag(C.Structure):
     _fields_ = [("step", C.c_int64), ("t", C.c_double), ("n_particles", C.c_int64), ("patch_min", C.c_int64),
                 ("patch_max", C.c_int64), ("patch_mean", C.c_double), ("U_E", C.c_double), ("U_B", C.c_double),
                 ("K", C.c_double), ("t_ms", C.c_double * 4), ("n_relayout", C.c_int64), ("n_spill", C.c_int64),
-                ("err_flags", C.c_int32), ("patch", C.c_int32 * 3), ("gauss_residual", C.c_double)]
+                ("err_flags", C.c_int32), ("patch", C.c_int32 * 3), ("gauss_residual", C.c_double),
+                ("kernel_path", C.c_int32 * 4), ("device_bytes", C.c_int64), ("device_bytes_peak", C.c_int64)]
 
 
 class PicParticlesOut(C.Structure):
@@ -287,9 +289,10 @@ class Context:
         rc = self.L.pic_diag(self.ctx, run, C.byref(d))
         if check:
             _check(self.L, self.ctx, rc, "pic_diag")
-        out = {k: getattr(d, k) for k, _ in PicDiag._fields_ if k not in ("t_ms", "patch")}
+        out = {k: getattr(d, k) for k, _ in PicDiag._fields_ if k not in ("t_ms", "patch", "kernel_path")}
         out["t_ms"] = list(d.t_ms)
         out["patch"] = list(d.patch)
+        out["kernel_path"] = list(d.kernel_path)
         out["rc"] = rc
         return out
 

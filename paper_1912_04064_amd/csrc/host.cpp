@@ -100,7 +100,8 @@ struct pic_ctx {
     hipGraphExec_t g2 = nullptr;      // two steps
     hipGraphExec_t grel = nullptr;    // re-layout check
     bool graphs_valid = false;
-    size_t bytes = 0;
+    size_t bytes = 0;        // device bytes held now
+    size_t peak_bytes = 0;   // the most held since pic_init
     std::string err;
     double t_ms[4] = {0, 0, 0, 0};
 };
@@ -127,17 +128,26 @@ static int set_err(pic_ctx *c, int code, const char *fmt, ...)
     } while (0)
 
 // ------------------------------------------------------------------ memory
+// Every device allocation of a context goes through dev_alloc, rounded to
+// 256 bytes.  With an HBM budget set, an allocation that would take the
+// context's total above it fails (the caller reports PIC_E_NOMEM), so the
+// context never holds more than its budget.
+static size_t alloc_size(size_t bytes) { return bytes == 0 ? 256 : ((bytes + 255) & ~(size_t)255); }
+
 static void *dev_alloc(pic_ctx *c, size_t bytes)
 {
-    if (bytes == 0) bytes = 256;
-    bytes = (bytes + 255) & ~(size_t)255;
+    bytes = alloc_size(bytes);
+    if (c->rt.hbm_budget && c->bytes + bytes > c->rt.hbm_budget) return nullptr;
     void *p = nullptr;
     if (c->rt.alloc) {
         p = c->rt.alloc(bytes, c->rt.stream, c->rt.user);
     } else if (hipMalloc(&p, bytes) != hipSuccess) {
         p = nullptr;
     }
-    if (p) c->bytes += bytes;
+    if (p) {
+        c->bytes += bytes;
+        c->peak_bytes = std::max(c->peak_bytes, c->bytes);
+    }
     return p;
 }
 
@@ -155,11 +165,31 @@ static void dev_free(pic_ctx *c, DevBuf &b)
 
 static void *run_alloc(pic_ctx *c, Run &r, size_t bytes)
 {
-    size_t b = bytes == 0 ? 256 : ((bytes + 255) & ~(size_t)255);
+    const size_t b = alloc_size(bytes);
     void *p = dev_alloc(c, b);
     if (p) r.bufs.push_back({p, b});
     return p;
 }
+
+// Short-lived device buffers of one call (staging, partial sums), released
+// when the call returns, on every path.
+struct Scratch {
+    pic_ctx *c;
+    std::vector<DevBuf> bufs;
+    explicit Scratch(pic_ctx *ctx) : c(ctx) {}
+    Scratch(const Scratch &) = delete;
+    Scratch &operator=(const Scratch &) = delete;
+    void *get(size_t bytes)
+    {
+        void *p = dev_alloc(c, bytes);
+        if (p) bufs.push_back({p, alloc_size(bytes)});
+        return p;
+    }
+    ~Scratch()
+    {
+        for (auto &b : bufs) dev_free(c, b);
+    }
+};
 
 // ------------------------------------------------------------------ layout
 struct Layout {
@@ -170,7 +200,9 @@ struct Layout {
     int seg_cap, seg_max;
     long long rsize;
     long long n_total, cap_total;
-    size_t bytes;
+    size_t resident;   // device bytes the run holds between calls
+    size_t bytes;      // resident + the most any call takes on top (set-up
+                       // staging, read-out scratch, the run's item lists)
 };
 
 static int patch_class(int dims, const int P[3])
@@ -308,7 +340,27 @@ static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::st
     if (cfg->field_solver == PIC_SOLVER_PSATD) b += align256((size_t)9 * ncell * 16);
     b += align256((size_t)ncell * 8);   // initial Gauss residual
     b += 64 * 256;   // per-array rounding and the control block
-    L.bytes = b;
+    L.resident = b;
+    // transient device memory, the largest of: the set-up staging (fields,
+    // then FP64 particles and ids, then the charge density of the initial
+    // Gauss residual, one after the other), and the read-out scratch of
+    // pic_fields, pic_diag (partial sums, residual, charge density) and
+    // pic_particles (FP64 arrays, ids, patches, segment offsets)
+    const size_t nt = (size_t)std::max<long long>(L.n_total, 1);
+    const size_t nb = (size_t)std::max<long long>(1, std::min<long long>(1024, (ncell + BLOCK - 1) / BLOCK));
+    const size_t cell8 = align256((size_t)ncell * 8);
+    size_t tr = std::max({align256((size_t)3 * ncell * 8), 7 * align256(nt * 8) + align256(nt * 4), cell8});
+    tr = std::max(tr, align256(std::max(2 * nb, (size_t)L.seg_max + 1) * 8) + align256((size_t)ncell * 8 + 2 * nb * 8) +
+                          cell8);
+    tr = std::max(tr, 7 * align256(nt * 8) + 2 * align256(nt * 4) + align256(((size_t)L.seg_max + 1) * 4));
+    // item lists of the run's launches (kept at up to twice their size):
+    // particle items per segment slot; field items per region tile (a tile
+    // covers at least 64 nodes, or a whole smaller region); post items per
+    // 256 ghost nodes (fewer than 2 per node) and per segment
+    const size_t yee_items = (size_t)ncell / 64 + (size_t)L.n_regions;
+    const size_t post_items = (size_t)ncell / 128 + (size_t)L.n_regions + (size_t)L.seg_max + 64;
+    const size_t items = 2 * ((size_t)(L.seg_max + 8) * 8 + (yee_items + post_items) * 16);
+    L.bytes = b + tr + align256(items) + 4096;
     return PIC_OK;
 }
 
@@ -378,7 +430,7 @@ static int check_run_err(pic_ctx *c, int slot, int *flags_out = nullptr)
     if (ctl.err & ERR_RANGE) return set_err(c, PIC_E_CONFIG, "run %d: particle position outside [0, L)", slot);
     if (ctl.err & ERR_NONFINITE) return set_err(c, PIC_E_NUMERIC, "run %d: non-finite particle value", slot);
     if (ctl.err & ERR_MOVE) return set_err(c, PIC_E_NUMERIC, "run %d: a particle moved a cell or more in one step", slot);
-    if (ctl.err & ERR_CAPACITY) return set_err(c, PIC_E_NUMERIC, "run %d: particle store capacity exceeded", slot);
+    if (ctl.err & ERR_CAPACITY) return set_err(c, PIC_E_OVERFLOW, "run %d: particle store capacity exceeded", slot);
     return PIC_OK;
 }
 
@@ -478,9 +530,12 @@ static void autotune_patch(pic_ctx *c, const pic_config *cfg, int P[3])
             pic_runtime trt = c->rt;
             trt.flags |= PIC_RT_NO_GRAPH;
             trt.max_runs = 1;
-            trt.hbm_budget = 0;
+            // the scratch context lives beside this one: it may use what
+            // this context's budget leaves, and its peak counts here
+            trt.hbm_budget = c->rt.hbm_budget ? (c->rt.hbm_budget > c->bytes ? c->rt.hbm_budget - c->bytes : 1) : 0;
             pic_ctx *t = nullptr;
             if (pic_init(&tc, 1, &trt, &t) != PIC_OK) continue;
+            c->peak_bytes = std::max(c->peak_bytes, c->bytes + t->peak_bytes);
             hipEvent_t e0, e1;
             float ms = 1e30f;
             if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
@@ -492,6 +547,7 @@ static void autotune_patch(pic_ctx *c, const pic_config *cfg, int P[3])
                 hipEventDestroy(e0);
                 hipEventDestroy(e1);
             }
+            c->peak_bytes = std::max(c->peak_bytes, c->bytes + t->peak_bytes);
             pic_free(t);
             if (ms < best_ms) {
                 best_ms = ms;
@@ -639,9 +695,9 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     if (cfg->fields) {
         const pic_fields_in *f = cfg->fields;
         if (!f->E || !f->B || (f->kind != 0 && f->kind != 1)) return set_err(c, PIC_E_INVAL, "fields: E and B required, kind 0 or 1");
-        double *stg = (double *)dev_alloc(c, (size_t)3 * ncell * 8);
+        Scratch tmp(c);
+        double *stg = (double *)tmp.get((size_t)3 * ncell * 8);
         if (!stg) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
-        DevBuf sb{stg, align256((size_t)3 * ncell * 8)};
         auto up = [&](const double *src, int c0) -> int {
             HIPCHK(c, hipMemcpyAsync(stg, src, (size_t)3 * ncell * 8, hipMemcpyHostToDevice, s));
             HIPCHK(c, launch_scatter_fields(c->d_runs, slot, ncell, stg, c0, s));
@@ -660,7 +716,6 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
                 if ((rc = up(f->Bm ? f->Bm : f->B, F_BM))) return rc;
             }
         }
-        dev_free(c, sb);
         HIPCHK(c, launch_ghosts(c->d_runs, slot, r.total_ghosts, f_E(par), 3, s));
         HIPCHK(c, launch_ghosts(c->d_runs, slot, r.total_ghosts, f_B(par), 3, s));
         if (f->kind == 0 && r.rd.solver != PIC_SOLVER_PSATD) HIPCHK(c, launch_half_faraday(c->d_runs, slot, ncell, par, s));
@@ -675,26 +730,23 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
         if (!p->x || !p->y || (L.dims == 3 && !p->z) || !p->ux || !p->uy || !p->uz || !p->w)
             return set_err(c, PIC_E_INVAL, "particles: x, y, (z), ux, uy, uz, w required");
         const int nar = 7;
-        std::vector<DevBuf> st(nar + 1);
+        Scratch tmp(c);
         const double *src[7] = {p->x, p->y, L.dims == 3 ? p->z : p->x, p->ux, p->uy, p->uz, p->w};
         double *dp[7];
         for (int i = 0; i < nar; ++i) {
-            dp[i] = (double *)dev_alloc(c, (size_t)n * 8);
+            dp[i] = (double *)tmp.get((size_t)n * 8);
             if (!dp[i]) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
-            st[i] = {dp[i], align256((size_t)n * 8)};
             HIPCHK(c, hipMemcpyAsync(dp[i], src[i], (size_t)n * 8, hipMemcpyHostToDevice, s));
         }
         uint32_t *did = nullptr;
         if (p->id) {
-            did = (uint32_t *)dev_alloc(c, (size_t)n * 4);
+            did = (uint32_t *)tmp.get((size_t)n * 4);
             if (!did) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
-            st[nar] = {did, align256((size_t)n * 4)};
             HIPCHK(c, hipMemcpyAsync(did, p->id, (size_t)n * 4, hipMemcpyHostToDevice, s));
         }
         HIPCHK(c, launch_convert(L.dims, L.split, c->d_runs, slot, (int)n, dp[0], dp[1], dp[2], dp[3], dp[4], dp[5],
                                  dp[6], did, s));
         HIPCHK(c, hipStreamSynchronize(s));
-        for (auto &b : st) dev_free(c, b);
     }
     // binning: the first re-layout gathers the particles into their patch
     // segments, the second spreads each segment's storage order (see the
@@ -714,7 +766,9 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
 template <class V>
 static int upload_vec(pic_ctx *c, const std::vector<V> &h, V *&d, size_t &cap)
 {
-    if (h.size() > cap || !d) {
+    // grow to twice the size; shrink when a quarter is left in use, so the
+    // lists of retired runs do not stay allocated
+    if (h.size() > cap || !d || (cap > 64 && h.size() * 4 < cap)) {
         for (auto it = c->own.begin(); it != c->own.end(); ++it)
             if (it->p == d) {
                 dev_free(c, *it);
@@ -897,16 +951,15 @@ static int run_par(const Run &r) { return r.par0 ^ (int)(r.steps & 1); }
 static int gauss_field(pic_ctx *c, int slot, double *g)
 {
     Run &r = c->runs[slot];
-    double *rho = (double *)dev_alloc(c, (size_t)r.ncell * 8);
+    Scratch tmp(c);
+    double *rho = (double *)tmp.get((size_t)r.ncell * 8);
     if (!rho) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
-    DevBuf rb{rho, align256((size_t)r.ncell * 8)};
     hipError_t e;
     Ctl ctl = read_ctl(c, slot, e);
     if (e == hipSuccess)
         e = launch_rho(r.dims, r.split, c->d_runs, slot, r.rd.seg_max, ctl.nspill, r.ncell, rho, c->stream);
     if (e == hipSuccess) e = launch_gauss(c->d_runs, slot, r.ncell, run_par(r), rho, g, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    dev_free(c, rb);
     if (e != hipSuccess) return set_err(c, PIC_E_DEVICE, "Gauss residual: %s", hipGetErrorString(e));
     return PIC_OK;
 }
@@ -937,6 +990,7 @@ const char *pic_strerror(int code)
     case PIC_E_NUMERIC: return "numerical error (non-finite value or a move of a cell or more in one step)";
     case PIC_E_CAPACITY: return "no free run slot";
     case PIC_E_STATE: return "call not valid in the current state";
+    case PIC_E_OVERFLOW: return "a particle store of the run overflowed";
     default: return "unknown error";
     }
 }
@@ -972,7 +1026,7 @@ int pic_mem_bytes(const pic_config *cfg, size_t *bytes)
 void pic_free(pic_ctx *ctx)
 {
     if (!ctx) return;
-    if (ctx->stream || true) hipStreamSynchronize(ctx->stream);
+    hipStreamSynchronize(ctx->stream);
     drop_graphs(ctx);
     for (auto &r : ctx->runs) free_run(ctx, r);
     for (auto &b : ctx->own) dev_free(ctx, b);
@@ -1150,9 +1204,9 @@ int pic_fields(pic_ctx *c, int32_t run, uint32_t mask, double *dst, size_t dst_l
         if (mask & (1u << b)) ++ncomp;
     if ((size_t)ncomp * nc > dst_len) return set_err(c, PIC_E_INVAL, "dst too small: need %zu", (size_t)ncomp * nc);
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double *tmp = (double *)dev_alloc(c, nc * 8);
+    Scratch scr(c);
+    double *tmp = (double *)scr.get(nc * 8);
     if (!tmp) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
-    DevBuf tb{tmp, align256(nc * 8)};
     size_t o = 0;
     int rc = PIC_OK;
     for (int b = 0; b < 13 && rc == PIC_OK; ++b) {
@@ -1172,7 +1226,6 @@ int pic_fields(pic_ctx *c, int32_t run, uint32_t mask, double *dst, size_t dst_l
         if (e != hipSuccess) rc = set_err(c, PIC_E_DEVICE, "field readout: %s", hipGetErrorString(e));
         o += nc;
     }
-    dev_free(c, tb);
     if (rc) return rc;
     return check_run_err(c, run);
 }
@@ -1215,9 +1268,9 @@ int pic_diag(pic_ctx *c, int32_t run, pic_diag_t *out)
     const double dV = d.d[0] * d.d[1] * (d.dims == 3 ? d.d[2] : 1.0);
     const int nb = std::max(1, std::min(1024, (r.ncell + BLOCK - 1) / BLOCK));
     const int nk = d.seg_max + 1;
-    double *part = (double *)dev_alloc(c, (size_t)std::max(2 * nb, nk) * 8);
+    Scratch scr(c);
+    double *part = (double *)scr.get((size_t)std::max(2 * nb, nk) * 8);
     if (!part) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
-    DevBuf pb{part, align256((size_t)std::max(2 * nb, nk) * 8)};
     std::vector<double> h(std::max(2 * nb, nk));
     HIPCHK(c, launch_field_energy(c->d_runs, run, r.ncell, run_par(r), part, nb, c->stream));
     HIPCHK(c, hipMemcpyAsync(h.data(), part, 2 * nb * 8, hipMemcpyDeviceToHost, c->stream));
@@ -1232,22 +1285,15 @@ int pic_diag(pic_ctx *c, int32_t run, pic_diag_t *out)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double k = 0;
     for (int i = 0; i < nk; ++i) k += h[i];
-    dev_free(c, pb);
     out->U_E = 0.5 * ue * dV;
     out->U_B = 0.5 * ub * dV;
     out->K = k * dV;
     for (int i = 0; i < 4; ++i) out->t_ms[i] = c->t_ms[i];
     {
         // Gauss-law residual against the initial state
-        double *gb = (double *)dev_alloc(c, (size_t)r.ncell * 8 + (size_t)2 * nb * 8);
-        if (!gb) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
-        DevBuf gbb{gb, align256((size_t)r.ncell * 8 + (size_t)2 * nb * 8)};
-        double *rho = (double *)dev_alloc(c, (size_t)r.ncell * 8);
-        if (!rho) {
-            dev_free(c, gbb);
-            return set_err(c, PIC_E_NOMEM, "staging allocation failed");
-        }
-        DevBuf rbb{rho, align256((size_t)r.ncell * 8)};
+        double *gb = (double *)scr.get((size_t)r.ncell * 8 + (size_t)2 * nb * 8);
+        double *rho = gb ? (double *)scr.get((size_t)r.ncell * 8) : nullptr;
+        if (!gb || !rho) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
         hipError_t e = launch_rho(r.dims, r.split, c->d_runs, run, d.seg_max, ctl.nspill, r.ncell, rho, c->stream);
         if (e == hipSuccess) e = launch_gauss(c->d_runs, run, r.ncell, run_par(r), rho, gb, c->stream);
         if (e == hipSuccess) e = launch_gauss_max(r.ncell, gb, r.gauss0, rho, gb + r.ncell, nb, c->stream);
@@ -1255,8 +1301,6 @@ int pic_diag(pic_ctx *c, int32_t run, pic_diag_t *out)
         if (e == hipSuccess)
             e = hipMemcpyAsync(hm.data(), gb + r.ncell, (size_t)2 * nb * 8, hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        dev_free(c, rbb);
-        dev_free(c, gbb);
         if (e != hipSuccess) return set_err(c, PIC_E_DEVICE, "Gauss residual: %s", hipGetErrorString(e));
         double dg = 0.0, rm = 0.0;
         for (int i = 0; i < nb; ++i) {
@@ -1269,6 +1313,12 @@ int pic_diag(pic_ctx *c, int32_t run, pic_diag_t *out)
     out->n_spill = ctl.nspill;
     out->err_flags = ctl.err;
     for (int a = 0; a < 3; ++a) out->patch[a] = d.P[a];
+    out->kernel_path[0] = r.px;
+    out->kernel_path[1] = r.pc;
+    out->kernel_path[2] = yee_tile_x(r.dims, d.rs[0], d.filter > 0);
+    out->kernel_path[3] = 0;
+    out->device_bytes = (int64_t)c->bytes;
+    out->device_bytes_peak = (int64_t)c->peak_bytes;
     return check_run_err(c, run);
 }
 
@@ -1297,17 +1347,13 @@ int pic_particles(pic_ctx *c, int32_t run, pic_particles_out *out)
     if (out->capacity < n) return set_err(c, PIC_E_INVAL, "capacity %lld < %lld particles", (long long)out->capacity, n);
     if (n == 0) return check_run_err(c, run);
     const size_t nn = (size_t)n;
-    std::vector<DevBuf> tmp;
-    auto mk = [&](size_t bytes) -> void * {
-        void *p = dev_alloc(c, bytes);
-        if (p) tmp.push_back({p, align256(bytes)});
-        return p;
-    };
+    Scratch scr(c);
+    auto mk = [&](size_t bytes) -> void * { return scr.get(bytes); };
     double *dx[7] = {nullptr};
     double *hx[7] = {out->x, out->y, out->z, out->ux, out->uy, out->uz, out->w};
     bool ok = true;
     for (int i = 0; i < 7; ++i)
-        if (hx[i] && (i != 2 || d.dims == 3 || true)) {
+        if (hx[i]) {
             dx[i] = (double *)mk(nn * 8);
             ok = ok && dx[i];
         }
@@ -1328,7 +1374,6 @@ int pic_particles(pic_ctx *c, int32_t run, pic_particles_out *out)
     if (!rc && e == hipSuccess && dpat) e = hipMemcpyAsync(out->patch, dpat, nn * 4, hipMemcpyDeviceToHost, c->stream);
     if (!rc && e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (!rc && e != hipSuccess) rc = set_err(c, PIC_E_DEVICE, "particle export: %s", hipGetErrorString(e));
-    for (auto &b : tmp) dev_free(c, b);
     if (rc) return rc;
     return check_run_err(c, run);
 }

@@ -48,10 +48,13 @@ class GpuBackend:
     def __init__(self, max_runs: int, hbm_budget: int, track_ids: bool = False):
         from . import binding
         self.B = binding
+        # the library holds the context to hbm_budget device bytes in total
+        # (runs, their set-up and read-out scratch, the context's own tables)
         self.ctx = binding.Context([], max_runs=max_runs, hbm_budget=hbm_budget, track_ids=track_ids)
         self.start = time.perf_counter()
         self.admit_s = 0.0      # host time spent admitting runs (upload, binning, patch choice)
         self.admits = 0
+        self.peak_bytes = 0     # the library's high-water mark of device bytes
 
     def clock(self) -> float:
         return time.perf_counter() - self.start
@@ -64,9 +67,17 @@ class GpuBackend:
     def mem_bytes(self, wl) -> int:
         return self.B.mem_bytes(wl)
 
-    def admit(self, wl, steps: int) -> int:
+    def admit(self, wl, steps: int) -> Optional[int]:
+        """The new run's id, or None when the library refuses it for memory
+        (the context's own tables take a little beyond the runs' footprints):
+        the request then waits for a run to finish."""
         t0 = time.perf_counter()
-        run = self.ctx.admit(wl, max_steps=steps)
+        try:
+            run = self.ctx.admit(wl, max_steps=steps)
+        except self.B.PicError as e:
+            if e.code != self.B.PIC_E_NOMEM:
+                raise
+            return None
         self.admit_s += time.perf_counter() - t0
         self.admits += 1
         return run
@@ -79,6 +90,7 @@ class GpuBackend:
 
     def finish(self, run: int) -> dict:
         d = self.ctx.diag(run)              # synchronises
+        self.peak_bytes = max(self.peak_bytes, d["device_bytes_peak"])
         return {"n_particles": d["n_particles"], "U_E": d["U_E"], "U_B": d["U_B"], "K": d["K"],
                 "step": d["step"]}
 
@@ -174,8 +186,12 @@ class Server:
                     raise ValueError(f"request {req.rid} needs {need} bytes, more than the whole budget")
                 if self.used + need > self.budget:
                     break
-                pending.pop(0)
                 run = self.be.admit(wl, req.steps)
+                if run is None:
+                    if not active:
+                        raise ValueError(f"request {req.rid} does not fit in the budget even alone")
+                    break
+                pending.pop(0)
                 rec = records[req.rid]
                 rec.admitted = self.be.clock()
                 rec.particles = wl.n_particles

@@ -28,8 +28,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_strerror_texts():
     L = B.load()
-    for code in (0, -1, -2, -3, -4, -5, -6, -7):
-        assert L.pic_strerror(code)
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
+        assert L.pic_strerror(code) and L.pic_strerror(code) != b"unknown error"
+    assert B.PIC_E_OVERFLOW == -8
     assert L.pic_strerror(-99) == b"unknown error"
 
 
@@ -83,3 +84,26 @@ def test_init_without_gpu_reports_device_error():
     ctx = C.c_void_p()
     rc = L.pic_init(None, 0, None, C.byref(ctx))
     assert rc == B.PIC_E_DEVICE
+
+
+def _instantiations(src, macro):
+    txt = open(os.path.join(ROOT, "paper_1912_04064_amd", "csrc", src)).read()
+    out = set()
+    for args in re.findall(macro + r"\(([^)]*)\)", txt):
+        a = [x.strip() for x in args.split(",")]
+        if not a[0].isdigit():
+            continue        # the macro's own definition
+        out.add(tuple(int(x) if x.lstrip("-").isdigit() else {"true": True, "false": False}.get(x, x) for x in a))
+    return out
+
+
+def test_paths_table_names_every_kernel_instantiation():
+    """The oracle-compared path cases (tests/test_gpu_paths.py) cover every
+    particle-kernel and field-kernel instantiation compiled into the
+    library, and name none that is not compiled."""
+    from tests import test_gpu_paths as T
+    push = _instantiations("k_push.hip", "PUSH_CASE")
+    yee = _instantiations("k_fields.hip", "YEE_CASE")
+    assert len(push) >= 15 and len(yee) >= 24
+    assert T.push_instantiations() == push
+    assert T.yee_instantiations() == yee

@@ -106,20 +106,18 @@ def test_budget_admission_and_serving_loop():
     reqs = reqs[:12]
     mk = lambda r: WL.request_workload(r, patch=(16, 16))
     need = max(B.mem_bytes(mk(r)) for r in reqs)
-    be = S.GpuBackend(max_runs=4, hbm_budget=0)
-    srv = S.Server(be, hbm_budget=3 * need, max_runs=4, steps_per_call=10)
+    budget = 3 * need
+    be = S.GpuBackend(max_runs=4, hbm_budget=budget)
+    srv = S.Server(be, hbm_budget=budget, max_runs=4, steps_per_call=10)
     recs = srv.serve(reqs, mk)
     be.close()
     summ = S.summarize(recs)
-    say("serving summary", summ)
+    say("serving summary", summ, "library peak device bytes", be.peak_bytes, "budget", budget)
     assert len(recs) == len(reqs) and srv.max_active <= 4
-    # device bytes of the runs live at any time never exceed the budget
-    events = sorted([(r.admitted, r.bytes) for r in recs] + [(r.finished, -r.bytes) for r in recs],
-                    key=lambda e: (e[0], e[1]))
-    live = peak = 0
-    for _, b in events:
-        live += b
-        peak = max(peak, live)
-    assert peak <= 3 * need
+    # the library's own count of every device byte it held (runs, set-up
+    # staging, read-out scratch, patch autotuning, context tables) never
+    # went above the budget, and at least two runs shared the GPU at once
+    assert 0 < be.peak_bytes <= budget
+    assert srv.max_active >= 2
     for r, q in zip(recs, reqs):
         assert r.result["step"] == q.steps and r.result["n_particles"] == mk(q).n_particles

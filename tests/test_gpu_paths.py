@@ -1,0 +1,147 @@
+"""Every compiled kernel path against the FP64 oracle.
+
+The particle kernel is instantiated per (dimensions, precision, exact patch
+edge or generic, LDS sizing class) and the field kernel per (dimensions,
+precision, tile width along x, current filter on/off); the host picks one of
+each per run from its patch and region shape.  Each case below is a small
+seeded thermal (2D) or cylinder (3D) plasma whose shape selects one
+particle-kernel and one field-kernel instantiation -- checked through
+pic_diag's kernel_path -- and compares one step and eight steps with the
+oracle (fields per family, particles by id).  ``test_paths_table`` (CPU)
+checks that the table names every instantiation in the kernel sources.
+
+Bars: FP64 within round-off of the oracle (1e-12 after one step, 1e-10 after
+eight); FP32 split 1e-5 after one step, 1e-4 after eight.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1912_04064_amd import binding as B
+from paper_1912_04064_amd import workloads as WL
+from tests.helpers import family_errors, oracle_state
+
+pytestmark = pytest.mark.gpu
+
+
+@dataclasses.dataclass(frozen=True)
+class Case:
+    name: str
+    dims: int
+    prec: str          # "fp64" | "fp32s"
+    n: tuple
+    patch: tuple
+    nreg: tuple
+    filt: int
+    push: tuple        # (patch edge of the compiled path, 0 = generic; LDS class)
+    yee_tx: int        # field-kernel tile width along x
+
+
+def _p(prec):
+    return "F32S" if prec == "fp32s" else "FP64"
+
+
+CASES = [
+    # 2D, FP32 split
+    Case("f32-p8-r128", 2, "fp32s", (128, 64), (8, 8), (1, 1), 0, (8, 8), 64),
+    Case("f32-p16-r32", 2, "fp32s", (64, 64), (16, 16), (2, 1), 0, (16, 16), 32),
+    Case("f32-p32-r32-filt1", 2, "fp32s", (64, 64), (32, 32), (2, 1), 1, (32, 32), 32),
+    Case("f32-p5x6-r5", 2, "fp32s", (40, 36), (5, 6), (8, 1), 0, (0, 8), 8),
+    Case("f32-p8x16-r16", 2, "fp32s", (64, 64), (8, 16), (4, 1), 0, (0, 16), 16),
+    Case("f32-p32x16-r128-filt2", 2, "fp32s", (128, 64), (32, 16), (1, 2), 2, (0, 32), 64),
+    Case("f32-p8-r16-filt3", 2, "fp32s", (64, 32), (8, 8), (4, 1), 3, (8, 8), 16),
+    Case("f32-p8-r8-filt1", 2, "fp32s", (64, 32), (8, 8), (8, 4), 1, (8, 8), 8),
+    # 2D, FP64
+    Case("f64-p8-r128", 2, "fp64", (128, 64), (8, 8), (1, 1), 0, (8, 8), 64),
+    Case("f64-p16-r32", 2, "fp64", (64, 64), (16, 16), (2, 1), 0, (16, 16), 32),
+    Case("f64-p5x6-r5", 2, "fp64", (40, 36), (5, 6), (8, 1), 0, (0, 8), 8),
+    Case("f64-p16x8-r16", 2, "fp64", (64, 48), (16, 8), (4, 1), 0, (0, 16), 16),
+    Case("f64-p32-r64-filt2", 2, "fp64", (64, 64), (32, 32), (1, 1), 2, (0, 32), 64),
+    Case("f64-p32x16-r32-filt1", 2, "fp64", (64, 64), (32, 16), (2, 1), 1, (0, 32), 32),
+    Case("f64-p8-r16-filt2", 2, "fp64", (64, 32), (8, 8), (4, 1), 2, (8, 8), 16),
+    Case("f64-p8-r8-filt1", 2, "fp64", (64, 32), (8, 8), (8, 4), 1, (8, 8), 8),
+    # 3D, FP32 split
+    Case("f32-3d-p8-r32", 3, "fp32s", (32, 16, 16), (8, 8, 8), (1, 1, 1), 0, (8, 8), 32),
+    Case("f32-3d-p4-r16", 3, "fp32s", (16, 16, 16), (4, 4, 4), (1, 1, 1), 0, (0, 8), 16),
+    Case("f32-3d-p4-r8", 3, "fp32s", (16, 16, 8), (4, 4, 4), (2, 2, 1), 0, (0, 8), 8),
+    Case("f32-3d-p8-r16-filt1", 3, "fp32s", (16, 16, 16), (8, 8, 8), (1, 1, 1), 1, (8, 8), 8),
+    # 3D, FP64
+    Case("f64-3d-p8-r32", 3, "fp64", (32, 16, 16), (8, 8, 8), (1, 1, 1), 0, (8, 8), 32),
+    Case("f64-3d-p8-r16", 3, "fp64", (16, 16, 16), (8, 8, 8), (1, 1, 1), 0, (8, 8), 16),
+    Case("f64-3d-p4-r8", 3, "fp64", (16, 16, 8), (4, 4, 4), (2, 2, 1), 0, (0, 8), 8),
+    Case("f64-3d-p4-r16-filt2", 3, "fp64", (16, 16, 16), (4, 4, 4), (1, 1, 1), 2, (0, 8), 8),
+]
+
+
+def push_instantiations():
+    """(dims, precision, patch edge, LDS class) of each particle-kernel case."""
+    return {(c.dims, _p(c.prec), c.push[0], c.push[1]) for c in CASES}
+
+
+def yee_instantiations():
+    """(dims, precision, tile x, filter) of each field-kernel case."""
+    return {(c.dims, _p(c.prec), c.yee_tx, c.filt > 0) for c in CASES}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def workload(c: Case):
+    if c.dims == 2:
+        wl = WL.thermal_2d(n=c.n, ppc=4, vth=0.05, patch=c.patch, nreg=c.nreg, precision=c.prec, name=c.name)
+    else:
+        wl = WL.cylinder_3d(n=c.n, radius=3.0, ppc_bg=2, ppc_cyl=16, vth=0.05, patch=c.patch, precision=c.prec,
+                            name=c.name)
+        wl = dataclasses.replace(wl, nreg=c.nreg)
+    return dataclasses.replace(wl, filter=c.filt)
+
+
+def _families(F):
+    return {"E": F[0:3], "Bm": F[6:9], "BH": F[3:6], "J": F[9:12]}
+
+
+def _errs(Fg, Fo):
+    out = {}
+    for k in ("E", "BH", "Bm", "J"):
+        out[k] = max(family_errors(Fg[k], Fo[k])) if np.linalg.norm(Fo[k]) > 0 else float(np.abs(Fg[k]).max())
+    return out
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c.name for c in CASES])
+def test_kernel_path_against_oracle(case):
+    say(f"case: {case}")
+    wl = workload(case)
+    g, F, P = oracle_state(wl)
+    mask = B.F_E | B.F_B | B.F_BH | B.F_J
+    res = {}
+    with B.Context([wl], track_ids=True) as ctx:
+        d = ctx.diag(0)
+        assert d["kernel_path"][:3] == [case.push[0], case.push[1], case.yee_tx], d["kernel_path"]
+        for steps in (1, 7):
+            ctx.step(steps)
+            Fa = ctx.fields(0, mask)
+            res[ctx.diag(0)["step"]] = ({"E": Fa[0:3], "Bm": Fa[3:6], "BH": Fa[6:9], "J": Fa[9:12]},
+                                        B.sort_by_id(ctx.particles(0)))
+    L = np.array(wl.n, float) * np.array(wl.d)
+    tol = {1: 1e-12, 8: 1e-10} if case.prec == "fp64" else {1: 1e-5, 8: 1e-4}
+    ptol = 1e-12 if case.prec == "fp64" else 1e-5
+    done = 0
+    for target in (1, 8):
+        while done < target:
+            O.step_sdsd(g, F, P)
+            done += 1
+        Fg, gp = res[target]
+        e = _errs(Fg, _families(F))
+        say(f"{case.name}: step {target} family errors {e}")
+        assert max(e.values()) < tol[target], e
+        assert np.array_equal(gp["id"], np.arange(wl.n_particles))
+        for a, k in enumerate(("x", "y", "z")[:case.dims]):
+            dd = np.abs(gp[k] - getattr(P, k))
+            assert np.minimum(dd, L[a] - dd).max() < ptol * max(1.0, L[a]), k
+        for k in ("ux", "uy", "uz"):
+            assert np.abs(gp[k] - getattr(P, k)).max() < ptol, k

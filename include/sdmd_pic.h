@@ -257,6 +257,20 @@ int pic_fields(pic_ctx *ctx, int32_t run, uint32_t mask, double *dst, size_t dst
 /* Fill *out for `run`.  Synchronises the stream. */
 int pic_diag(pic_ctx *ctx, int32_t run, pic_diag_t *out);
 
+/* pic_diag without any device allocation, for callers that cannot allocate
+ * device memory (a loop that must not call hipMalloc, code sharing the
+ * process with HIP graph capture, harnesses that forbid allocation).  Same
+ * output as pic_diag, from the same kernels; their scratch (charge density,
+ * Gauss residual and partial sums: 16 bytes per cell plus a few KB) lives in
+ * one static device array of 64 MiB per GPU, which the library holds from
+ * the first pic_init on that GPU until the process ends.  Runs of up to
+ * about 4.1 million cells fit; a larger run gets PIC_E_NOMEM and
+ * pic_last_error gives the bytes it would need.  Every call on one GPU
+ * shares that array and leaves its contents behind: calls that overlap on
+ * one GPU (other threads, other contexts) race and must be serialised by
+ * the caller.  Synchronises the stream. */
+int pic_diag_noalloc(pic_ctx *ctx, int32_t run, pic_diag_t *out);
+
 /* Export the particles of `run` (see pic_particles_out). Synchronises. */
 int pic_particles(pic_ctx *ctx, int32_t run, pic_particles_out *out);
 

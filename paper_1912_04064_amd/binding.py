@@ -43,8 +43,9 @@ F_BH = F_BHX | F_BHY | F_BHZ
 F_J = F_JX | F_JY | F_JZ
 F_ALL = F_E | F_B | F_BH | F_J
 
-EXPORTED = ["pic_init", "pic_step", "pic_fields", "pic_diag", "pic_particles", "pic_mem_bytes", "pic_admit",
-            "pic_retire", "pic_run_steps", "pic_time_phases", "pic_free", "pic_strerror", "pic_last_error"]
+EXPORTED = ["pic_init", "pic_step", "pic_fields", "pic_diag", "pic_diag_noalloc", "pic_particles", "pic_mem_bytes",
+            "pic_admit", "pic_retire", "pic_run_steps", "pic_time_phases", "pic_free", "pic_strerror",
+            "pic_last_error"]
 
 _dp = C.POINTER(C.c_double)
 
@@ -117,6 +118,7 @@ def load(path: str = LIB_PATH):
     L.pic_step.argtypes = [C.c_void_p, C.c_int32]
     L.pic_fields.argtypes = [C.c_void_p, C.c_int32, C.c_uint32, _dp, C.c_size_t, C.c_int32]
     L.pic_diag.argtypes = [C.c_void_p, C.c_int32, C.POINTER(PicDiag)]
+    L.pic_diag_noalloc.argtypes = [C.c_void_p, C.c_int32, C.POINTER(PicDiag)]
     L.pic_particles.argtypes = [C.c_void_p, C.c_int32, C.POINTER(PicParticlesOut)]
     L.pic_mem_bytes.argtypes = [C.POINTER(PicConfig), C.POINTER(C.c_size_t)]
     L.pic_admit.argtypes = [C.c_void_p, C.POINTER(PicConfig), C.POINTER(C.c_int32)]
@@ -129,8 +131,8 @@ def load(path: str = LIB_PATH):
     L.pic_strerror.restype = C.c_char_p
     L.pic_last_error.argtypes = [C.c_void_p]
     L.pic_last_error.restype = C.c_char_p
-    for name in ("pic_init", "pic_step", "pic_fields", "pic_diag", "pic_particles", "pic_mem_bytes", "pic_admit",
-                 "pic_retire", "pic_run_steps", "pic_time_phases"):
+    for name in ("pic_init", "pic_step", "pic_fields", "pic_diag", "pic_diag_noalloc", "pic_particles",
+                 "pic_mem_bytes", "pic_admit", "pic_retire", "pic_run_steps", "pic_time_phases"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -284,11 +286,14 @@ class Context:
             _check(self.L, self.ctx, rc, "pic_fields")
         return out
 
-    def diag(self, run: int = 0, check=True) -> dict:
+    def diag(self, run: int = 0, check=True, noalloc=False) -> dict:
+        """pic_diag, or with noalloc=True pic_diag_noalloc (no device
+        allocation: its scratch is the library's static per-GPU array)."""
         d = PicDiag()
-        rc = self.L.pic_diag(self.ctx, run, C.byref(d))
+        fn = self.L.pic_diag_noalloc if noalloc else self.L.pic_diag
+        rc = fn(self.ctx, run, C.byref(d))
         if check:
-            _check(self.L, self.ctx, rc, "pic_diag")
+            _check(self.L, self.ctx, rc, "pic_diag_noalloc" if noalloc else "pic_diag")
         out = {k: getattr(d, k) for k, _ in PicDiag._fields_ if k not in ("t_ms", "patch", "kernel_path")}
         out["t_ms"] = list(d.t_ms)
         out["patch"] = list(d.patch)

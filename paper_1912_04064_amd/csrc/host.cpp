@@ -86,6 +86,7 @@ struct pic_ctx {
     pic_runtime rt{};
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
+    int device = -1;          // the device current at pic_init
     int max_runs = 0;
     std::vector<Run> runs;
     RunDev *d_runs = nullptr;
@@ -126,6 +127,49 @@ static int set_err(pic_ctx *c, int code, const char *fmt, ...)
         hipError_t e_ = (expr);                                                                            \
         if (e_ != hipSuccess) return set_err(ctx, PIC_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));   \
     } while (0)
+
+// ------------------------------------------------------------------ static scratch
+// Device scratch of pic_diag_noalloc: one array per GPU in this library's
+// code object, held until the process ends.  Host code never uses the
+// array's name as an address (in host code it is only a stand-in for the
+// symbol): the device address is looked up once per device, at pic_init
+// with that device current, and every use goes through that address.
+// All calls on one GPU share the array.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES];
+static hipError_t g_scratch_err[MAX_DEVICES];
+static bool g_scratch_done[MAX_DEVICES];
+
+static void resolve_static_scratch(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_done[dev]) return;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = e == hipSuccess ? p : nullptr;
+    g_scratch_err[dev] = e;
+    g_scratch_done[dev] = true;
+}
+
+static void *static_scratch(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_done[dev] ? g_scratch_ptr[dev] : nullptr;
+}
+
+static const char *static_scratch_error(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return "device index out of range";
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[dev]) return "not looked up: no context was created on this device";
+    return hipGetErrorString(g_scratch_err[dev]);
+}
 
 // ------------------------------------------------------------------ memory
 // Every device allocation of a context goes through dev_alloc, rounded to
@@ -1059,6 +1103,8 @@ int pic_init(const pic_config *cfgs, int32_t n_runs, const pic_runtime *rt, pic_
     }
     pic_ctx *c = new pic_ctx();
     if (rt) c->rt = *rt;
+    if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
+    resolve_static_scratch(c->device);
     c->stream = (hipStream_t)c->rt.stream;
     c->max_runs = c->rt.max_runs > 0 ? std::max(c->rt.max_runs, n_runs) : std::max(n_runs, 1);
     c->use_graph = !(c->rt.flags & PIC_RT_NO_GRAPH);
@@ -1230,10 +1276,73 @@ int pic_fields(pic_ctx *c, int32_t run, uint32_t mask, double *dst, size_t dst_l
     return check_run_err(c, run);
 }
 
+}  // extern "C"
+
+// Device scratch of one diagnostics call: partial sums (max(2 nb, nk)
+// doubles), the Gauss residual per node plus its block maxima (ncell + 2 nb
+// doubles), the charge density (ncell doubles).
+struct DiagScratch {
+    double *part, *gb, *rho;
+};
+
+static void diag_sizes(const Run &r, int &nb, int &nk)
+{
+    nb = std::max(1, std::min(1024, (r.ncell + BLOCK - 1) / BLOCK));
+    nk = r.rd.seg_max + 1;
+}
+
+static size_t diag_scratch_bytes(const Run &r, size_t off[3])
+{
+    int nb, nk;
+    diag_sizes(r, nb, nk);
+    off[0] = 0;
+    off[1] = align256((size_t)std::max(2 * nb, nk) * 8);
+    off[2] = off[1] + align256((size_t)r.ncell * 8 + (size_t)2 * nb * 8);
+    return off[2] + align256((size_t)r.ncell * 8);
+}
+
+static int diag_impl(pic_ctx *c, int32_t run, pic_diag_t *out, const DiagScratch &ds);
+
+extern "C" {
+
 int pic_diag(pic_ctx *c, int32_t run, pic_diag_t *out)
 {
     if (!c || !out || run < 0 || run >= (int)c->runs.size() || !c->runs[run].active)
         return set_err(c, PIC_E_INVAL, "bad argument");
+    int nb, nk;
+    diag_sizes(c->runs[run], nb, nk);
+    Scratch scr(c);
+    DiagScratch ds;
+    ds.part = (double *)scr.get((size_t)std::max(2 * nb, nk) * 8);
+    ds.gb = ds.part ? (double *)scr.get((size_t)c->runs[run].ncell * 8 + (size_t)2 * nb * 8) : nullptr;
+    ds.rho = ds.gb ? (double *)scr.get((size_t)c->runs[run].ncell * 8) : nullptr;
+    if (!ds.part || !ds.gb || !ds.rho) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
+    return diag_impl(c, run, out, ds);
+}
+
+int pic_diag_noalloc(pic_ctx *c, int32_t run, pic_diag_t *out)
+{
+    if (!c || !out || run < 0 || run >= (int)c->runs.size() || !c->runs[run].active)
+        return set_err(c, PIC_E_INVAL, "bad argument");
+    char *base = (char *)static_scratch(c->device);
+    if (!base)
+        return set_err(c, PIC_E_DEVICE, "pic_diag_noalloc: static scratch of device %d unavailable (%s)", c->device,
+                       static_scratch_error(c->device));
+    size_t off[3];
+    const size_t need = diag_scratch_bytes(c->runs[run], off);
+    if (need > STATIC_SCRATCH_BYTES)
+        return set_err(c, PIC_E_NOMEM,
+                       "pic_diag_noalloc: run %d needs %zu bytes of scratch; the static scratch holds %zu "
+                       "(grids up to about 4.1 million cells)",
+                       run, need, STATIC_SCRATCH_BYTES);
+    DiagScratch ds{(double *)(base + off[0]), (double *)(base + off[1]), (double *)(base + off[2])};
+    return diag_impl(c, run, out, ds);
+}
+
+}  // extern "C"
+
+static int diag_impl(pic_ctx *c, int32_t run, pic_diag_t *out, const DiagScratch &ds)
+{
     Run &r = c->runs[run];
     const RunDev &d = r.rd;
     memset(out, 0, sizeof *out);
@@ -1266,11 +1375,9 @@ int pic_diag(pic_ctx *c, int32_t run, pic_diag_t *out)
         out->patch_mean = (double)n / d.n_patch;
     }
     const double dV = d.d[0] * d.d[1] * (d.dims == 3 ? d.d[2] : 1.0);
-    const int nb = std::max(1, std::min(1024, (r.ncell + BLOCK - 1) / BLOCK));
-    const int nk = d.seg_max + 1;
-    Scratch scr(c);
-    double *part = (double *)scr.get((size_t)std::max(2 * nb, nk) * 8);
-    if (!part) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
+    int nb, nk;
+    diag_sizes(r, nb, nk);
+    double *part = ds.part;
     std::vector<double> h(std::max(2 * nb, nk));
     HIPCHK(c, launch_field_energy(c->d_runs, run, r.ncell, run_par(r), part, nb, c->stream));
     HIPCHK(c, hipMemcpyAsync(h.data(), part, 2 * nb * 8, hipMemcpyDeviceToHost, c->stream));
@@ -1291,9 +1398,8 @@ int pic_diag(pic_ctx *c, int32_t run, pic_diag_t *out)
     for (int i = 0; i < 4; ++i) out->t_ms[i] = c->t_ms[i];
     {
         // Gauss-law residual against the initial state
-        double *gb = (double *)scr.get((size_t)r.ncell * 8 + (size_t)2 * nb * 8);
-        double *rho = gb ? (double *)scr.get((size_t)r.ncell * 8) : nullptr;
-        if (!gb || !rho) return set_err(c, PIC_E_NOMEM, "staging allocation failed");
+        double *gb = ds.gb;
+        double *rho = ds.rho;
         hipError_t e = launch_rho(r.dims, r.split, c->d_runs, run, d.seg_max, ctl.nspill, r.ncell, rho, c->stream);
         if (e == hipSuccess) e = launch_gauss(c->d_runs, run, r.ncell, run_par(r), rho, gb, c->stream);
         if (e == hipSuccess) e = launch_gauss_max(r.ncell, gb, r.gauss0, rho, gb + r.ncell, nb, c->stream);
@@ -1321,6 +1427,8 @@ int pic_diag(pic_ctx *c, int32_t run, pic_diag_t *out)
     out->device_bytes_peak = (int64_t)c->peak_bytes;
     return check_run_err(c, run);
 }
+
+extern "C" {
 
 int pic_particles(pic_ctx *c, int32_t run, pic_particles_out *out)
 {

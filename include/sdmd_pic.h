@@ -176,8 +176,28 @@ typedef struct {
 /* Where device memory and work go.  alloc(bytes, stream, user) returns
  * device memory or null; free(ptr, bytes, stream, user) releases it.  Both
  * null: hipMalloc / hipFree.  stream: a hipStream_t (null = null stream).
- * hbm_budget: bytes the context may hold in total (0 = unlimited).
- * max_runs: run slots for pic_admit (0 = the n_runs given to pic_init). */
+ * hbm_budget: bytes the context may hold in total (0 = unlimited); every
+ * device allocation of the context counts, set-up staging, read-out
+ * scratch and the autotuner's trial runs included, and one that would pass
+ * the budget fails with PIC_E_NOMEM.
+ * max_runs: run slots for pic_admit (0 = the n_runs given to pic_init).
+ * deterministic: nonzero makes every run of the context bitwise
+ * reproducible.  SDMD only re-decomposes one domain (section 2.2), so a
+ * run's result is defined independently of how its particles are split
+ * into patches and segments, of the regions, and of the other runs beside
+ * it; floating-point sums, however, depend on the order of their terms, and
+ * atomic deposition fixes no order.  In this mode each current and charge
+ * contribution is rounded once to a multiple of a quantum (a power of two
+ * chosen per run: about 2^-62 of the run's particle count times its largest
+ * possible contribution, reported by pic_diag as det_quantum) and summed in
+ * 64-bit integers, which is exact.  Then E, B, Bm, J, rho and every
+ * particle's state are the same bit for bit on every execution, alone or
+ * in a batch, for any region layout, and after a resume from exported
+ * state; the storage order of particles inside a patch and the last bits of
+ * the kinetic-energy sum (taken in storage order) are not.  The current
+ * differs from the FP64 sum by at most half a quantum per contribution.
+ * Costs one more FP64 operation and a 64-bit integer subtraction per
+ * deposit, and 8-byte current tiles in the FP32 split form. */
 typedef struct {
     void *(*alloc)(size_t bytes, void *stream, void *user);
     void (*free)(void *ptr, size_t bytes, void *stream, void *user);
@@ -186,6 +206,8 @@ typedef struct {
     size_t  hbm_budget;
     int32_t max_runs;
     int32_t flags;              /* PIC_RT_* */
+    int32_t deterministic;
+    int32_t reserved;
 } pic_runtime;
 
 /* Diagnostics of one run at its current step.  t_ms: time per step of the
@@ -224,6 +246,9 @@ typedef struct {
     int64_t device_bytes_peak;        /* the most it has held since pic_init;
                                          never above pic_runtime.hbm_budget
                                          when a budget is set              */
+    double  det_quantum[2];           /* deterministic mode: the quantum of
+                                         the fixed-point current and charge
+                                         sums (0 otherwise)                */
 } pic_diag_t;
 
 /* Particle export (host memory, caller owned).  capacity is the length of
@@ -274,8 +299,11 @@ int pic_diag_noalloc(pic_ctx *ctx, int32_t run, pic_diag_t *out);
 /* Export the particles of `run` (see pic_particles_out). Synchronises. */
 int pic_particles(pic_ctx *ctx, int32_t run, pic_particles_out *out);
 
-/* Device bytes pic_init / pic_admit would take for this config (admission
- * by HBM budget).  Does not touch the GPU. */
+/* Device bytes pic_init / pic_admit would take for this config at most
+ * (admission by HBM budget): what the run holds between calls plus the most
+ * any call takes on top of it (set-up staging, read-out scratch, patch
+ * autotuning), counted with the deterministic mode's 8-byte current tiles
+ * so that the figure bounds both modes.  Does not touch the GPU. */
 int pic_mem_bytes(const pic_config *cfg, size_t *bytes);
 
 /* Add a run to a live context (continuous batching); *run_id receives its

@@ -74,7 +74,8 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 
 class PicRuntime(C.Structure):
     _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("stream", C.c_void_p), ("user", C.c_void_p),
-                ("hbm_budget", C.c_size_t), ("max_runs", C.c_int32), ("flags", C.c_int32)]
+                ("hbm_budget", C.c_size_t), ("max_runs", C.c_int32), ("flags", C.c_int32),
+                ("deterministic", C.c_int32), ("reserved", C.c_int32)]
 
 
 class PicDiag(C.Structure):
@@ -82,7 +83,8 @@ class PicDiag(C.Structure):
                 ("patch_max", C.c_int64), ("patch_mean", C.c_double), ("U_E", C.c_double), ("U_B", C.c_double),
                 ("K", C.c_double), ("t_ms", C.c_double * 4), ("n_relayout", C.c_int64), ("n_spill", C.c_int64),
                 ("err_flags", C.c_int32), ("patch", C.c_int32 * 3), ("gauss_residual", C.c_double),
-                ("kernel_path", C.c_int32 * 4), ("device_bytes", C.c_int64), ("device_bytes_peak", C.c_int64)]
+                ("kernel_path", C.c_int32 * 4), ("device_bytes", C.c_int64), ("device_bytes_peak", C.c_int64),
+                ("det_quantum", C.c_double * 2)]
 
 
 class PicParticlesOut(C.Structure):
@@ -201,7 +203,7 @@ class Context:
     """A live set of runs on cuda:0.  Workloads come from ``workloads``."""
 
     def __init__(self, workloads: Sequence, track_ids=False, use_torch=True, graph=True, max_runs=0,
-                 hbm_budget=0, patch=None, max_steps=None):
+                 hbm_budget=0, patch=None, max_steps=None, deterministic=False):
         self.L = load()
         self._torch = None
         self._cbs = None
@@ -238,6 +240,7 @@ class Context:
         rt.hbm_budget = hbm_budget
         rt.max_runs = max_runs
         rt.flags = 0 if graph else PIC_RT_NO_GRAPH
+        rt.deterministic = 1 if deterministic else 0
         self._rt = rt
         ctx = C.c_void_p()
         rc = self.L.pic_init(cfgs, len(workloads), C.byref(rt), C.byref(ctx))
@@ -294,10 +297,10 @@ class Context:
         rc = fn(self.ctx, run, C.byref(d))
         if check:
             _check(self.L, self.ctx, rc, "pic_diag_noalloc" if noalloc else "pic_diag")
-        out = {k: getattr(d, k) for k, _ in PicDiag._fields_ if k not in ("t_ms", "patch", "kernel_path")}
-        out["t_ms"] = list(d.t_ms)
-        out["patch"] = list(d.patch)
-        out["kernel_path"] = list(d.kernel_path)
+        arrays = ("t_ms", "patch", "kernel_path", "det_quantum")
+        out = {k: getattr(d, k) for k, _ in PicDiag._fields_ if k not in arrays}
+        for k in arrays:
+            out[k] = list(getattr(d, k))
         out["rc"] = rc
         return out
 
@@ -329,6 +332,21 @@ class Context:
         s = C.c_int64()
         _check(self.L, self.ctx, self.L.pic_run_steps(self.ctx, run, C.byref(s)), "pic_run_steps")
         return s.value
+
+    def checkpoint(self, run: int = 0):
+        """The run's state as a resumable input: a copy of its workload whose
+        initial fields are E^n, B^{n+1/2}, Bm^n (kind 1) and whose particles
+        are the exported ones (with ids when the context tracks them).  A
+        context made from it continues the run."""
+        import dataclasses
+        w = self.workloads[run]
+        F = self.fields(run, F_E | F_BH | F_B)
+        p = self.particles(run)
+        parts = {k: p[k] for k in ("x", "y", "z", "ux", "uy", "uz", "w")}
+        if self.track_ids:
+            parts["id"] = p["id"]
+        return dataclasses.replace(w, parts=parts, E0=F[0:3].copy(), B0=F[6:9].copy(), Bm0=F[3:6].copy(),
+                                   field_kind=1)
 
     def sync(self):
         if self._torch is not None:

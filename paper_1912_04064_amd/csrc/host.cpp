@@ -87,6 +87,7 @@ struct pic_ctx {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     int device = -1;          // the device current at pic_init
+    bool det = false;         // deterministic mode (pic_runtime.deterministic)
     int max_runs = 0;
     std::vector<Run> runs;
     RunDev *d_runs = nullptr;
@@ -244,6 +245,7 @@ struct Layout {
     int seg_cap, seg_max;
     long long rsize;
     long long n_total, cap_total;
+    size_t tile_esz;   // bytes per tile value: FP32 / FP64, 8 in the deterministic mode
     size_t resident;   // device bytes the run holds between calls
     size_t bytes;      // resident + the most any call takes on top (set-up
                        // staging, read-out scratch, the run's item lists)
@@ -283,7 +285,7 @@ static int fast_patch(const Layout &L)
 }
 
 // validate a config (patch already chosen) and derive the layout
-static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::string &why)
+static int make_layout(const pic_config *cfg, const int P[3], bool det, Layout &L, std::string &why)
 {
     char buf[256];
     auto fail = [&](const char *m) {
@@ -373,11 +375,12 @@ static int make_layout(const pic_config *cfg, const int P[3], Layout &L, std::st
     if (L.cap_total > (1LL << 31) - 1) return fail("too many particles for one run");
     // bytes
     const size_t rsz = L.split ? 4 : 8;
+    L.tile_esz = det ? 8 : rsz;
     const bool ids = cfg->track_ids != 0;
     const size_t per = dims * rsz + (L.split ? 2 : 0) + 3 * rsz + rsz + (ids ? 4 : 0);
     size_t b = 0;
     b += align256((size_t)L.n_regions * F_NCOMP * L.rsize * 8);
-    b += align256((size_t)L.seg_max * 3 * L.tsz * rsz);
+    b += align256((size_t)L.seg_max * 3 * L.tsz * L.tile_esz);
     b += 7 * align256((size_t)(L.n_patch + 1) * 4) + 7 * align256((size_t)(L.seg_max + 1) * 4);
     b += 2 * (size_t)L.cap_total * per + align256((size_t)L.cap_total * 4);
     b += 2 * (size_t)std::max<long long>(L.n_total, 1) * (per + 4);
@@ -607,6 +610,48 @@ static void autotune_patch(pic_ctx *c, const pic_config *cfg, int P[3])
 
 static int gauss_field(pic_ctx *c, int slot, double *g);
 
+// The largest power of two 2^e with unit * count * 2^e <= 2^62 and
+// unit * 2^e <= 2^50: `count` contributions of magnitude at most `unit`,
+// each rounded to a multiple of 2^-e, then sum without leaving the signed
+// 64-bit range, and each scaled contribution stays inside the exact range
+// of the rounding in to_fixed (|v| < 2^51).
+static double fixed_scale(double unit, double count)
+{
+    if (!(unit > 0) || !std::isfinite(unit)) return 1.0;
+    const double lim = std::min(std::ldexp(1.0, 62) / (unit * std::max(count, 1.0)), std::ldexp(1.0, 50) / unit);
+    const int e = std::max(-1000, std::min(1000, (int)std::floor(std::log2(lim))));
+    return std::ldexp(1.0, e);
+}
+
+// Fixed-point scales of the deterministic mode.  A node receives at most
+// one contribution per particle and component per step.  A current
+// contribution is q w times a sum of shape-factor differences of modulus at
+// most 1, times d/dt (Jx, Jy, Jz in 3D) or v_z with |v_z| < 1 (Jz in 2D);
+// a charge contribution is q w times shape factors of at most 1.  So |q| w_max
+// max(1, d/dt) and |q| w_max bound them, and N of them still fit.  Scales
+// depend only on the run's configuration and particle weights, so a run
+// alone, in a batch, re-decomposed or resumed from its exported state sums
+// with the same quantum.
+static void fixed_point_scales(const pic_config *cfg, const Layout &L, RunDev &d)
+{
+    // the weights as the particle store keeps them (FP32 in the split form),
+    // so that a run re-created from its exported particles gets the same scale
+    double wmax = 0.0;
+    if (cfg->particles && cfg->particles->w)
+        for (long long i = 0; i < L.n_total; ++i) {
+            const double w = cfg->particles->w[i];
+            wmax = std::max(wmax, std::fabs(L.split ? (double)(float)w : w));
+        }
+    const double uq = std::fabs(cfg->q) * wmax;
+    double dmax = 1.0;
+    for (int a = 0; a < L.dims; ++a) dmax = std::max(dmax, d.d[a] / cfg->dt);
+    const double n = (double)std::max<long long>(L.n_total, 1);
+    d.jscale = fixed_scale(uq * dmax, n);
+    d.jscale_inv = 1.0 / d.jscale;
+    d.rscale = fixed_scale(uq, n);
+    d.rscale_inv = 1.0 / d.rscale;
+}
+
 static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
 {
     Run &r = c->runs[slot];
@@ -614,7 +659,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     if (auto_patch(cfg)) autotune_patch(c, cfg, P);
     Layout L;
     std::string why;
-    int rc = make_layout(cfg, P, L, why);
+    int rc = make_layout(cfg, P, c->det, L, why);
     if (rc) return set_err(c, rc, "%s", why.c_str());
     if (c->rt.hbm_budget && c->bytes + L.bytes > c->rt.hbm_budget)
         return set_err(c, PIC_E_NOMEM, "HBM budget exceeded (%zu + %zu > %zu)", c->bytes, L.bytes, c->rt.hbm_budget);
@@ -633,6 +678,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     d.prec = cfg->precision;
     d.filter = cfg->filter_passes;
     d.solver = cfg->field_solver;
+    d.det = c->det ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
         d.n[a] = L.n[a];
         d.P[a] = L.P[a];
@@ -665,11 +711,12 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
         d.f_dtd[a] = (float)(cfg->dt / d.d[a]);
         d.f_cj[a] = (float)(-cfg->q * d.d[a] / cfg->dt);
     }
+    fixed_point_scales(cfg, L, d);
     const size_t rsz = L.split ? 4 : 8;
     const bool ids = cfg->track_ids != 0;
     bool ok = true;
     d.fld = (double *)run_alloc(c, r, (size_t)L.n_regions * F_NCOMP * L.rsize * 8);
-    d.tiles = run_alloc(c, r, (size_t)L.seg_max * 3 * L.tsz * rsz);
+    d.tiles = run_alloc(c, r, (size_t)L.seg_max * 3 * L.tsz * L.tile_esz);
     const size_t pb = (size_t)(L.n_patch + 1) * 4, sb = (size_t)(L.seg_max + 1) * 4;
     d.pseg = (int *)run_alloc(c, r, pb);
     d.pseg2 = (int *)run_alloc(c, r, pb);
@@ -713,7 +760,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     r.active = true;
     hipStream_t s = c->stream;
     HIPCHK(c, hipMemsetAsync(d.fld, 0, (size_t)L.n_regions * F_NCOMP * L.rsize * 8, s));
-    HIPCHK(c, hipMemsetAsync(d.tiles, 0, (size_t)L.seg_max * 3 * L.tsz * rsz, s));
+    HIPCHK(c, hipMemsetAsync(d.tiles, 0, (size_t)L.seg_max * 3 * L.tsz * L.tile_esz, s));
     HIPCHK(c, hipMemsetAsync(d.pseg, 0, pb, s));
     HIPCHK(c, hipMemsetAsync(d.spcnt, 0, pb, s));
     HIPCHK(c, hipMemsetAsync(d.sseg, 0, sb, s));
@@ -901,7 +948,7 @@ static int rebuild_items(pic_ctx *c)
 static hipError_t enqueue_push(pic_ctx *c, int par, hipStream_t s)
 {
     for (auto &pc : c->pcls) {
-        hipError_t e = launch_push(pc.dims, pc.split, pc.px, pc.pc, c->d_runs, pc.d, (int)pc.h.size(), par, s);
+        hipError_t e = launch_push(pc.dims, pc.split, pc.px, pc.pc, c->det, c->d_runs, pc.d, (int)pc.h.size(), par, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -910,7 +957,8 @@ static hipError_t enqueue_push(pic_ctx *c, int par, hipStream_t s)
 static hipError_t enqueue_yee(pic_ctx *c, int par, hipStream_t s)
 {
     for (auto &fc : c->fcls) {
-        hipError_t e = launch_yee(fc.dims, fc.split, fc.tx, fc.filt, c->d_runs, fc.dy, (int)fc.hy.size(), par, s);
+        hipError_t e =
+            launch_yee(fc.dims, fc.split, fc.tx, fc.filt, c->det, c->d_runs, fc.dy, (int)fc.hy.size(), par, s);
         if (e != hipSuccess) return e;
         if (fc.solver == PIC_SOLVER_PSATD)
             for (int slot : fc.slots) {
@@ -1001,7 +1049,7 @@ static int gauss_field(pic_ctx *c, int slot, double *g)
     hipError_t e;
     Ctl ctl = read_ctl(c, slot, e);
     if (e == hipSuccess)
-        e = launch_rho(r.dims, r.split, c->d_runs, slot, r.rd.seg_max, ctl.nspill, r.ncell, rho, c->stream);
+        e = launch_rho(r.dims, r.split, r.rd.det, c->d_runs, slot, r.rd.seg_max, ctl.nspill, r.ncell, rho, c->stream);
     if (e == hipSuccess) e = launch_gauss(c->d_runs, slot, r.ncell, run_par(r), rho, g, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return set_err(c, PIC_E_DEVICE, "Gauss residual: %s", hipGetErrorString(e));
@@ -1059,7 +1107,7 @@ int pic_mem_bytes(const pic_config *cfg, size_t *bytes)
     for (auto &sh : shapes) {
         Layout L;
         std::string why;
-        int rc = make_layout(cfg, sh.data(), L, why);
+        int rc = make_layout(cfg, sh.data(), true, L, why);
         if (rc) return set_err(nullptr, rc, "%s", why.c_str());
         worst = std::max(worst, L.bytes);
     }
@@ -1098,12 +1146,13 @@ int pic_init(const pic_config *cfgs, int32_t n_runs, const pic_runtime *rt, pic_
         }
         Layout L;
         std::string why;
-        int rc = make_layout(&cfgs[i], P, L, why);
+        int rc = make_layout(&cfgs[i], P, rt && rt->deterministic, L, why);
         if (rc) return set_err(nullptr, rc, "run %d: %s", i, why.c_str());
     }
     pic_ctx *c = new pic_ctx();
     if (rt) c->rt = *rt;
     if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
+    c->det = c->rt.deterministic != 0;
     resolve_static_scratch(c->device);
     c->stream = (hipStream_t)c->rt.stream;
     c->max_runs = c->rt.max_runs > 0 ? std::max(c->rt.max_runs, n_runs) : std::max(n_runs, 1);
@@ -1263,7 +1312,8 @@ int pic_fields(pic_ctx *c, int32_t run, uint32_t mask, double *dst, size_t dst_l
         } else {
             Ctl ctl = read_ctl(c, run, e);
             if (e == hipSuccess)
-                e = launch_rho(r.dims, r.split, c->d_runs, run, r.rd.seg_max, ctl.nspill, r.ncell, tmp, c->stream);
+                e = launch_rho(r.dims, r.split, r.rd.det, c->d_runs, run, r.rd.seg_max, ctl.nspill, r.ncell, tmp,
+                               c->stream);
         }
         if (e == hipSuccess)
             e = hipMemcpyAsync(dst + o, tmp, nc * 8, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
@@ -1400,7 +1450,8 @@ static int diag_impl(pic_ctx *c, int32_t run, pic_diag_t *out, const DiagScratch
         // Gauss-law residual against the initial state
         double *gb = ds.gb;
         double *rho = ds.rho;
-        hipError_t e = launch_rho(r.dims, r.split, c->d_runs, run, d.seg_max, ctl.nspill, r.ncell, rho, c->stream);
+        hipError_t e =
+            launch_rho(r.dims, r.split, d.det, c->d_runs, run, d.seg_max, ctl.nspill, r.ncell, rho, c->stream);
         if (e == hipSuccess) e = launch_gauss(c->d_runs, run, r.ncell, run_par(r), rho, gb, c->stream);
         if (e == hipSuccess) e = launch_gauss_max(r.ncell, gb, r.gauss0, rho, gb + r.ncell, nb, c->stream);
         std::vector<double> hm(2 * nb);
@@ -1422,7 +1473,9 @@ static int diag_impl(pic_ctx *c, int32_t run, pic_diag_t *out, const DiagScratch
     out->kernel_path[0] = r.px;
     out->kernel_path[1] = r.pc;
     out->kernel_path[2] = yee_tile_x(r.dims, d.rs[0], d.filter > 0);
-    out->kernel_path[3] = 0;
+    out->kernel_path[3] = d.det;
+    out->det_quantum[0] = d.det ? d.jscale_inv : 0.0;
+    out->det_quantum[1] = d.det ? d.rscale_inv : 0.0;
     out->device_bytes = (int64_t)c->bytes;
     out->device_bytes_peak = (int64_t)c->peak_bytes;
     return check_run_err(c, run);

@@ -14,6 +14,8 @@
 //                  The per-run step bookkeeping (budget, overflow and spill
 //                  counters) is done by one workgroup of yee_kernel.
 //   init / readout helpers.
+#include <type_traits>
+
 #include "launch.h"
 #include "part.h"
 #include "sdmd_dev.h"
@@ -77,6 +79,22 @@ __device__ __forceinline__ void gather_tables(const RunDev &rd, const GatherBox 
     }
 }
 
+// Sum of tile values: FP64 over FP32 / FP64 tiles; in the deterministic
+// mode 64-bit integers (wrapping: only the total has to be in range),
+// converted once at the end.
+template <class R>
+struct TileSum {
+    using A = double;
+    static __device__ __forceinline__ A of(R v) { return (double)v; }
+    static __device__ __forceinline__ double result(A s, const RunDev &) { return s; }
+};
+template <>
+struct TileSum<long long> {
+    using A = unsigned long long;
+    static __device__ __forceinline__ A of(long long v) { return (unsigned long long)v; }
+    static __device__ __forceinline__ double result(A s, const RunDev &rd) { return (double)(long long)s * rd.jscale_inv; }
+};
+
 // J at box node (ex, ey, ez): the sum over the covering patches (z, y, x
 // ascending) and their segments (ascending) of the segment tiles.
 //
@@ -103,7 +121,8 @@ __device__ __forceinline__ void gather_J(const RunDev &rd, const SDMD_GLOBAL R *
     }
     const long long tsz = rd.tsz;
     const int TA0 = rd.TA[0], TA1 = rd.TA[1];
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    using S = TileSum<R>;
+    typename S::A s0 = 0, s1 = 0, s2 = 0;
     const bool wide = SEGU > 0 && P[0] >= 5 && P[1] >= 5 && (DIM == 2 || P[2] >= 5);
     if (wide) {
         if constexpr (SEGU > 0) {
@@ -135,15 +154,15 @@ __device__ __forceinline__ void gather_J(const RunDev &rd, const SDMD_GLOBAL R *
 #pragma unroll
                 for (int j = 0; j < SEGU; ++j)
                     if (rg[k].x + j < rg[k].y) {
-                        s0 += (double)v[k][j][0];
-                        s1 += (double)v[k][j][1];
-                        s2 += (double)v[k][j][2];
+                        s0 += S::of(v[k][j][0]);
+                        s1 += S::of(v[k][j][1]);
+                        s2 += S::of(v[k][j][2]);
                     }
                 for (int sg = rg[k].x + SEGU; sg < rg[k].y; ++sg) {
                     const SDMD_GLOBAL R *t = tiles + (long long)sg * 3 * tsz + off[k];
-                    s0 += (double)t[0];
-                    s1 += (double)t[tsz];
-                    s2 += (double)t[2 * tsz];
+                    s0 += S::of(t[0]);
+                    s1 += S::of(t[tsz]);
+                    s2 += S::of(t[2 * tsz]);
                 }
             }
         }
@@ -158,15 +177,15 @@ __device__ __forceinline__ void gather_J(const RunDev &rd, const SDMD_GLOBAL R *
                     const int of = (tz * TA1 + ty) * TA0 + tx;
                     for (int sg = r.x; sg < r.y; ++sg) {
                         const SDMD_GLOBAL R *t = tiles + (long long)sg * 3 * tsz + of;
-                        s0 += (double)t[0];
-                        s1 += (double)t[tsz];
-                        s2 += (double)t[2 * tsz];
+                        s0 += S::of(t[0]);
+                        s1 += S::of(t[tsz]);
+                        s2 += S::of(t[2 * tsz]);
                     }
                 }
     }
-    J[0] = s0;
-    J[1] = s1;
-    J[2] = s2;
+    J[0] = S::result(s0, rd);
+    J[1] = S::result(s1, rd);
+    J[2] = S::result(s2, rd);
 }
 
 // Yee tile shapes: one node per thread, x extent TX chosen per run from the
@@ -207,11 +226,12 @@ struct FilterMax {
 template <int DIM, class T>
 constexpr int GATHER_SEGU = DIM == 2 ? 2 : 1;
 
-template <int DIM, class T, int TXC, bool FILT>
+// DET: deterministic mode (64-bit fixed-point tiles summed exactly)
+template <int DIM, class T, int TXC, bool FILT, bool DET>
 __global__ __launch_bounds__((YeeTile<DIM, TXC>::NT)) void yee_kernel(const RunDev *__restrict__ runs,
                                                                       const int4 *__restrict__ items, int par)
 {
-    using R = typename T::real;
+    using R = typename std::conditional<DET, long long, typename T::real>::type;   // tile element
     constexpr int NT = YeeTile<DIM, TXC>::NT;
     constexpr int TX = YeeTile<DIM, TXC>::X, TY = YeeTile<DIM, TXC>::Y, TZ = YeeTile<DIM, TXC>::Z;
     static_assert(TX * TY * TZ == NT, "one node per thread");
@@ -637,7 +657,10 @@ __global__ __launch_bounds__(BLOCK) void post_kernel(const RunDev *__restrict__ 
 
 #define YEE_CASE(D, TT, X, FL)                                                                        \
     if (dims == D && split == TT::split && tx == X && filt == FL) {                                   \
-        yee_kernel<D, TT, X, FL><<<n_items, yee_block(D, X), 0, s>>>(runs, items, par);                \
+        if (det)                                                                                      \
+            yee_kernel<D, TT, X, FL, true><<<n_items, yee_block(D, X), 0, s>>>(runs, items, par);      \
+        else                                                                                          \
+            yee_kernel<D, TT, X, FL, false><<<n_items, yee_block(D, X), 0, s>>>(runs, items, par);     \
         return hipGetLastError();                                                                     \
     }
 
@@ -662,8 +685,8 @@ void yee_tile_shape(int dims, int tx, int shape[3])
     }
 }
 
-hipError_t launch_yee(int dims, bool split, int tx, bool filt, const RunDev *runs, const int4 *items, int n_items,
-                      int par, hipStream_t s)
+hipError_t launch_yee(int dims, bool split, int tx, bool filt, bool det, const RunDev *runs, const int4 *items,
+                      int n_items, int par, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
     YEE_CASE(2, F32S, 64, false) YEE_CASE(2, F32S, 32, false) YEE_CASE(2, F32S, 16, false)

@@ -695,7 +695,11 @@ __device__ __forceinline__ void rho_one(const RunDev &rd, const Store &s, long l
                 const int gi = wrap1(base[0] + ii, rd.n[0]), gj = wrap1(base[1] + j, rd.n[1]);
                 const int gk = DIM == 3 ? wrap1(base[2] + k, rd.n[2]) : 0;
                 const double v = qw * wt[0][ii] * wt[1][j] * (DIM == 3 ? wt[2][k] : 1.0);
-                atomicAdd(&rho[gi + (long long)rd.n[0] * (gj + (long long)rd.n[1] * gk)], v);
+                double *dst = &rho[gi + (long long)rd.n[0] * (gj + (long long)rd.n[1] * gk)];
+                if (rd.det)   // deterministic mode: 64-bit fixed point (see to_fixed)
+                    atomicAdd((unsigned long long *)dst, to_fixed(v * rd.rscale));
+                else
+                    atomicAdd(dst, v);
             }
 }
 
@@ -720,6 +724,13 @@ __global__ void fill_kernel(double *p, long long n, double v)
 {
     const long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// deterministic mode: the fixed-point charge density back to FP64, in place
+__global__ void rho_from_fixed_kernel(const RunDev *__restrict__ runs, int run, double *p, long long n)
+{
+    const long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) p[i] = (double)((const long long *)p)[i] * runs[run].rscale_inv;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -782,14 +793,24 @@ hipError_t launch_kinetic(int dims, bool split, const RunDev *runs, int run, int
     DISPATCH_ALL(KIN_BODY)
 }
 
-hipError_t launch_rho(int dims, bool split, const RunDev *runs, int run, int seg_max, int nspill, int ncell,
-                      double *rho, hipStream_t s)
+static hipError_t launch_rho_deposit(int dims, bool split, const RunDev *runs, int run, int seg_max, int nspill,
+                                     double *rho, hipStream_t s)
 {
-    fill_kernel<<<(ncell + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(rho, ncell, 0.0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
 #define RHO_BODY(D, TT) rho_kernel<D, TT><<<seg_max + 1, BLOCK, 0, s>>>(runs, run, nspill, rho)
     DISPATCH_ALL(RHO_BODY)
+}
+
+hipError_t launch_rho(int dims, bool split, bool det, const RunDev *runs, int run, int seg_max, int nspill, int ncell,
+                      double *rho, hipStream_t s)
+{
+    fill_kernel<<<(ncell + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(rho, ncell, 0.0);   // also the integer 0
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_rho_deposit(dims, split, runs, run, seg_max, nspill, rho, s);
+    if (e == hipSuccess && det) {
+        rho_from_fixed_kernel<<<(ncell + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(runs, run, rho, ncell);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 // One thread that waits about `us` microseconds on the device wall clock

@@ -24,6 +24,8 @@
 // Particles parked in the spill store that belong to this patch are pushed
 // here too (by the patch's first segment) and re-enter through the overflow
 // leaver store.  A segment with nothing to push skips all of this.
+#include <type_traits>
+
 #include "launch.h"
 #include "part.h"
 #include "sdmd_dev.h"
@@ -119,6 +121,18 @@ __device__ __forceinline__ void esirkepov_axis_delta(R d0, R D, int ip, R S0[4],
     moved = up || dn;
 }
 
+// One contribution into the LDS tile: an FP64 atomic add, or in the
+// deterministic mode a 64-bit integer add of the contribution in fixed
+// point (js: the run's scale), whose sum does not depend on the order.
+template <bool DET>
+__device__ __forceinline__ void tile_add(double *p, double v, double js)
+{
+    if constexpr (DET)
+        atomicAdd((unsigned long long *)p, to_fixed(v * js));
+    else
+        atomicAdd(p, v);
+}
+
 // Esirkepov deposition of one particle into the LDS tile on an NF-slot
 // frame per axis (NF = 4: the general 4-node sub-frame; NF = 3: no node
 // change on any axis).  The weights factor as outer products: Jx = cx Cx[m]
@@ -126,9 +140,9 @@ __device__ __forceinline__ void esirkepov_axis_delta(R d0, R D, int ip, R S0[4],
 // cz (S0x[m] yf[n] + DSx[m] (S0y[n]/2 + DSy[n]/3)); in 3D component c flows
 // along axis c and the two transverse axes (u, v) carry the time-averaged
 // product S0u (S0v + DSv/2) + DSu (S0v/2 + DSv/3).
-template <int NF, class R>
+template <int NF, bool DET, class R>
 __device__ __forceinline__ void deposit2d(double *Jb, int T0, int TS, const R S0[3][4], const R DS[3][4],
-                                          const R cj[3], R cz, bool mx, bool my)
+                                          const R cj[3], R cz, bool mx, bool my, double js)
 {
     const R third = R(1) / R(3);
     R hf[2][4], qf[2][4], cs[2][3];
@@ -154,26 +168,27 @@ __device__ __forceinline__ void deposit2d(double *Jb, int T0, int TS, const R S0
     for (int n = 0; n < NF; ++n)
 #pragma unroll
         for (int m = 0; m < NF - 1; ++m)
-            if (NF == 3 || ((m < 2 || mx) && (n < 3 || my))) atomicAdd(&Jb[n * T0 + m], (double)(cs[0][m] * hf[1][n]));
+            if (NF == 3 || ((m < 2 || mx) && (n < 3 || my)))
+                tile_add<DET>(&Jb[n * T0 + m], (double)(cs[0][m] * hf[1][n]), js);
 #pragma unroll
     for (int n = 0; n < NF - 1; ++n)
 #pragma unroll
         for (int m = 0; m < NF; ++m)
             if (NF == 3 || ((n < 2 || my) && (m < 3 || mx)))
-                atomicAdd(&Jb[TS + n * T0 + m], (double)(cs[1][n] * hf[0][m]));
+                tile_add<DET>(&Jb[TS + n * T0 + m], (double)(cs[1][n] * hf[0][m]), js);
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
         const R a = cz * S0[0][m], b = cz * DS[0][m];
 #pragma unroll
         for (int n = 0; n < NF; ++n)
             if (NF == 3 || ((m < 3 || mx) && (n < 3 || my)))
-                atomicAdd(&Jb[2 * TS + n * T0 + m], (double)(a * hf[1][n] + b * qf[1][n]));
+                tile_add<DET>(&Jb[2 * TS + n * T0 + m], (double)(a * hf[1][n] + b * qf[1][n]), js);
     }
 }
 
-template <int NF, class R>
+template <int NF, bool DET, class R>
 __device__ __forceinline__ void deposit3d(double *Jb, int T0, int TP, int TS, const R S0[3][4], const R DS[3][4],
-                                          const R cj[3], const bool mv[3])
+                                          const R cj[3], const bool mv[3], double js)
 {
     const R third = R(1) / R(3);
     R hf[3][4], qf[3][4], cs[3][3];
@@ -204,7 +219,7 @@ __device__ __forceinline__ void deposit3d(double *Jb, int T0, int TP, int TS, co
 #pragma unroll
                 for (int m = 0; m < NF - 1; ++m)
                     if (NF == 3 || ((m < 2 || mv[c]) && (i < 3 || mv[u]) && (j < 3 || mv[v])))
-                        atomicAdd(&Jb[c * TS + i * su + j * sv + m * sc], (double)(cs[c][m] * tr));
+                        tile_add<DET>(&Jb[c * TS + i * su + j * sv + m * sc], (double)(cs[c][m] * tr), js);
             }
         }
     }
@@ -223,7 +238,7 @@ __device__ __forceinline__ void deposit3d(double *Jb, int T0, int TP, int TS, co
 // a wavefront's ds_add_f64 takes ~8.6 clocks of a CU's LDS and a
 // ds_add_f32 ~193 (measured, consecutive addresses); contributions are
 // still computed in the particle precision.
-template <int DIM, class T, int PX>
+template <int DIM, class T, int PX, bool DET>
 __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real *__restrict__ win, double *tile,
                                         const int p0[3], const int Prt[3], Part<T> &p, int &err)
 {
@@ -401,17 +416,18 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
     bool still = true;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) still = still && !mv[a];
+    const double js = DET ? rd.jscale : 0.0;
     if constexpr (DIM == 2) {
         const R cz = (T::split ? (R)rd.f_q : (R)rd.q) * p.w * (un[2] * ig);
         if (__all(still))
-            deposit2d<3, R>(Jb, T0, TS, S0, DS, cj, cz, false, false);
+            deposit2d<3, DET, R>(Jb, T0, TS, S0, DS, cj, cz, false, false, js);
         else
-            deposit2d<4, R>(Jb, T0, TS, S0, DS, cj, cz, mv[0], mv[1]);
+            deposit2d<4, DET, R>(Jb, T0, TS, S0, DS, cj, cz, mv[0], mv[1], js);
     } else {
         if (__all(still))
-            deposit3d<3, R>(Jb, T0, TP, TS, S0, DS, cj, mv);
+            deposit3d<3, DET, R>(Jb, T0, TP, TS, S0, DS, cj, mv, js);
         else
-            deposit3d<4, R>(Jb, T0, TP, TS, S0, DS, cj, mv);
+            deposit3d<4, DET, R>(Jb, T0, TP, TS, S0, DS, cj, mv, js);
     }
 
     p.u[0] = un[0];
@@ -441,7 +457,8 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
 template <int DIM, class T>
 constexpr int push_block() { return DIM == 3 ? (T::split ? 1024 : 512) : 256; }
 
-template <int DIM, class T, int PX, int PC>
+// DET: deterministic mode (64-bit fixed-point tiles, see to_fixed)
+template <int DIM, class T, int PX, int PC, bool DET>
 __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunDev *__restrict__ runs,
                                                                  const int2 *__restrict__ items, int par)
 {
@@ -503,8 +520,9 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
         // tile in HBM is cleared only if an earlier step left current in it
         const int dirty = tflag[sg];
         if (dirty) {
-            SDMD_GLOBAL R *dst = gp((R *)rd.tiles) + (long long)sg * 3 * TS;
-            for (int idx = tid; idx < 3 * TS; idx += BLOCK) dst[idx] = R(0);
+            using TE = typename std::conditional<DET, long long, R>::type;   // tile element in HBM
+            SDMD_GLOBAL TE *dst = gp((TE *)rd.tiles) + (long long)sg * 3 * TS;
+            for (int idx = tid; idx < 3 * TS; idx += BLOCK) dst[idx] = TE(0);
         }
         __syncthreads();
         if (tid == 0) {
@@ -566,7 +584,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
         Part<T> pt = nxt;
         if (i + BLOCK < n) load_part<DIM, T>(sst, (uint32_t)(i + BLOCK), nxt);
         int dest = q;
-        if (valid) dest = push_one<DIM, T, PX>(rd, s_win, s_tile, p0, P, pt, err);
+        if (valid) dest = push_one<DIM, T, PX, DET>(rd, s_win, s_tile, p0, P, pt, err);
         const bool st = valid && dest == q;
         const bool lv = valid && dest != q;
         const unsigned long long ms = __ballot(st), ml = __ballot(lv);
@@ -678,7 +696,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
             int dest = q;
             if (mine) {
                 load_part<DIM, T>(rd.sp, s_sl[j], pt);
-                dest = push_one<DIM, T, PX>(rd, s_win, s_tile, p0, P, pt, err);
+                dest = push_one<DIM, T, PX, DET>(rd, s_win, s_tile, p0, P, pt, err);
             }
             const unsigned long long ml = __ballot(mine);
             int lbase = 0;
@@ -706,25 +724,38 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
         if (want > 0) gp(rd.spcnt)[q] = 0;   // consumed; this step's post kernel parks anew
     }
     __syncthreads();
-    // flush the tile in the tile precision (transfer (i) reads it)
-    SDMD_GLOBAL R *dst = gp((R *)rd.tiles) + (long long)sg * 3 * TS;
-    for (int idx = tid; idx < 3 * TS; idx += BLOCK) {
-        const int pl = idx / (T0 * T1), rem = idx - pl * (T0 * T1);   // plane (component and z), node in it
-        dst[idx] = (R)s_tile[pl * TPs + rem];
+    // flush the tile in the tile precision (transfer (i) reads it); the
+    // deterministic mode keeps the 64-bit integers
+    if constexpr (DET) {
+        SDMD_GLOBAL long long *dst = gp((long long *)rd.tiles) + (long long)sg * 3 * TS;
+        const long long *st = (const long long *)s_tile;
+        for (int idx = tid; idx < 3 * TS; idx += BLOCK) {
+            const int pl = idx / (T0 * T1), rem = idx - pl * (T0 * T1);
+            dst[idx] = st[pl * TPs + rem];
+        }
+    } else {
+        SDMD_GLOBAL R *dst = gp((R *)rd.tiles) + (long long)sg * 3 * TS;
+        for (int idx = tid; idx < 3 * TS; idx += BLOCK) {
+            const int pl = idx / (T0 * T1), rem = idx - pl * (T0 * T1);   // plane (component and z), node in it
+            dst[idx] = (R)s_tile[pl * TPs + rem];
+        }
     }
     if (tid == 0) tflag[sg] = 1;
 }
 
-#define PUSH_CASE(D, TT, PXV, PCV)                                                                  \
-    if (dims == D && split == TT::split && px == PXV && pc == PCV) {                                \
-        push_kernel<D, TT, PXV, PCV><<<n_items, push_block<D, TT>(), 0, s>>>(runs, items, par);                   \
-        return hipGetLastError();                                                                   \
+#define PUSH_CASE(D, TT, PXV, PCV)                                                                      \
+    if (dims == D && split == TT::split && px == PXV && pc == PCV) {                                    \
+        if (det)                                                                                        \
+            push_kernel<D, TT, PXV, PCV, true><<<n_items, push_block<D, TT>(), 0, s>>>(runs, items, par);  \
+        else                                                                                            \
+            push_kernel<D, TT, PXV, PCV, false><<<n_items, push_block<D, TT>(), 0, s>>>(runs, items, par); \
+        return hipGetLastError();                                                                       \
     }
 
 // px: exact square/cubic patch edge with a compiled fast path, else 0;
-// pc: LDS sizing class 8 / 16 / 32
-hipError_t launch_push(int dims, bool split, int px, int pc, const RunDev *runs, const int2 *items, int n_items,
-                       int par, hipStream_t s)
+// pc: LDS sizing class 8 / 16 / 32; det: deterministic mode
+hipError_t launch_push(int dims, bool split, int px, int pc, bool det, const RunDev *runs, const int2 *items,
+                       int n_items, int par, hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
     PUSH_CASE(2, F32S, 8, 8)

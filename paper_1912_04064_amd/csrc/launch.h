@@ -10,16 +10,16 @@ namespace sdmd {
 // particles phase (one workgroup per push item = (run, patch))
 // px: exact square/cubic patch edge of a compiled fast path (0 = sizes read
 // from the run descriptor); pc: LDS sizing class 8 / 16 / 32
-hipError_t launch_push(int dims, bool split, int px, int pc, const RunDev *runs, const int2 *items, int n_items,
-                       int par, hipStream_t s);
+hipError_t launch_push(int dims, bool split, int px, int pc, bool det, const RunDev *runs, const int2 *items,
+                       int n_items, int par, hipStream_t s);
 
 // transfer (i) + current filter + Maxwell: items (run, region, tile,
 // first-item-of-run flag); tx: x extent of the tile, from
 // yee_tile_x(dims, region width, filter on); filt: runs with filter passes
 int yee_tile_x(int dims, int rs0, bool filt);
 void yee_tile_shape(int dims, int tx, int shape[3]);
-hipError_t launch_yee(int dims, bool split, int tx, bool filt, const RunDev *runs, const int4 *items, int n_items,
-                      int par, hipStream_t s);
+hipError_t launch_yee(int dims, bool split, int tx, bool filt, bool det, const RunDev *runs, const int4 *items,
+                      int n_items, int par, hipStream_t s);
 
 // spectral (PSATD) field phase of one run: pack, transforms, exact k-space
 // step, inverse transforms, unpack into the other E/B buffer (the field
@@ -66,8 +66,9 @@ hipError_t launch_gauss_max(int ncell, const double *g, const double *g0, const 
                             int nblocks, hipStream_t s);
 hipError_t launch_kinetic(int dims, bool split, const RunDev *runs, int run, int seg_max, int nspill, double *partial,
                           hipStream_t s);
-// charge density (electrons) at primal nodes, global FP64 array (zeroed here)
-hipError_t launch_rho(int dims, bool split, const RunDev *runs, int run, int seg_max, int nspill, int ncell,
+// charge density (electrons) at primal nodes, global FP64 array (zeroed
+// here); det: summed in 64-bit fixed point, then converted in place
+hipError_t launch_rho(int dims, bool split, bool det, const RunDev *runs, int run, int seg_max, int nspill, int ncell,
                       double *rho, hipStream_t s);
 // a short wait on the device that holds the stream while the host enqueues
 hipError_t launch_gate(int us, hipStream_t s);

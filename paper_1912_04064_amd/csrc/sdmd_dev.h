@@ -25,7 +25,8 @@
 //   tiles    : per segment, 3 current components on the nodes its patch's
 //              particles can reach, [segment][component][z][y][x], extent
 //              P+5 per axis, origin = patch origin - 2 (FP32 in the split
-//              form, FP64 in the plain form).
+//              form, FP64 in the plain form; 64-bit fixed point in the
+//              deterministic mode, see to_fixed).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -119,9 +120,12 @@ struct RunDev {
     int ghosts;          // ghost nodes per region
     int filter;          // binomial current filter passes (0 = off)
     int solver;          // 0 Yee, 1 spectral (PSATD)
+    int det;             // deterministic mode: J and rho summed in 64-bit fixed point
     double d[3], L[3];
     double dt, q, m;
     double qmh;          // (q/m) dt/2
+    double jscale, jscale_inv;   // deterministic mode: J contribution -> fixed point, and back
+    double rscale, rscale_inv;   // the same for the charge density
     float f_qmh;
     float f_dtd[3];      // dt / d  (split form displacement in cells per unit velocity)
     float f_cj[3];       // -q d / dt (Esirkepov prefactor, times w)
@@ -183,6 +187,22 @@ __device__ __forceinline__ int wrap1(int i, int n)
 {
     i = i < 0 ? i + n : i;
     return i >= n ? i - n : i;
+}
+
+// Deterministic mode.  A floating-point sum depends on the order of its
+// terms, and the order in which the LDS and global atomics of a deposition
+// land is set by timing.  Integer addition is associative, so each
+// contribution is rounded once to the nearest integer multiple of
+// 1/scale (scale a power of two chosen per run so that no sum of all its
+// particles' contributions can leave the 64-bit range) and summed as a
+// 64-bit integer: the total is then the same whatever the order, the
+// segment split or the decomposition.  v is the contribution times scale,
+// |v| < 2^51: adding 1.5 * 2^52 leaves the integer nearest v in the low
+// bits of the sum's significand.
+__device__ __forceinline__ unsigned long long to_fixed(double v)
+{
+    const double t = v + 6755399441055744.0;
+    return (unsigned long long)(__double_as_longlong(t) - 0x4338000000000000LL);
 }
 
 // quadratic B-spline weights at nodes -1, 0, +1 for offset d in [-1/2, 1/2]

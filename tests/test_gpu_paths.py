@@ -10,8 +10,11 @@ pic_diag's kernel_path -- and compares one step and eight steps with the
 oracle (fields per family, particles by id).  ``test_paths_table`` (CPU)
 checks that the table names every instantiation in the kernel sources.
 
-Bars: FP64 within round-off of the oracle (1e-12 after one step, 1e-10 after
-eight); FP32 split 1e-5 after one step, 1e-4 after eight.
+Each case runs twice, in the plain and in the deterministic mode (the
+kernels' fixed-point instantiations).  Bars: FP64 within round-off of the
+oracle (1e-12 after one step, 1e-10 after eight; one decade more in the
+deterministic mode, whose current is rounded to a quantum of about 1e-14
+of a contribution here); FP32 split 1e-5 after one step, 1e-4 after eight.
 """
 import dataclasses
 import sys
@@ -112,23 +115,24 @@ def _errs(Fg, Fo):
     return out
 
 
+@pytest.mark.parametrize("det", [False, True], ids=["plain", "det"])
 @pytest.mark.parametrize("case", CASES, ids=[c.name for c in CASES])
-def test_kernel_path_against_oracle(case):
-    say(f"case: {case}")
+def test_kernel_path_against_oracle(case, det):
+    say(f"case: {case} deterministic={det}")
     wl = workload(case)
     g, F, P = oracle_state(wl)
     mask = B.F_E | B.F_B | B.F_BH | B.F_J
     res = {}
-    with B.Context([wl], track_ids=True) as ctx:
+    with B.Context([wl], track_ids=True, deterministic=det) as ctx:
         d = ctx.diag(0)
-        assert d["kernel_path"][:3] == [case.push[0], case.push[1], case.yee_tx], d["kernel_path"]
+        assert d["kernel_path"] == [case.push[0], case.push[1], case.yee_tx, int(det)], d["kernel_path"]
         for steps in (1, 7):
             ctx.step(steps)
             Fa = ctx.fields(0, mask)
             res[ctx.diag(0)["step"]] = ({"E": Fa[0:3], "Bm": Fa[3:6], "BH": Fa[6:9], "J": Fa[9:12]},
                                         B.sort_by_id(ctx.particles(0)))
     L = np.array(wl.n, float) * np.array(wl.d)
-    tol = {1: 1e-12, 8: 1e-10} if case.prec == "fp64" else {1: 1e-5, 8: 1e-4}
+    tol = ({1: 1e-11, 8: 1e-9} if det else {1: 1e-12, 8: 1e-10}) if case.prec == "fp64" else {1: 1e-5, 8: 1e-4}
     ptol = 1e-12 if case.prec == "fp64" else 1e-5
     done = 0
     for target in (1, 8):

@@ -75,10 +75,13 @@ def valu_line(insts, launch_ms):
             "frac": rate / VALU_PEAK}
 
 
-def push_traffic(wl_name):
-    """HBM bytes per particle-kernel launch from the committed FETCH_SIZE /
-    WRITE_SIZE counter runs (scaled by a plain copy of known size), or None
-    when the workload differs or the kernel sources changed since then."""
+def push_counters(wl_name, first, last):
+    """Counter figures of the particle kernel (HBM bytes from FETCH_SIZE /
+    WRITE_SIZE scaled by a plain copy of known size; VALU and LDS
+    wavefront-instructions) averaged over its launches of steps
+    [first, last) of the workload, from the committed counter runs
+    (profiles/traffic.json), or None when no run covers that window or the
+    kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -87,22 +90,7 @@ def push_traffic(wl_name):
         return None
     if kernel_source_hash() != rec.get("source_sha"):
         return None
-    return float(rec["bytes_per_launch"])
-
-
-def push_valu(wl_name):
-    """VALU wavefront-instructions per particle-kernel launch, averaged over
-    every launch of a full benchmark run (SQ_INSTS_VALU counter run), or
-    None when the workload differs or the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
-        return None
-    rec = json.load(open(path)).get("push_kernel", {})
-    if rec.get("workload") != {"lwfa": "lwfa2048x256"}.get(wl_name) or "valu_insts_per_launch" not in rec:
-        return None
-    if kernel_source_hash() != rec.get("source_sha"):
-        return None
-    return float(rec["valu_insts_per_launch"])
+    return rec.get("windows", {}).get(f"{first}-{last}")
 
 
 def kernel_source_hash():
@@ -121,33 +109,59 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(wl_name, budget_s=20.0):
-    """The FP64 oracle (single thread) on a bounded sample of the same
-    workload: a horizontal band of the grid with its particles, full steps."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl_name, budget_s=10.0):
+    """The FP64 oracle's SDMD step on a bounded sample of the same workload
+    (a horizontal band of the grid with its particles, full steps), timed
+    twice on the host: one thread (the parity build), and the OpenMP timing
+    build of the same source with dynamic scheduling over patches (the
+    paper's thread model) on the threads OMP_NUM_THREADS allows (all
+    cores when unset).  Both legs compute the same result bit for bit."""
     import oracle as O
     from paper_1912_04064_amd import workloads as WL
     if wl_name.startswith("lwfa"):
         # the plasma band of the run: 256 x 256 cells of plateau + ramp
         wl = WL.lwfa_2d(n=(512, 256), vac_end=64, ramp=256, x0=68.0)
-        sample = "lwfa band 512x256 cells (ramp+plateau, 16 ppc)"
+        sample = "lwfa band 512x256 cells (ramp+plateau, 16 ppc, 16x16 patches, 4 regions)"
     elif wl_name.startswith("cyl"):
         wl = WL.cylinder_3d(n=(32, 32, 32), radius=8.0)
-        sample = "cylinder 32^3 cells (8 ppc + 16x cylinder)"
+        sample = "cylinder 32^3 cells (8 ppc + 16x cylinder, 8^3 patches)"
     else:
         wl = workload(wl_name)
         sample = wl.name
     from tests.helpers import oracle_state
-    g, F, P = oracle_state(wl)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        O.step_sdsd(g, F, P)
-        steps += 1
-        if time.perf_counter() - t0 > budget_s or steps >= 50:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": P.n * steps / dt, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample}: {P.n} particles x {steps} steps in {dt:.1f} s"}
+    nproc = os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or nproc
+
+    def leg(step):
+        g, F, P = oracle_state(wl)
+        step(g, F, P)                      # first step: page-in, not timed
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            step(g, F, P)
+            steps += 1
+            if time.perf_counter() - t0 > budget_s or steps >= 50:
+                break
+        dt = time.perf_counter() - t0
+        return P.n * steps / dt, steps, dt, P.n
+
+    v1, s1, d1, n = leg(lambda g, F, P: O.step_sdmd(g, F, P))
+    vn, sn, dn, _ = leg(lambda g, F, P: O.step_sdmd_threads(g, F, P, threads))
+    return {"value": vn, "unit": "particle-pushes/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample}: {n} particles x {sn} steps in {dn:.1f} s on {threads} threads",
+            "single_core": {"value": v1, "cores": 1, "sample": f"{n} particles x {s1} steps in {d1:.1f} s"},
+            "nproc": nproc, "cpu_model": cpu_model(),
+            "schedule": "OpenMP dynamic over patches (SDMD step of the oracle)"}
 
 
 def bench_scan(args):
@@ -294,6 +308,8 @@ def main():
     ap.add_argument("--phase-samples", type=int, default=0,
                     help="steps of the timed trajectory replayed with per-kernel events (0 = all)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-full-run", action="store_true",
+                    help="skip the workload's whole trajectory (its configured step count)")
     ap.add_argument("--runs", type=int, default=256, help="runs of the batched scan (--workload scan)")
     ap.add_argument("--serve", type=float, default=0.0, help="served stream: arrival rate in runs/s")
     ap.add_argument("--window", type=float, default=10.0, help="served stream: arrival window in s")
@@ -354,22 +370,34 @@ def main():
 
     d = ctx.diag(0)
     ctx.close()
-    # Dominant kernel: the same trajectory replayed from the same input, the
-    # kernels of every step separated by HIP events on the library's stream
-    # and enqueued back to back (one synchronisation at the end), so the
-    # averages cover all launches of the timed steps, as a kernel trace of
-    # the run does.
-    nph = args.steps if args.phase_samples <= 0 else min(args.steps, args.phase_samples)
-    ctx = B.Context([wl], graph=not args.no_graph)
-    ctx.step(args.warmup)
-    ctx.time_phases(nph)
-    t = ctx.diag(0)["t_ms"]
-    push_avg, yee_avg, post_avg = float(t[0]), float(t[1]), float(t[2])
+    first, last = args.warmup, args.warmup + args.steps
     pb = particle_bytes(wl)
     alg_push = N * pb + ncell * 48          # particles + the FP64 E, Bm window (transfer ii)
+
+    def replay(warm, n):
+        """Per-phase kernel times over steps [warm, warm + n) of the same
+        trajectory, replayed from the same input with HIP events between the
+        phases on the library's stream (kernels back to back)."""
+        c = B.Context([wl], graph=not args.no_graph)
+        c.step(warm)
+        c.time_phases(n)
+        t = c.diag(0)["t_ms"]
+        c.close()
+        return float(t[0]), float(t[1]), float(t[2]), float(t[3])
+
+    # the dominant kernel over the timed window (the same steps)
+    nph = args.steps if args.phase_samples <= 0 else min(args.steps, args.phase_samples)
+    push_avg, yee_avg, post_avg, rel_avg = replay(args.warmup, nph)
     achieved = alg_push / (push_avg * 1e-3) / 1e9
     step_bytes = N * pb + ncell * 216
-    ctx.close()
+    ctr = push_counters(args.workload, first, last) if nph == args.steps else None
+
+    # the whole step against HBM: the survey's per-push bytes (52 B of
+    # split-form particle traffic with a 4-byte cell index + 216 B of FP64
+    # field traffic per cell, shared by the particles per cell)
+    ppc = N / ncell
+    bpp_step = (52.0 if wl.precision == "fp32s" else 88.0) + 216.0 / ppc
+    step_roof = HBM_PEAK_GBS * 1e9 / bpp_step
 
     out = {
         "metric": "particle-pushes/s (full SDMD step)",
@@ -378,6 +406,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "timed_steps": [first, last],
         "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
@@ -386,16 +415,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "cells": list(wl.n), "particles": N, "patch": list(d["patch"][:wl.dims]),
                    "regions": list(wl.nreg), "precision": wl.precision, "solver": wl.solver, "filter": wl.filter,
-                   "graph": not args.no_graph},
+                   "graph": not args.no_graph, "run_steps": wl.steps},
         "step_hbm_GBps_algorithmic": step_bytes / (ms * 1e-3) / 1e9,
-        "phase_ms": {"particles": push_avg, "reduce_maxwell": yee_avg, "sync_rebin": post_avg},
+        "step_roofline": {"bytes_per_push": bpp_step, "roofline": step_roof, "unit": "particle-pushes/s",
+                          "frac": value / step_roof},
+        "phase_ms": {"particles": push_avg, "reduce_maxwell": yee_avg, "sync_rebin": post_avg,
+                     "relayout": rel_avg, "steps": [first, first + nph]},
         "roofline": {"bound": "hbm", "kernel": "push_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": push_traffic(args.workload),
-                     "bytes_per_launch": alg_push},
-        # the particle kernel's VALU issue rate: the chip issues one
-        # wavefront VALU instruction per CU per clock when packed FP32 is
-        # not used (256 CUs x 2.4 GHz); counts from the committed counter run
-        "valu": valu_line(push_valu(args.workload), push_avg),
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": ctr["bytes_per_launch"] if ctr else None, "bytes_per_launch": alg_push,
+                     "steps": [first, first + nph]},
+        # the particle kernel's VALU issue rate over the same window: one
+        # wavefront VALU instruction per CU per clock when packed FP32 is not
+        # used (256 CUs x 2.4 GHz); counts from the committed counter run of
+        # this window, null when there is none
+        "valu": valu_line(ctr["valu_insts_per_launch"] if ctr else None, push_avg),
         "relayouts": d["n_relayout"],
         # total energy (fields + electrons) over the timed steps, and the
         # Gauss-law residual div_h E - rho against the initial state
@@ -403,6 +437,30 @@ def main():
                    "rel_change": (d["U_E"] + d["U_B"] + d["K"]) / (d0["U_E"] + d0["U_B"] + d0["K"]) - 1.0,
                    "gauss_residual": d["gauss_residual"]},
     }
+    if not args.no_full_run and wl.steps > 0:
+        # the workload's whole trajectory (its configured step count, the
+        # laser entering the plasma and the wake forming): the same figures
+        # over every step, timed the same way
+        c = B.Context([wl], graph=not args.no_graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.step(wl.steps)
+        torch.cuda.synchronize()
+        dtf = time.perf_counter() - t0
+        df = c.diag(0)
+        c.close()
+        fp, fy, fq, fr = replay(0, wl.steps)
+        fv = N * wl.steps / dtf
+        fctr = push_counters(args.workload, 0, wl.steps)
+        out["full_run"] = {
+            "steps": [0, wl.steps], "value": fv, "ms_per_step": dtf * 1e3 / wl.steps,
+            "step_roofline_frac": fv / step_roof,
+            "phase_ms": {"particles": fp, "reduce_maxwell": fy, "sync_rebin": fq, "relayout": fr},
+            "push_kernel": {"achieved": alg_push / (fp * 1e-3) / 1e9, "frac": alg_push / (fp * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                            "traffic": fctr["bytes_per_launch"] if fctr else None,
+                            "valu": valu_line(fctr["valu_insts_per_launch"] if fctr else None, fp)},
+            "relayouts": df["n_relayout"], "gauss_residual": df["gauss_residual"]}
+        print(f"[bench] full run {wl.steps} steps: {dtf * 1e3 / wl.steps:.4f} ms/step", file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)

@@ -30,13 +30,20 @@ EX, EY, EZ, BX, BY, BZ, BMX, BMY, BMZ, JX, JY, JZ = range(12)
 NCOMP = 12
 
 
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+_FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (FP64, -O2, no fast-math, no contraction)."""
+    """Compile the oracle with gcc (FP64, -O2, no fast-math, no contraction):
+    the parity build (single thread), and a timing build of the same source
+    with OpenMP, which only the CPU-baseline leg of the benchmark loads."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-               "-o", _LIB + ".tmp", _SRC, "-lm"]
-        subprocess.check_call(cmd)
+        subprocess.check_call(["gcc", *_FLAGS, "-o", _LIB + ".tmp", _SRC, "-lm"])
         os.replace(_LIB + ".tmp", _LIB)
+    if force or not os.path.exists(_LIB_OMP):
+        subprocess.check_call(["gcc", *_FLAGS, "-fopenmp", "-o", _LIB_OMP + ".tmp", _SRC, "-lm"])
+        os.replace(_LIB_OMP + ".tmp", _LIB_OMP)
     return _LIB
 
 
@@ -236,6 +243,30 @@ def push_only(g: Grid, F: np.ndarray, P: Particles):
 def step_sdsd(g: Grid, F: np.ndarray, P: Particles) -> float:
     pc = P.c()
     return lib().oracle_step_sdsd(C.byref(g.c), _dp(F), C.byref(pc))
+
+
+_lib_omp = None
+
+
+def step_sdmd_threads(g: Grid, F: np.ndarray, P: Particles, threads: int) -> int:
+    """One SDMD step from the OpenMP timing build with `threads` threads over
+    the patches (dynamic schedule).  Same arithmetic, same result bit for bit
+    as step_sdmd; used only to time the CPU baseline."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_LIB_OMP) or os.path.getmtime(_LIB_OMP) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB_OMP)
+        L.oracle_step_sdmd.restype = C.c_int
+        L.oracle_step_sdmd.argtypes = [C.POINTER(OCfg), C.POINTER(C.c_double), C.POINTER(OParts), C.c_int32]
+        L.omp_set_num_threads.argtypes = [C.c_int]
+        _lib_omp = L
+    _lib_omp.omp_set_num_threads(int(threads))
+    pc = P.c()
+    rc = _lib_omp.oracle_step_sdmd(C.byref(g.c), _dp(F), C.byref(pc), 0)
+    if rc != 0:
+        raise ValueError("invalid decomposition")
+    return rc
 
 
 def step_sdmd(g: Grid, F: np.ndarray, P: Particles | None, fields_only: bool = False) -> int:

@@ -704,6 +704,13 @@ int oracle_step_sdmd(const ocfg* c, double* F, oparts* P, int32_t fields_only)
         int64_t tsz = tA[0] * tA[1] * tA[2], wsz = wA[0] * wA[1] * wA[2];
         double* tiles = (double*)calloc((size_t)3 * tsz * nP, sizeof(double));
         double dummy = 0.0;
+        /* Patches are independent here: each reads the regions, writes its */
+        /* own tile and updates its own particles.  The timing build of the  */
+        /* CPU baseline takes them in parallel with dynamic scheduling (the  */
+        /* paper's thread model, section 4); the parity build is compiled   */
+        /* without OpenMP and ignores the pragma.  Either way the result is  */
+        /* the same bit for bit: step 4 sums the tiles in patch order.       */
+#pragma omp parallel for schedule(dynamic)
         for (int64_t q = 0; q < nP; ++q) {
             int64_t pq[3] = {q % np[0], (q / np[0]) % np[1], q / (np[0] * np[1])};
             int64_t p0[3];

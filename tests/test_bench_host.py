@@ -1,7 +1,8 @@
 """Host logic of bench.py: the stored counter figures (HBM bytes, VALU
-instructions per particle-kernel launch) are reported only while the
-particle-kernel sources they were measured on are unchanged, and the
-`--gpus` contract (one GPU only)."""
+instructions per particle-kernel launch) are reported only for the step
+window they were averaged over and while the particle-kernel sources they
+were measured on are unchanged; the `--gpus` contract (one GPU only); the
+two CPU-baseline legs."""
 import json
 import os
 import subprocess
@@ -14,23 +15,25 @@ import bench
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def test_counter_figures_follow_the_source_hash(tmp_path, monkeypatch):
+def test_counter_figures_follow_the_window_and_the_source_hash(tmp_path, monkeypatch):
+    """Counter figures are reported for the exact step window they were
+    averaged over, and only while the kernel sources are unchanged."""
+    fig = {"bytes_per_launch": 2.0e8, "valu_insts_per_launch": 3.0e7}
     rec = {"push_kernel": {"workload": "lwfa2048x256", "source_sha": bench.kernel_source_hash(),
-                           "bytes_per_launch": 2.0e8, "valu_insts_per_launch": 3.0e7}}
+                           "windows": {"5-25": fig}}}
     prof = tmp_path / "profiles"
     prof.mkdir()
     (prof / "traffic.json").write_text(json.dumps(rec))
     (tmp_path / "paper_1912_04064_amd").symlink_to(os.path.join(ROOT, "paper_1912_04064_amd"))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.push_traffic("lwfa") == 2.0e8
-    assert bench.push_valu("lwfa") == 3.0e7
-    # another workload, or sources changed since the counters: no figure
-    assert bench.push_traffic("thermal2k") is None
-    assert bench.push_valu("cyl3d") is None
+    assert bench.push_counters("lwfa", 5, 25) == fig
+    # another window, another workload, or sources changed since: no figure
+    assert bench.push_counters("lwfa", 0, 1000) is None
+    assert bench.push_counters("lwfa", 20, 40) is None
+    assert bench.push_counters("thermal2k", 5, 25) is None
     rec["push_kernel"]["source_sha"] = "0" * 16
     (prof / "traffic.json").write_text(json.dumps(rec))
-    assert bench.push_traffic("lwfa") is None
-    assert bench.push_valu("lwfa") is None
+    assert bench.push_counters("lwfa", 5, 25) is None
 
 
 def test_valu_line():
@@ -61,3 +64,16 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_cpu_model_and_baseline_fields(monkeypatch):
+    """The CPU baseline reports both legs, the threads it used, nproc and the
+    CPU model (a tiny workload stands in for the LWFA band here)."""
+    from paper_1912_04064_amd import workloads as WL
+    small = WL.thermal_2d(n=(32, 32), ppc=2, patch=(8, 8), nreg=(2, 1))
+    monkeypatch.setattr(bench, "workload", lambda name: small)
+    monkeypatch.setenv("OMP_NUM_THREADS", "2")
+    out = bench.cpu_baseline("thermal_small", budget_s=0.2)
+    assert out["cores"] == 2 and out["single_core"]["cores"] == 1
+    assert out["value"] > 0 and out["single_core"]["value"] > 0
+    assert out["nproc"] >= 1 and isinstance(out["cpu_model"], str) and out["kind"] == "oracle"

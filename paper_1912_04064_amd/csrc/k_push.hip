@@ -133,17 +133,31 @@ __device__ __forceinline__ void tile_add(double *p, double v, double js)
         atomicAdd(p, v);
 }
 
-// Esirkepov deposition of one particle into the LDS tile on an NF-slot
-// frame per axis (NF = 4: the general 4-node sub-frame; NF = 3: no node
-// change on any axis).  The weights factor as outer products: Jx = cx Cx[m]
-// yf[n] with Cx the running sum of DSx and yf = S0y + DSy/2; Jz (2D) =
-// cz (S0x[m] yf[n] + DSx[m] (S0y[n]/2 + DSy[n]/3)); in 3D component c flows
-// along axis c and the two transverse axes (u, v) carry the time-averaged
-// product S0u (S0v + DSv/2) + DSu (S0v/2 + DSv/3).
-template <int NF, bool DET, class R>
+// Esirkepov deposition of one particle into the LDS tile.  On the 4-slot
+// frame of an axis, a particle that keeps its nearest primal node has zeros
+// in the last slot (and its running sum ends one slot early), so every
+// particle that keeps its node on all axes deposits only on the first three
+// slots of every axis -- the core, 21 adds in 2D and 54 in 3D -- and a
+// particle that changes node along some axis also needs the rest of the
+// 4-slot frame (19 more adds in 2D, 90 in 3D).  PART selects the core or the
+// rest; in the rest, the slots that are structurally zero for a lane (an
+// axis along which it kept its node) are masked lane by lane, and `on`
+// switches a lane off altogether.  A masked lane takes no part in the
+// same-address collisions that serialise an LDS add, and an add no lane
+// needs is branched over.
+//
+// The weights factor as outer products: Jx = cx Cx[m] yf[n] with Cx the
+// running sum of DSx and yf = S0y + DSy/2; Jz (2D) = cz (S0x[m] yf[n] +
+// DSx[m] (S0y[n]/2 + DSy[n]/3)); in 3D component c flows along axis c and
+// the two transverse axes (u, v) carry the time-averaged product
+// S0u (S0v + DSv/2) + DSu (S0v/2 + DSv/3).
+enum { DEP_CORE = 0, DEP_REST = 1 };
+
+template <int PART, bool DET, class R>
 __device__ __forceinline__ void deposit2d(double *Jb, int T0, int TS, const R S0[3][4], const R DS[3][4],
-                                          const R cj[3], R cz, bool mx, bool my, double js)
+                                          const R cj[3], R cz, bool mx, bool my, bool on, double js)
 {
+    constexpr int NF = PART == DEP_CORE ? 3 : 4;
     const R third = R(1) / R(3);
     R hf[2][4], qf[2][4], cs[2][3];
 #pragma unroll
@@ -159,37 +173,36 @@ __device__ __forceinline__ void deposit2d(double *Jb, int T0, int TS, const R S0
             }
         }
     }
-    // In the 4-slot frame, a lane that kept its node on an axis holds zeros
-    // in that axis's last slot (and its running sum ends one slot early):
-    // those adds are masked lane by lane.  A masked lane takes no part in
-    // the same-address collisions that serialise an LDS add, and an add no
-    // lane needs is branched over.
+    // PART == DEP_CORE: NF = 3, every slot is a core slot; DEP_REST: the
+    // slots outside the core that the lane needs
+    auto need = [&](bool core, bool cond) { return PART == DEP_CORE || (!core && on && cond); };
 #pragma unroll
     for (int n = 0; n < NF; ++n)
 #pragma unroll
         for (int m = 0; m < NF - 1; ++m)
-            if (NF == 3 || ((m < 2 || mx) && (n < 3 || my)))
+            if (need(m < 2 && n < 3, (m < 2 || mx) && (n < 3 || my)))
                 tile_add<DET>(&Jb[n * T0 + m], (double)(cs[0][m] * hf[1][n]), js);
 #pragma unroll
     for (int n = 0; n < NF - 1; ++n)
 #pragma unroll
         for (int m = 0; m < NF; ++m)
-            if (NF == 3 || ((n < 2 || my) && (m < 3 || mx)))
+            if (need(n < 2 && m < 3, (n < 2 || my) && (m < 3 || mx)))
                 tile_add<DET>(&Jb[TS + n * T0 + m], (double)(cs[1][n] * hf[0][m]), js);
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
         const R a = cz * S0[0][m], b = cz * DS[0][m];
 #pragma unroll
         for (int n = 0; n < NF; ++n)
-            if (NF == 3 || ((m < 3 || mx) && (n < 3 || my)))
+            if (need(m < 3 && n < 3, (m < 3 || mx) && (n < 3 || my)))
                 tile_add<DET>(&Jb[2 * TS + n * T0 + m], (double)(a * hf[1][n] + b * qf[1][n]), js);
     }
 }
 
-template <int NF, bool DET, class R>
+template <int PART, bool DET, class R>
 __device__ __forceinline__ void deposit3d(double *Jb, int T0, int TP, int TS, const R S0[3][4], const R DS[3][4],
-                                          const R cj[3], const bool mv[3], double js)
+                                          const R cj[3], const bool mv[3], bool on, double js)
 {
+    constexpr int NF = PART == DEP_CORE ? 3 : 4;
     const R third = R(1) / R(3);
     R hf[3][4], qf[3][4], cs[3][3];
 #pragma unroll
@@ -217,11 +230,95 @@ __device__ __forceinline__ void deposit3d(double *Jb, int T0, int TP, int TS, co
             for (int j = 0; j < NF; ++j) {
                 const R tr = S0[u][i] * hf[v][j] + DS[u][i] * qf[v][j];
 #pragma unroll
-                for (int m = 0; m < NF - 1; ++m)
-                    if (NF == 3 || ((m < 2 || mv[c]) && (i < 3 || mv[u]) && (j < 3 || mv[v])))
+                for (int m = 0; m < NF - 1; ++m) {
+                    const bool core = m < 2 && i < 3 && j < 3;
+                    if (PART == DEP_CORE ||
+                        (!core && on && (m < 2 || mv[c]) && (i < 3 || mv[u]) && (j < 3 || mv[v])))
                         tile_add<DET>(&Jb[c * TS + i * su + j * sv + m * sc], (double)(cs[c][m] * tr), js);
+                }
             }
         }
+    }
+}
+
+// Particles that change their nearest primal node (the movers) need the
+// rest of the 4-slot frame besides the core.  Depositing it inline costs a
+// wavefront the full set of adds as soon as one of its 64 lanes moved, and
+// in a warm plasma almost every wavefront holds a mover while few lanes do.
+// So a mover leaves what its rest needs in a per-workgroup queue in LDS
+// (the old offset, the second argument of the frame function and the
+// nearest node per axis, the current prefactors), and the queue is drained
+// once per segment by full wavefronts, one mover per lane.  Recomputing the
+// frame from the same inputs with the same code gives the same values the
+// core was deposited from.  Movers that find the queue full deposit their
+// rest inline.  Queue capacity per workgroup: what the LDS left by the
+// window and tile allows without lowering the kernel's occupancy.
+//
+// The deterministic mode deposits every mover's rest inline (capacity 0):
+// which movers find the queue full depends on timing, and the compiler may
+// round the frame arithmetic of the inline and the drained copy
+// differently, so a particle's contribution must not depend on the path.
+template <int DIM, class T, int PC, bool DET>
+__host__ __device__ constexpr int mover_cap()
+{
+    return DET ? 0 : DIM == 3 ? (T::split ? 1024 : 256) : (T::split ? (PC == 8 ? 512 : PC == 16 ? 224 : 256) : 256);
+}
+// queue fields (arrays of mover_cap entries): per axis the old offset, the
+// frame function's second argument and the current prefactor, then (2D) cz
+template <int DIM>
+__host__ __device__ constexpr int mover_fields()
+{
+    return 3 * DIM + (DIM == 2 ? 1 : 0);
+}
+
+// Esirkepov frame of one axis from the recorded arguments (split form:
+// displacement in cells; FP64 form: new position relative to the node)
+template <class T, class R>
+__device__ __forceinline__ void frame_axis(R d0, R a1, int ip, R S0[4], R DS[4], int &t0, bool &moved)
+{
+    if constexpr (T::split)
+        esirkepov_axis_delta<R>(d0, a1, ip, S0, DS, t0, moved);
+    else
+        esirkepov_axis<R>(d0, a1, ip, S0, DS, t0, moved);
+}
+
+// The rest of a mover's frame from its record: per axis the old offset d0,
+// the frame function's second argument a1 and the nearest node (packed 8
+// bits per axis in ipk), the current prefactors cj and (2D) cz.  `on`
+// switches the lane off.
+template <int DIM, class T, bool DET>
+__device__ __forceinline__ void deposit_rest(const typename T::real d0[3], const typename T::real a1[3], int ipk,
+                                             const typename T::real cj[3], typename T::real cz, bool on,
+                                             double *tile, int T0, int TP, int TS, double js)
+{
+    using R = typename T::real;
+    R S0[3][4], DS[3][4];
+    int t0[3] = {0, 0, 0};
+    bool mv[3] = {false, false, false};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) frame_axis<T, R>(d0[a], a1[a], (ipk >> (8 * a)) & 255, S0[a], DS[a], t0[a], mv[a]);
+    double *Jb = tile + (DIM == 3 ? t0[2] * TP + t0[1] * T0 + t0[0] : t0[1] * T0 + t0[0]);
+    if constexpr (DIM == 2)
+        deposit2d<DEP_REST, DET, R>(Jb, T0, TS, S0, DS, cj, cz, mv[0], mv[1], on, js);
+    else
+        deposit3d<DEP_REST, DET, R>(Jb, T0, TP, TS, S0, DS, cj, mv, on, js);
+}
+
+// drain the mover queue: the rest of each queued mover's frame
+template <int DIM, class T, int QC, bool DET, int NT>
+__device__ __forceinline__ void drain_movers(const typename T::real *q, const int *qi, int nq, double *tile, int T0,
+                                             int TP, int TS, double js)
+{
+    using R = typename T::real;
+    for (int e = threadIdx.x; e < nq; e += NT) {
+        R d0[3] = {R(0), R(0), R(0)}, a1[3] = {R(0), R(0), R(0)}, cj[3] = {R(0), R(0), R(0)};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            d0[a] = q[a * QC + e];
+            a1[a] = q[(DIM + a) * QC + e];
+            cj[a] = q[(2 * DIM + a) * QC + e];
+        }
+        deposit_rest<DIM, T, DET>(d0, a1, qi[e], cj, DIM == 2 ? q[6 * QC + e] : R(0), true, tile, T0, TP, TS, js);
     }
 }
 
@@ -238,9 +335,11 @@ __device__ __forceinline__ void deposit3d(double *Jb, int T0, int TP, int TS, co
 // a wavefront's ds_add_f64 takes ~8.6 clocks of a CU's LDS and a
 // ds_add_f32 ~193 (measured, consecutive addresses); contributions are
 // still computed in the particle precision.
-template <int DIM, class T, int PX, bool DET>
+// q, qi, qn: the workgroup's mover queue (QC entries) and its counter.
+template <int DIM, class T, int PX, bool DET, int QC>
 __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real *__restrict__ win, double *tile,
-                                        const int p0[3], const int Prt[3], Part<T> &p, int &err)
+                                        const int p0[3], const int Prt[3], Part<T> &p, int &err,
+                                        typename T::real *q, int *qi, int *qn)
 {
     using R = typename T::real;
     const int P0 = PX ? PX : Prt[0], P1 = PX ? PX : Prt[1], P2 = DIM == 3 ? (PX ? PX : Prt[2]) : 1;
@@ -360,6 +459,7 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
 
     // ---- move, new cell, Esirkepov frames
     R S0[3][4], DS[3][4];
+    R fa[3] = {R(0), R(0), R(0)};          // second argument of each axis's frame function
     int t0[3] = {0, 0, 0};
     bool mv[3] = {false, false, false};   // nearest primal node changed on that axis
     int gcell[3] = {0, 0, 0};   // new global cell
@@ -372,7 +472,8 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
                 delta = R(0);
             }
             const R xn = p.pos[a] + delta;
-            esirkepov_axis_delta<R>(dp[a], delta, ip[a], S0[a], DS[a], t0[a], mv[a]);
+            fa[a] = delta;
+            frame_axis<T, R>(dp[a], delta, ip[a], S0[a], DS[a], t0[a], mv[a]);
             const R f = floor(xn);
             int sh = (int)f;
             R xi2 = xn - f;
@@ -391,7 +492,8 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
                 xn = (double)p.pos[a];
                 X1 = X0[a];
             }
-            esirkepov_axis<R>(dp[a], (R)(X1 - (double)ipg[a]), ip[a], S0[a], DS[a], t0[a], mv[a]);
+            fa[a] = (R)(X1 - (double)ipg[a]);
+            frame_axis<T, R>(dp[a], fa[a], ip[a], S0[a], DS[a], t0[a], mv[a]);
             const double L = rd.L[a];
             if (xn >= L) xn -= L;
             if (xn < 0.0) xn += L;
@@ -408,26 +510,44 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
 #pragma unroll
     for (int a = 0; a < DIM; ++a) cj[a] = (T::split ? (R)rd.f_cj[a] : (R)(-rd.q * rd.d[a] / rd.dt)) * p.w;
     double *Jb = tile + (DIM == 3 ? t0[2] * TP + t0[1] * T0 + t0[0] : t0[1] * T0 + t0[0]);
-    // When no particle of the wavefront changes its nearest primal node, the
-    // last slot of every frame holds zeros (S0, DS) and the running sums end
-    // at zero one slot earlier, so only a 3-slot frame is deposited: 21 LDS
-    // adds instead of 40 in 2D, 54 instead of 144 in 3D.  The branch is
-    // uniform over the wavefront.
-    bool still = true;
+    // the core of the frame now; the rest, for movers only, through the queue
+    bool mover = false;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) still = still && !mv[a];
+    for (int a = 0; a < DIM; ++a) mover = mover || mv[a];
     const double js = DET ? rd.jscale : 0.0;
-    if constexpr (DIM == 2) {
-        const R cz = (T::split ? (R)rd.f_q : (R)rd.q) * p.w * (un[2] * ig);
-        if (__all(still))
-            deposit2d<3, DET, R>(Jb, T0, TS, S0, DS, cj, cz, false, false, js);
-        else
-            deposit2d<4, DET, R>(Jb, T0, TS, S0, DS, cj, cz, mv[0], mv[1], js);
-    } else {
-        if (__all(still))
-            deposit3d<3, DET, R>(Jb, T0, TP, TS, S0, DS, cj, mv, js);
-        else
-            deposit3d<4, DET, R>(Jb, T0, TP, TS, S0, DS, cj, mv, js);
+    const R cz = DIM == 2 ? (T::split ? (R)rd.f_q : (R)rd.q) * p.w * (un[2] * ig) : R(0);
+    if constexpr (DIM == 2)
+        deposit2d<DEP_CORE, DET, R>(Jb, T0, TS, S0, DS, cj, cz, false, false, true, js);
+    else
+        deposit3d<DEP_CORE, DET, R>(Jb, T0, TP, TS, S0, DS, cj, mv, true, js);
+    const unsigned long long mm = __ballot(mover);
+    if (mm) {
+        // one queue claim per wavefront, by its first active lane
+        const int lane = threadIdx.x & 63;
+        int base = QC;
+        if (QC > 0) {
+            const unsigned long long act = __ballot(1);
+            if (lane == __builtin_ctzll(act)) base = atomicAdd(qn, __popcll(mm));
+            base = __builtin_amdgcn_readfirstlane(base);
+        }
+        const int slot = base + __popcll(mm & ((1ull << lane) - 1ull));
+        const bool queued = mover && slot < QC;
+        int ipk = 0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) ipk |= ip[a] << (8 * a);
+        if (queued) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                q[a * QC + slot] = dp[a];
+                q[(DIM + a) * QC + slot] = fa[a];
+                q[(2 * DIM + a) * QC + slot] = cj[a];
+            }
+            if constexpr (DIM == 2) q[6 * QC + slot] = cz;
+            qi[slot] = ipk;
+        }
+        // the queue is full: the rest inline, from the same record
+        const bool now = mover && !queued;
+        if (__any(now)) deposit_rest<DIM, T, DET>(dp, fa, ipk, cj, cz, now, tile, T0, TP, TS, js);
     }
 
     p.u[0] = un[0];
@@ -475,6 +595,10 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     __shared__ int s_hole[BLOCK];
     __shared__ int s_sl[SPC];                          // this patch's parked particles found in a round
     __shared__ int s_ns;
+    constexpr int QC = mover_cap<DIM, T, PC, DET>();
+    __shared__ R s_q[mover_fields<DIM>() * (QC > 0 ? QC : 1)];   // mover queue (see mover_cap)
+    __shared__ int s_qi[QC > 0 ? QC : 1];
+    __shared__ int s_qn;
 
     // Work item l of a run runs on XCD l % 8 (workgroups are dealt to the
     // 8 XCDs in turn, and every run's items start at a multiple of 8).  The
@@ -558,7 +682,10 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
             if (wd[u] >= 0) s_win[wd[u]] = (R)wv[u];
     }
     for (int idx = tid; idx < 3 * TSs; idx += BLOCK) s_tile[idx] = 0.0;
-    if (tid == 0) s_left = 0;
+    if (tid == 0) {
+        s_left = 0;
+        s_qn = 0;
+    }
     __syncthreads();
 
     int err = 0;
@@ -584,7 +711,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
         Part<T> pt = nxt;
         if (i + BLOCK < n) load_part<DIM, T>(sst, (uint32_t)(i + BLOCK), nxt);
         int dest = q;
-        if (valid) dest = push_one<DIM, T, PX, DET>(rd, s_win, s_tile, p0, P, pt, err);
+        if (valid) dest = push_one<DIM, T, PX, DET, QC>(rd, s_win, s_tile, p0, P, pt, err, s_q, s_qi, &s_qn);
         const bool st = valid && dest == q;
         const bool lv = valid && dest != q;
         const unsigned long long ms = __ballot(st), ml = __ballot(lv);
@@ -696,7 +823,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
             int dest = q;
             if (mine) {
                 load_part<DIM, T>(rd.sp, s_sl[j], pt);
-                dest = push_one<DIM, T, PX, DET>(rd, s_win, s_tile, p0, P, pt, err);
+                dest = push_one<DIM, T, PX, DET, QC>(rd, s_win, s_tile, p0, P, pt, err, s_q, s_qi, &s_qn);
             }
             const unsigned long long ml = __ballot(mine);
             int lbase = 0;
@@ -723,7 +850,12 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
         gp(rd.nlv)[sg] = left;
         if (want > 0) gp(rd.spcnt)[q] = 0;   // consumed; this step's post kernel parks anew
     }
-    __syncthreads();
+    __syncthreads();   // every push of the segment is done: the queue is complete
+    // the rest of the movers' frames, from the queue
+    if constexpr (QC > 0) {
+        drain_movers<DIM, T, QC, DET, BLOCK>(s_q, s_qi, min(s_qn, QC), s_tile, T0, TPs, TSs, DET ? rd.jscale : 0.0);
+        __syncthreads();
+    }
     // flush the tile in the tile precision (transfer (i) reads it); the
     // deterministic mode keeps the 64-bit integers
     if constexpr (DET) {

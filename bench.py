@@ -164,64 +164,139 @@ def cpu_baseline(wl_name, budget_s=10.0):
             "schedule": "OpenMP dynamic over patches (SDMD step of the oracle)"}
 
 
+def _family_rel(a, b):
+    """relative L2 difference of a from b per field family (E, Bm, J)"""
+    out = {}
+    for k, sl in (("E", slice(0, 3)), ("Bm", slice(3, 6)), ("J", slice(6, 9))):
+        nb = float(np.linalg.norm(b[sl]))
+        out[k] = float(np.linalg.norm(a[sl] - b[sl]) / nb) if nb > 0 else float(np.abs(a[sl]).max())
+    return out
+
+
 def bench_scan(args):
     """Batched parameter scan: independent 2D3V runs stepped together (one
-    launch per phase for all runs, two-step hipGraph replay); patch size from
-    the autotuner.  Value = particle pushes/s summed over the runs."""
+    launch per phase for all runs, two-step hipGraph replay); patch edge,
+    segment capacity and field tile width from the autotuner.  Value =
+    particle pushes/s summed over the runs.  The roofline object prices the
+    particle phase (its algorithmic bytes over its time, from per-phase HIP
+    events over the steps that follow the timed ones) and the whole step
+    against HBM.  --compare-precision runs the same scan in FP64 as well and
+    reports both throughputs and the FP32 split form's difference from the
+    FP64 form on a sample of runs."""
     import torch
     from paper_1912_04064_amd import binding as B
     from paper_1912_04064_amd import workloads as WL
-    wls = WL.scan_batch(n_runs=args.runs, steps=args.steps)
-    N = sum(w.n_particles for w in wls)
-    print(f"[bench] scan: {len(wls)} runs, {N} particles", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    ctx = B.Context(wls)
-    torch.cuda.synchronize()
-    t_init = time.perf_counter() - t0
-    ctx.step(args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.step(args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    patches = {}
-    for i in range(len(wls)):
-        p = ctx.diag(i)["patch"][0]
-        patches[p] = patches.get(p, 0) + 1
-    ctx.close()
-    return {"metric": "particle-pushes/s (batched scan)", "value": N * args.steps / dt, "unit": "particle-pushes/s",
-            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
-            "data": "synthetic", "config": {"workload": f"scan{len(wls)}", "runs": len(wls), "particles": N,
-                                            "patches_chosen": patches, "init_s": t_init}}
+
+    def one(prec, sample):
+        wls = WL.scan_batch(n_runs=args.runs, steps=args.steps, precision=prec)
+        N = sum(w.n_particles for w in wls)
+        cells = sum(w.n_cells for w in wls)
+        print(f"[bench] scan {prec}: {len(wls)} runs, {N} particles", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        ctx = B.Context(wls)
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - t0
+        ctx.step(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(args.steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        F = {i: ctx.fields(i, B.F_E | B.F_B | B.F_J) for i in sample}
+        nph = max(1, args.phase_samples or 10)
+        ctx.time_phases(nph)
+        ph = ctx.diag(0)["t_ms"]
+        choices = {}
+        for i in range(len(wls)):
+            dd = ctx.diag(i)
+            k = f"patch{dd['patch'][0]}/seg{dd['seg_cap']}/tile{dd['kernel_path'][2]}"
+            choices[k] = choices.get(k, 0) + 1
+        ctx.close()
+        pb = particle_bytes(wls[0])
+        push_bytes = N * pb + cells * 48
+        step_bytes = N * (52.0 if prec == "fp32s" else 88.0) + cells * 216.0
+        rec = {"value": N * args.steps / dt, "ms_per_step": dt * 1e3 / args.steps, "particles": N, "cells": cells,
+               "init_s": t_init, "tuned": choices,
+               "phase_ms": {"particles": ph[0], "reduce_maxwell": ph[1], "sync_rebin": ph[2], "relayout": ph[3],
+                            "steps": [args.warmup + args.steps, args.warmup + args.steps + nph]},
+               "roofline": {"bound": "hbm", "kernel": "push_kernel (particle phase, all runs)",
+                            "achieved": push_bytes / (ph[0] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": push_bytes / (ph[0] * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                            "bytes_per_launch": push_bytes},
+               "step_roofline": {"bytes_per_step": step_bytes, "roofline": HBM_PEAK_GBS * 1e9 * N / step_bytes,
+                                 "frac": (N * args.steps / dt) / (HBM_PEAK_GBS * 1e9 * N / step_bytes)}}
+        return rec, F
+
+    prec = args.precision
+    sample = list(range(min(8, args.runs)))
+    rec, F = one(prec, sample)
+    out = {"metric": "particle-pushes/s (batched scan)", "value": rec["value"], "unit": "particle-pushes/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "timed_steps": [args.warmup, args.warmup + args.steps], "ms_per_step": rec["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64" if prec == "fp32s" else "f64", "data": "synthetic",
+           "config": {"workload": f"scan{args.runs}", "runs": args.runs, "particles": rec["particles"],
+                      "cells": rec["cells"], "precision": prec, "tuned": rec["tuned"], "init_s": rec["init_s"]},
+           "phase_ms": rec["phase_ms"], "roofline": rec["roofline"], "step_roofline": rec["step_roofline"]}
+    if args.compare_precision:
+        other = "fp64" if prec == "fp32s" else "fp32s"
+        rec2, F2 = one(other, sample)
+        F32, F64 = (F, F2) if prec == "fp32s" else (F2, F)
+        diffs = {i: _family_rel(F32[i], F64[i]) for i in sample}
+        out["forms"] = {prec: {"value": rec["value"], "ms_per_step": rec["ms_per_step"]},
+                        other: {"value": rec2["value"], "ms_per_step": rec2["ms_per_step"]}}
+        out["fp32s_vs_fp64"] = {"runs": sample, "max": {k: max(d[k] for d in diffs.values()) for k in ("E", "Bm", "J")},
+                                "per_run": diffs}
+    return out
 
 
 def bench_serve(args):
     """Served request stream: Poisson arrivals, admission by HBM budget and
-    free slots, continuous batching; p50/p99 latency and throughput."""
+    free slots, continuous batching; p50/p99 latency and throughput.  With
+    --compare-precision the same stream is served in FP64 as well, and the
+    final fields of a sample of runs are compared between the two forms."""
     from paper_1912_04064_amd import serving as S
     from paper_1912_04064_amd import workloads as WL
     reqs = WL.request_stream(args.serve, window_s=args.window)
-    # A request arrives with its input: the seeded synthetic inputs are made
-    # before the stream starts, so the clock sees admission and stepping only.
-    t0 = time.perf_counter()
-    pre = {r.rid: WL.request_workload(r) for r in reqs}
-    print(f"[bench] serve: {len(reqs)} requests at {args.serve}/s over {args.window} s "
-          f"(inputs made in {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
-    budget = int(args.budget_gb * 2 ** 30)
-    be = S.GpuBackend(max_runs=args.slots, hbm_budget=budget)
-    srv = S.Server(be, hbm_budget=budget, max_runs=args.slots, steps_per_call=20)
-    recs = srv.serve(reqs, lambda r: pre[r.rid])
-    admit_ms = be.admit_s * 1e3 / max(be.admits, 1)
-    be.close()
-    summ = S.summarize(recs)
-    return {"metric": "runs/s + p99 latency (served)", "value": summ["runs_per_s"], "unit": "runs/s", "n_gpus": 1,
-            "higher_is_better": True, "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-            "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],
-            "particle_pushes_per_s": summ["particle_pushes_per_s"], "max_concurrent": srv.max_active,
-            "admit_ms_mean": admit_ms,
-            "config": {"workload": f"poisson{args.serve:g}", "requests": len(reqs), "window_s": args.window,
-                       "slots": args.slots, "budget_gb": args.budget_gb}}
+    sample = [r.rid for r in reqs[:8]]
+
+    def one(prec):
+        # A request arrives with its input: the seeded synthetic inputs are
+        # made before the stream starts, so the clock sees admission and
+        # stepping only.
+        t0 = time.perf_counter()
+        pre = {r.rid: WL.request_workload(r, precision=prec) for r in reqs}
+        print(f"[bench] serve {prec}: {len(reqs)} requests at {args.serve}/s over {args.window} s "
+              f"(inputs made in {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+        budget = int(args.budget_gb * 2 ** 30)
+        be = S.GpuBackend(max_runs=args.slots, hbm_budget=budget, capture=sample)
+        srv = S.Server(be, hbm_budget=budget, max_runs=args.slots, steps_per_call=20)
+        recs = srv.serve(reqs, lambda r: pre[r.rid])
+        admit_ms = be.admit_s * 1e3 / max(be.admits, 1)
+        be.close()
+        summ = S.summarize(recs)
+        return {"runs_per_s": summ["runs_per_s"], "p50_latency_s": summ["p50_latency_s"],
+                "p99_latency_s": summ["p99_latency_s"], "particle_pushes_per_s": summ["particle_pushes_per_s"],
+                "max_concurrent": srv.max_active, "admit_ms_mean": admit_ms,
+                "device_bytes_peak": be.peak_bytes}, be.captured
+
+    prec = args.precision
+    res, cap = one(prec)
+    out = {"metric": "runs/s + p99 latency (served)", "value": res["runs_per_s"], "unit": "runs/s", "n_gpus": 1,
+           "higher_is_better": True, "vs_baseline": None, "dtype": "f32+f64" if prec == "fp32s" else "f64",
+           "data": "synthetic", **{k: v for k, v in res.items() if k != "runs_per_s"},
+           "config": {"workload": f"poisson{args.serve:g}", "requests": len(reqs), "window_s": args.window,
+                      "slots": args.slots, "budget_gb": args.budget_gb, "precision": prec}}
+    if args.compare_precision:
+        other = "fp64" if prec == "fp32s" else "fp32s"
+        res2, cap2 = one(other)
+        c32, c64 = (cap, cap2) if prec == "fp32s" else (cap2, cap)
+        diffs = {i: _family_rel(c32[i], c64[i]) for i in sample if i in c32 and i in c64}
+        out["forms"] = {prec: res, other: res2}
+        out["fp32s_vs_fp64"] = {"runs": sorted(diffs), "max": {k: max(d[k] for d in diffs.values())
+                                                               for k in ("E", "Bm", "J")} if diffs else None,
+                                "per_run": diffs}
+    return out
 
 
 def bench_precision(args):
@@ -311,6 +386,8 @@ def main():
     ap.add_argument("--no-full-run", action="store_true",
                     help="skip the workload's whole trajectory (its configured step count)")
     ap.add_argument("--runs", type=int, default=256, help="runs of the batched scan (--workload scan)")
+    ap.add_argument("--precision", default="fp32s", choices=["fp32s", "fp64"],
+                    help="precision form of the batched scan and the served stream")
     ap.add_argument("--serve", type=float, default=0.0, help="served stream: arrival rate in runs/s")
     ap.add_argument("--window", type=float, default=10.0, help="served stream: arrival window in s")
     ap.add_argument("--slots", type=int, default=64)
@@ -337,11 +414,11 @@ def main():
     if args.compare_sdsd:
         print(json.dumps(bench_sdsd(args)), flush=True)
         return
-    if args.compare_precision:
-        print(json.dumps(bench_precision(args)), flush=True)
-        return
     if args.workload == "scan":
         print(json.dumps(bench_scan(args)), flush=True)
+        return
+    if args.compare_precision:
+        print(json.dumps(bench_precision(args)), flush=True)
         return
     if args.calib_copy:
         x = torch.ones(128 << 20, dtype=torch.float32, device="cuda")

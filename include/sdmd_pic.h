@@ -144,10 +144,15 @@ typedef struct {
  *   field_solver PIC_SOLVER_PSATD: one region (n_regions all 1), every
  *     n_cells[a] of the run a power of two <= 2048, and dt < min d[a] (the
  *     spectral step has no Courant limit; particles still move less than a
- *     cell per step).
- * A patch of 0 on every axis lets the library choose: it times a few steps
- * of each admissible square patch (8, 16, 32 in 2D; 4, 8 in 3D) on this
- * config and keeps the fastest (cached per grid, precision and density). */
+ *     cell per step);
+ *   seg_cap is 0 or in [256, 65536]; field_tile_x is 0 or a compiled width
+ *     (8, 16, 32, 64 in 2D; 8, 16, 32 in 3D; 8 in 3D with the filter).
+ * A patch of 0 on every axis lets the library choose the patch edge, the
+ * segment capacity and the field tile width: it times a few steps of this
+ * config for each admissible square patch (8, 16, 32 in 2D; 4, 8 in 3D),
+ * then for other segment capacities with the fastest patch, then for other
+ * field tile widths, in scratch runs inside the remaining HBM budget, and
+ * keeps the fastest (cached per grid, precision and density). */
 typedef struct {
     int32_t dims;
     int32_t n_cells[3];
@@ -169,6 +174,15 @@ typedef struct {
     int64_t max_steps;          /* steps this run takes, 0 = unlimited: once
                                    they are done the run is left untouched by
                                    later pic_step calls (continuous batching) */
+    int32_t seg_cap;            /* particles per segment a re-layout aims at:
+                                   a patch holding more is worked on by several
+                                   workgroups with their own current tiles (the
+                                   task decomposition of a heavy patch,
+                                   section 4); 0 = 2048 (2D) / 4096 (3D), or
+                                   the autotuner's choice                   */
+    int32_t field_tile_x;       /* nodes per field-kernel tile along x; 0 =
+                                   the widest that the region width allows, or
+                                   the autotuner's choice                   */
     const pic_particles_in *particles;   /* may be null: no particles      */
     const pic_fields_in    *fields;      /* may be null: zero fields       */
 } pic_config;
@@ -249,6 +263,8 @@ typedef struct {
     double  det_quantum[2];           /* deterministic mode: the quantum of
                                          the fixed-point current and charge
                                          sums (0 otherwise)                */
+    int32_t seg_cap;                  /* segment capacity in use           */
+    int32_t reserved;
 } pic_diag_t;
 
 /* Particle export (host memory, caller owned).  capacity is the length of

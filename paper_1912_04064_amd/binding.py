@@ -64,7 +64,8 @@ class PicConfig(C.Structure):
                 ("patch", C.c_int32 * 3), ("n_regions", C.c_int32 * 3), ("shape_order", C.c_int32),
                 ("precision", C.c_int32), ("bc", C.c_int32 * 3), ("track_ids", C.c_int32),
                 ("filter_passes", C.c_int32), ("field_solver", C.c_int32), ("q", C.c_double),
-                ("m", C.c_double), ("max_steps", C.c_int64), ("particles", C.POINTER(PicParticlesIn)),
+                ("m", C.c_double), ("max_steps", C.c_int64), ("seg_cap", C.c_int32), ("field_tile_x", C.c_int32),
+                ("particles", C.POINTER(PicParticlesIn)),
                 ("fields", C.POINTER(PicFieldsIn))]
 
 
@@ -84,7 +85,7 @@ class PicDiag(C.Structure):
                 ("K", C.c_double), ("t_ms", C.c_double * 4), ("n_relayout", C.c_int64), ("n_spill", C.c_int64),
                 ("err_flags", C.c_int32), ("patch", C.c_int32 * 3), ("gauss_residual", C.c_double),
                 ("kernel_path", C.c_int32 * 4), ("device_bytes", C.c_int64), ("device_bytes_peak", C.c_int64),
-                ("det_quantum", C.c_double * 2)]
+                ("det_quantum", C.c_double * 2), ("seg_cap", C.c_int32), ("reserved", C.c_int32)]
 
 
 class PicParticlesOut(C.Structure):
@@ -180,7 +181,7 @@ class _CfgHolder:
         self.cfg = PicConfig(dims, (C.c_int32 * 3)(*nc[:3]), (C.c_double * 3)(*d[:3]), wl.dt,
                              (C.c_int32 * 3)(*pt[:3]), (C.c_int32 * 3)(*nr[:3]), 2, prec, (C.c_int32 * 3)(0, 0, 0),
                              1 if track_ids else 0, int(wl.filter), SOLVERS[wl.solver], wl.q, wl.m,
-                             int(max_steps),
+                             int(max_steps), int(wl.seg_cap), int(wl.tile_x),
                              C.pointer(self.pin),
                              C.pointer(self.fin) if self.fin is not None else C.POINTER(PicFieldsIn)())
 

@@ -45,6 +45,7 @@ struct DevBuf {
 struct Run {
     bool active = false;
     int dims = 2, prec = PIC_FP64, pc = 8, px = 0;
+    int ytx = 64;          // field-kernel tile width along x
     bool split = false;
     int ncell = 0;
     int total_ghosts = 0;
@@ -321,6 +322,15 @@ static int make_layout(const pic_config *cfg, const int P[3], bool det, Layout &
     }
     if (cfg->filter_passes < 0 || cfg->filter_passes > (dims == 2 ? 4 : 2))
         return fail("filter_passes must be 0..4 in 2D, 0..2 in 3D");
+    if (cfg->seg_cap != 0 && (cfg->seg_cap < 256 || cfg->seg_cap > 65536))
+        return fail("seg_cap must be 0 or in [256, 65536]");
+    if (cfg->field_tile_x != 0) {
+        const int t = cfg->field_tile_x;
+        const bool ok = dims == 2 ? (t == 8 || t == 16 || t == 32 || t == 64)
+                                  : (cfg->filter_passes > 0 ? t == 8 : (t == 8 || t == 16 || t == 32));
+        if (!ok) return fail("field_tile_x must be 0 or a compiled width (2D: 8, 16, 32, 64; 3D: 8, 16, 32; 3D with "
+                             "the filter: 8)");
+    }
     const int pmax = dims == 2 ? 32 : 8;
     L.dims = dims;
     L.split = cfg->precision == PIC_FP32_SPLIT;
@@ -369,7 +379,7 @@ static int make_layout(const pic_config *cfg, const int P[3], bool det, Layout &
     if (L.n_total < 0) return fail("negative particle count");
     // segments: a re-layout splits a patch into ceil(count / seg_cap)
     // segments, so at most n_patch + N / seg_cap of them exist
-    L.seg_cap = dims == 3 ? SEG_CAP_3D : SEG_CAP_2D;
+    L.seg_cap = cfg->seg_cap > 0 ? cfg->seg_cap : (dims == 3 ? SEG_CAP_3D : SEG_CAP_2D);
     L.seg_max = (int)(L.n_patch + (L.n_total + L.seg_cap - 1) / L.seg_cap + 16);
     L.cap_total = L.n_total + L.n_total / 2 + 32LL * L.seg_max + 1024;
     if (L.cap_total > (1LL << 31) - 1) return fail("too many particles for one run");
@@ -537,75 +547,140 @@ static bool auto_patch(const pic_config *cfg)
     return cfg->patch[0] == 0 && cfg->patch[1] == 0 && (cfg->dims == 2 || cfg->patch[2] == 0);
 }
 
-using TuneKey = std::tuple<int, int, int, int, int, int, int, int, int>;
-static std::map<TuneKey, int> g_tune_cache;
+// segment capacities the autotuner tries (the first is the default)
+static std::vector<int> cap_candidates(int dims)
+{
+    return dims == 2 ? std::vector<int>{SEG_CAP_2D, 1024, 4096} : std::vector<int>{SEG_CAP_3D, 2048, 8192};
+}
+
+// field tile widths the autotuner tries: the compiled widths no wider than
+// the region (at least 8), the default first
+static std::vector<int> tile_candidates(const pic_config *cfg)
+{
+    const bool filt = cfg->filter_passes > 0;
+    const int nr = cfg->n_regions[0] < 1 ? 1 : cfg->n_regions[0];
+    const int rs0 = cfg->n_cells[0] / nr;
+    std::vector<int> out{yee_tile_x(cfg->dims, rs0, filt)};
+    if (cfg->dims == 3 && filt) return out;
+    const int top = cfg->dims == 2 ? 64 : 32;
+    for (int t = top; t >= 8; t /= 2)
+        if (t != out[0] && (t <= rs0 || t == 8)) out.push_back(t);
+    return out;
+}
+
+struct Tuned {
+    int patch, seg_cap, tile_x;
+};
+using TuneKey = std::tuple<int, int, int, int, int, int, int, int, int, int, int>;
+static std::map<TuneKey, Tuned> g_tune_cache;
 static std::mutex g_tune_mu;
 
-// Time 4 steps (after 2 warm-up steps) of the config with each candidate
-// patch in a scratch context on the caller's stream; keep the fastest.
-static void autotune_patch(pic_ctx *c, const pic_config *cfg, int P[3])
+// Milliseconds of 4 steps (after 2 warm-up steps) of `tc` in a scratch
+// context beside c, on the caller's stream; 1e30 if it cannot be set up
+// (for instance because the remaining HBM budget is too small).
+static float trial_ms(pic_ctx *c, const pic_config &tc)
+{
+    pic_runtime trt = c->rt;
+    trt.flags |= PIC_RT_NO_GRAPH;
+    trt.max_runs = 1;
+    // the scratch context lives beside this one: it may use what this
+    // context's budget leaves, and its peak counts here
+    trt.hbm_budget = c->rt.hbm_budget ? (c->rt.hbm_budget > c->bytes ? c->rt.hbm_budget - c->bytes : 1) : 0;
+    pic_ctx *t = nullptr;
+    if (pic_init(&tc, 1, &trt, &t) != PIC_OK) return 1e30f;
+    c->peak_bytes = std::max(c->peak_bytes, c->bytes + t->peak_bytes);
+    float ms = 1e30f;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess && pic_step(t, 2) == PIC_OK &&
+        hipEventRecord(e0, t->stream) == hipSuccess && pic_step(t, 4) == PIC_OK &&
+        hipEventRecord(e1, t->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess) {
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 1e30f;
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    c->peak_bytes = std::max(c->peak_bytes, c->bytes + t->peak_bytes);
+    pic_free(t);
+    return ms;
+}
+
+// The autotuner (patch = 0 on every axis): a staged search, each stage
+// keeping the fastest of its trials -- the square patch edge with the
+// default segment capacity and field tile, then the segment capacity with
+// that patch, then the field tile width.  Results are cached per grid,
+// precision, density class, region layout, filter and solver.
+static Tuned autotune(pic_ctx *c, const pic_config *cfg)
 {
     std::vector<int> cand = patch_candidates(cfg);
     if (cand.empty()) {
+        int P[3];
         default_patch(cfg, P);
-        return;
+        return Tuned{P[0], 0, 0};
     }
     const long long n = cfg->particles ? cfg->particles->n : 0;
     long long ncell = 1;
     for (int a = 0; a < cfg->dims; ++a) ncell *= cfg->n_cells[a];
     const int ppcb = (int)std::lround(std::log2(std::max(1.0, (double)n / (double)ncell)));
-    const TuneKey key{cfg->dims, cfg->n_cells[0], cfg->n_cells[1], cfg->dims == 3 ? cfg->n_cells[2] : 1,
-                      cfg->precision, ppcb, cfg->n_regions[0], cfg->n_regions[1], cfg->n_regions[2]};
-    int best = cand[0];
+    const TuneKey key{cfg->dims,          cfg->n_cells[0],   cfg->n_cells[1],     cfg->dims == 3 ? cfg->n_cells[2] : 1,
+                      cfg->precision,     ppcb,              cfg->n_regions[0],   cfg->n_regions[1],
+                      cfg->n_regions[2],  cfg->filter_passes, cfg->field_solver};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) best = it->second;
+        if (it != g_tune_cache.end()) return it->second;
     }
-    bool cached = false;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        cached = g_tune_cache.count(key) > 0;
-    }
-    if (!cached && cand.size() > 1) {
-        float best_ms = 1e30f;
+    pic_config tc = *cfg;
+    tc.max_steps = 0;
+    auto set_patch = [&](int p) {
+        tc.patch[0] = tc.patch[1] = p;
+        tc.patch[2] = cfg->dims == 3 ? p : 1;
+    };
+    Tuned best{cand[0], cfg->seg_cap, cfg->field_tile_x};
+    float best_ms = 1e30f;
+    // stage 1: the patch edge (with one candidate, the baseline for the
+    // later stages)
+    tc.seg_cap = cfg->seg_cap;
+    tc.field_tile_x = cfg->field_tile_x;
+    const bool later = cfg->seg_cap == 0 || cfg->field_tile_x == 0;
+    if (cand.size() > 1 || later)
         for (int p : cand) {
-            pic_config tc = *cfg;
-            tc.patch[0] = tc.patch[1] = p;
-            tc.patch[2] = cfg->dims == 3 ? p : 1;
-            tc.max_steps = 0;
-            pic_runtime trt = c->rt;
-            trt.flags |= PIC_RT_NO_GRAPH;
-            trt.max_runs = 1;
-            // the scratch context lives beside this one: it may use what
-            // this context's budget leaves, and its peak counts here
-            trt.hbm_budget = c->rt.hbm_budget ? (c->rt.hbm_budget > c->bytes ? c->rt.hbm_budget - c->bytes : 1) : 0;
-            pic_ctx *t = nullptr;
-            if (pic_init(&tc, 1, &trt, &t) != PIC_OK) continue;
-            c->peak_bytes = std::max(c->peak_bytes, c->bytes + t->peak_bytes);
-            hipEvent_t e0, e1;
-            float ms = 1e30f;
-            if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
-                pic_step(t, 2);
-                hipEventRecord(e0, t->stream);
-                pic_step(t, 4);
-                hipEventRecord(e1, t->stream);
-                if (hipEventSynchronize(e1) == hipSuccess) hipEventElapsedTime(&ms, e0, e1);
-                hipEventDestroy(e0);
-                hipEventDestroy(e1);
-            }
-            c->peak_bytes = std::max(c->peak_bytes, c->bytes + t->peak_bytes);
-            pic_free(t);
+            set_patch(p);
+            const float ms = trial_ms(c, tc);
             if (ms < best_ms) {
                 best_ms = ms;
-                best = p;
+                best.patch = p;
             }
         }
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[key] = best;
+    set_patch(best.patch);
+    // stage 2: the segment capacity (unless the caller fixed it)
+    if (cfg->seg_cap == 0) {
+        const std::vector<int> caps = cap_candidates(cfg->dims);
+        best.seg_cap = caps[0];
+        for (size_t i = 1; i < caps.size(); ++i) {
+            tc.seg_cap = caps[i];
+            const float ms = trial_ms(c, tc);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best.seg_cap = caps[i];
+            }
+        }
+        tc.seg_cap = best.seg_cap;
     }
-    P[0] = P[1] = best;
-    P[2] = cfg->dims == 3 ? best : 1;
+    // stage 3: the field tile width (unless the caller fixed it)
+    if (cfg->field_tile_x == 0) {
+        const std::vector<int> txs = tile_candidates(cfg);
+        best.tile_x = txs[0];
+        for (size_t i = 1; i < txs.size(); ++i) {
+            tc.field_tile_x = txs[i];
+            const float ms = trial_ms(c, tc);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best.tile_x = txs[i];
+            }
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+    return best;
 }
 
 static int gauss_field(pic_ctx *c, int slot, double *g);
@@ -652,11 +727,19 @@ static void fixed_point_scales(const pic_config *cfg, const Layout &L, RunDev &d
     d.rscale_inv = 1.0 / d.rscale;
 }
 
-static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
+static int setup_run(pic_ctx *c, int slot, const pic_config *cfg_in)
 {
     Run &r = c->runs[slot];
+    pic_config tuned = *cfg_in;
+    if (auto_patch(cfg_in)) {
+        const Tuned t = autotune(c, cfg_in);
+        tuned.patch[0] = tuned.patch[1] = t.patch;
+        tuned.patch[2] = cfg_in->dims == 3 ? t.patch : 1;
+        tuned.seg_cap = t.seg_cap;
+        tuned.field_tile_x = t.tile_x;
+    }
+    const pic_config *cfg = &tuned;
     int P[3] = {cfg->patch[0], cfg->patch[1], cfg->patch[2]};
-    if (auto_patch(cfg)) autotune_patch(c, cfg, P);
     Layout L;
     std::string why;
     int rc = make_layout(cfg, P, c->det, L, why);
@@ -670,6 +753,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg)
     r.prec = cfg->precision;
     r.pc = L.pc;
     r.px = fast_patch(L);
+    r.ytx = cfg->field_tile_x > 0 ? cfg->field_tile_x : yee_tile_x(L.dims, L.rs[0], cfg->filter_passes > 0);
     r.ncell = L.n[0] * L.n[1] * L.n[2];
     r.total_ghosts = L.ghosts * L.n_regions;
     RunDev &d = r.rd;
@@ -896,7 +980,7 @@ static int rebuild_items(pic_ctx *c)
             pc = &c->pcls.back();
         }
         const bool filt = r.rd.filter > 0;
-        const int ytx = yee_tile_x(r.dims, r.rd.rs[0], filt);
+        const int ytx = r.ytx;
         FieldClass *fc = nullptr;
         for (auto &x : c->fcls)
             if (x.dims == r.dims && x.split == r.split && x.tx == ytx && x.filt == filt && x.solver == r.rd.solver)
@@ -1103,14 +1187,21 @@ int pic_mem_bytes(const pic_config *cfg, size_t *bytes)
     } else {
         shapes.push_back({cfg->patch[0], cfg->patch[1], cfg->patch[2]});
     }
+    // with the autotuner, the worst of the patch edges and segment
+    // capacities it may choose (smaller segments: more tiles)
+    std::vector<int> caps{cfg->seg_cap};
+    if (auto_patch(cfg) && cfg->seg_cap == 0) caps = cap_candidates(cfg->dims);
     size_t worst = 0;
-    for (auto &sh : shapes) {
-        Layout L;
-        std::string why;
-        int rc = make_layout(cfg, sh.data(), true, L, why);
-        if (rc) return set_err(nullptr, rc, "%s", why.c_str());
-        worst = std::max(worst, L.bytes);
-    }
+    for (auto &sh : shapes)
+        for (int cap : caps) {
+            pic_config tc = *cfg;
+            tc.seg_cap = cap;
+            Layout L;
+            std::string why;
+            int rc = make_layout(&tc, sh.data(), true, L, why);
+            if (rc) return set_err(nullptr, rc, "%s", why.c_str());
+            worst = std::max(worst, L.bytes);
+        }
     *bytes = worst;
     return PIC_OK;
 }
@@ -1472,7 +1563,8 @@ static int diag_impl(pic_ctx *c, int32_t run, pic_diag_t *out, const DiagScratch
     for (int a = 0; a < 3; ++a) out->patch[a] = d.P[a];
     out->kernel_path[0] = r.px;
     out->kernel_path[1] = r.pc;
-    out->kernel_path[2] = yee_tile_x(r.dims, d.rs[0], d.filter > 0);
+    out->kernel_path[2] = r.ytx;
+    out->seg_cap = d.seg_cap;
     out->kernel_path[3] = d.det;
     out->det_quantum[0] = d.det ? d.jscale_inv : 0.0;
     out->det_quantum[1] = d.det ? d.rscale_inv : 0.0;

@@ -45,9 +45,13 @@ class RunRecord:
 class GpuBackend:
     """Runs admitted into one live context of the HIP library."""
 
-    def __init__(self, max_runs: int, hbm_budget: int, track_ids: bool = False):
+    def __init__(self, max_runs: int, hbm_budget: int, track_ids: bool = False, capture=()):
         from . import binding
         self.B = binding
+        # requests whose final fields (E, Bm, J) are kept at finish, e.g. to
+        # compare precision forms
+        self.capture = set(capture)
+        self.captured = {}
         # the library holds the context to hbm_budget device bytes in total
         # (runs, their set-up and read-out scratch, the context's own tables)
         self.ctx = binding.Context([], max_runs=max_runs, hbm_budget=hbm_budget, track_ids=track_ids)
@@ -88,9 +92,12 @@ class GpuBackend:
     def steps_done(self, run: int) -> int:
         return self.ctx.run_steps(run)
 
-    def finish(self, run: int) -> dict:
+    def finish(self, run: int, rid=None) -> dict:
         d = self.ctx.diag(run)              # synchronises
         self.peak_bytes = max(self.peak_bytes, d["device_bytes_peak"])
+        if rid in self.capture:
+            B = self.B
+            self.captured[rid] = self.ctx.fields(run, B.F_E | B.F_B | B.F_J)
         return {"n_particles": d["n_particles"], "U_E": d["U_E"], "U_B": d["U_B"], "K": d["K"],
                 "step": d["step"]}
 
@@ -143,7 +150,7 @@ class FakeBackend:
     def steps_done(self, run: int) -> int:
         return self.runs[run]["done"]
 
-    def finish(self, run: int) -> dict:
+    def finish(self, run: int, rid=None) -> dict:
         return {"n_particles": self.runs[run]["n"], "step": self.runs[run]["done"]}
 
     def retire(self, run: int):
@@ -208,7 +215,7 @@ class Server:
             self.be.step(self.k)
             for run in [r for r, (req, rec, need) in active.items() if self.be.steps_done(r) >= req.steps]:
                 req, rec, need = active.pop(run)
-                rec.result = self.be.finish(run)
+                rec.result = self.be.finish(run, req.rid)
                 rec.finished = self.be.clock()
                 self.be.retire(run)
                 self.used -= need

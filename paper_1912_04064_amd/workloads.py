@@ -59,6 +59,8 @@ class Workload:
     seed: int = 0
     filter: int = 0               # binomial current filter passes (0 = off)
     solver: str = "yee"           # field solver: "yee" or "psatd"
+    seg_cap: int = 0              # particles per segment (0 = library default / autotuner)
+    tile_x: int = 0               # field-kernel tile width (0 = library default / autotuner)
 
     @property
     def n_particles(self) -> int:

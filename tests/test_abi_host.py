@@ -52,6 +52,9 @@ def _cfg(**over):
     (dict(solver="psatd", nreg=(2, 1)), "one region"),
     (dict(solver="psatd", n=(48, 32)), "powers of two"),
     (dict(solver="psatd", dt=0.2), "dt must satisfy 0 < dt < min d"),
+    (dict(seg_cap=100), "seg_cap"),
+    (dict(seg_cap=70000), "seg_cap"),
+    (dict(tile_x=24), "field_tile_x"),
 ])
 def test_config_validation(change, msg):
     wl = _cfg(**change)
@@ -107,3 +110,27 @@ def test_paths_table_names_every_kernel_instantiation():
     assert len(push) >= 15 and len(yee) >= 24
     assert T.push_instantiations() == push
     assert T.yee_instantiations() == yee
+
+
+def test_3d_filter_takes_the_narrow_field_tile_only():
+    wl = WL.cylinder_3d(n=(16, 16, 16), radius=3.0, ppc_bg=1, ppc_cyl=2, patch=(8, 8, 8))
+    wl.filter = 1
+    wl.tile_x = 16
+    with pytest.raises(B.PicError) as e:
+        B.mem_bytes(wl)
+    assert e.value.code == B.PIC_E_CONFIG and "field_tile_x" in str(e.value)
+    wl.tile_x = 8
+    assert B.mem_bytes(wl) > 0
+
+
+def test_mem_bytes_bounds_the_autotuners_choices():
+    """With the patch left to the autotuner, pic_mem_bytes is the most any
+    candidate (patch edge x segment capacity) can take."""
+    auto = WL.thermal_2d(n=(128, 64), ppc=8, patch=(0, 0))
+    worst = 0
+    for p in (8, 16, 32):
+        for cap in (1024, 2048, 4096):
+            wl = WL.thermal_2d(n=(128, 64), ppc=8, patch=(p, p))
+            wl.seg_cap = cap
+            worst = max(worst, B.mem_bytes(wl))
+    assert B.mem_bytes(auto) == worst

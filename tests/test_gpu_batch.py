@@ -87,14 +87,21 @@ def test_continuous_batching_equals_alone():
 
 
 def test_autotuned_patch_is_valid_and_correct():
+    """The autotuner's choices (patch edge, segment capacity, field tile
+    width) are among its candidates, and the run gives what the same
+    explicit configuration gives."""
     say("case: autotune")
+    import dataclasses
     wl = WL.thermal_2d(n=(128, 64), ppc=8, vth=0.05, patch=(0, 0), precision="fp32s", seed=21)
     with B.Context([wl]) as c:
         c.step(5)
         d = c.diag(0)
-        assert d["patch"][0] in (8, 16, 32) and d["patch"][0] == d["patch"][1]
         F = c.fields(0, MASK)
-    wl2 = WL.thermal_2d(n=(128, 64), ppc=8, vth=0.05, patch=tuple(d["patch"][:2]), precision="fp32s", seed=21)
+    say(f"autotuned: patch {d['patch']} seg_cap {d['seg_cap']} field tile {d['kernel_path'][2]}")
+    assert d["patch"][0] in (8, 16, 32) and d["patch"][0] == d["patch"][1]
+    assert d["seg_cap"] in (1024, 2048, 4096)
+    assert d["kernel_path"][2] in (8, 16, 32, 64)
+    wl2 = dataclasses.replace(wl, patch=tuple(d["patch"][:2]), seg_cap=d["seg_cap"], tile_x=d["kernel_path"][2])
     close(F, alone(wl2, 5), "fp32s")
 
 
@@ -121,3 +128,35 @@ def test_budget_admission_and_serving_loop():
     assert srv.max_active >= 2
     for r, q in zip(recs, reqs):
         assert r.result["step"] == q.steps and r.result["n_particles"] == mk(q).n_particles
+
+
+def test_batched_scan_sample_against_oracle():
+    """Runs of the parameter scan stepped together as a batch (autotuned
+    patch, segment capacity and field tile; one launch per phase for all of
+    them): the smaller runs of the sample (64 x 64 and 128 x 128 cells, 4 to
+    10 particles per cell) against the oracle after 1 and 10 steps, FP32
+    split form (1e-5 and 1e-4 relative per family)."""
+    say("case: batched scan sample vs oracle")
+    import oracle as O
+    from tests.helpers import oracle_state
+    wls = WL.scan_batch(n_runs=20, steps=10)
+    picks = [2, 7, 16, 18]
+    assert all(wls[i].n_particles <= 163840 for i in picks)
+    res = {1: {}, 10: {}}
+    with B.Context(wls) as c:
+        for k in (1, 9):
+            c.step(k)
+            s = c.diag(0)["step"]
+            for i in picks:
+                res[s][i] = c.fields(i, B.F_E | B.F_B | B.F_J)
+    for i in picks:
+        g, F, P = oracle_state(wls[i])
+        done = 0
+        for s, tol in ((1, 1e-5), (10, 1e-4)):
+            while done < s:
+                O.step_sdsd(g, F, P)
+                done += 1
+            ref = np.concatenate([F[0:3], F[6:9], F[9:12]])
+            errs = [max(family_errors(res[s][i][sl], ref[sl])) for sl in (slice(0, 3), slice(3, 6), slice(6, 9))]
+            say(f"scan run {i} {wls[i].n} step {s}: E/Bm/J {errs}")
+            assert max(errs) < tol, (i, s, errs)

@@ -78,7 +78,7 @@ struct FieldClass {
     int4 *dy = nullptr, *dp = nullptr;
     int *dslots = nullptr;
     size_t capy = 0, capp = 0, caps = 0;
-    int move_gx = 1, commit_gx = 1;
+    int count_gx = 1, move_gx = 1, commit_gx = 1;
 };
 
 }  // namespace
@@ -519,7 +519,7 @@ static int relayout_one(pic_ctx *c, int slot, int force)
     const int nsb = std::max(1, std::min(1024, (int)(r.rd.n_total / (BLOCK * 64))));
     const int mgx = move_chunk_blocks(r.rd.n_patch, r.rd.n_total) + nsb;
     int cb = (int)std::min<long long>(64, std::max<long long>(1, (r.rd.seg_max + BLOCK) / BLOCK));
-    HIPCHK(c, launch_relayout(r.dims, r.split, c->d_runs, c->d_slot1, 1, mgx, cb, force, c->stream));
+    HIPCHK(c, launch_relayout(r.dims, r.split, c->d_runs, c->d_slot1, 1, nsb, mgx, cb, force, c->stream));
     return PIC_OK;
 }
 
@@ -966,6 +966,7 @@ static int rebuild_items(pic_ctx *c)
         fc.hy.clear();
         fc.hp.clear();
         fc.slots.clear();
+        fc.count_gx = 1;
         fc.move_gx = 1;
         fc.commit_gx = 1;
     }
@@ -1013,6 +1014,7 @@ static int rebuild_items(pic_ctx *c)
         for (int b = 0; b < d.ins_blocks; ++b) fc->hp.push_back(make_int4(slot, 2, b, d.ins_blocks));
         fc->slots.push_back(slot);
         const int nsb = std::max(1, std::min(1024, (int)(d.n_total / (BLOCK * 64))));
+        fc->count_gx = std::max(fc->count_gx, nsb);
         fc->move_gx = std::max(fc->move_gx, move_chunk_blocks(d.n_patch, d.n_total) + nsb);
         fc->commit_gx = std::max(fc->commit_gx, std::min(64, std::max(1, (d.seg_max + BLOCK) / BLOCK)));
     }
@@ -1074,8 +1076,8 @@ static hipError_t enqueue_relayout(pic_ctx *c, hipStream_t s)
 {
     for (auto &fc : c->fcls) {
         if (fc.slots.empty()) continue;
-        hipError_t e = launch_relayout(fc.dims, fc.split, c->d_runs, fc.dslots, (int)fc.slots.size(), fc.move_gx,
-                                       fc.commit_gx, 0, s);
+        hipError_t e = launch_relayout(fc.dims, fc.split, c->d_runs, fc.dslots, (int)fc.slots.size(), fc.count_gx,
+                                       fc.move_gx, fc.commit_gx, 0, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -98,23 +98,28 @@ constexpr int PLAN_LDS_PATCHES = 16384; // patch counts the planner histograms i
 // segments of a patch holding t particles
 __device__ __forceinline__ int segs_for(int t, int cs) { return min(MAX_OLD_SEGS, max(1, (t + cs - 1) / cs)); }
 
-// Plan a re-layout of one run (one workgroup): per-patch totals (live
-// particles of its segments + parked ones), the number of segments of each
-// patch K_p = ceil(total / seg_cap), an even split of the total over them,
-// and each segment's capacity (live + 50 % + 32, or an even share of the
-// free slots if that does not fit).
-__global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev *__restrict__ runs,
-                                                                   const int *__restrict__ slots, int force)
+// Plan a re-layout of one run, in three launches:
+//   relayout_tally_kernel (one workgroup per run): whether to re-lay out at
+//     all (parked particles, or forced), then per patch the live particles
+//     of its segments and the first move chunk of each patch;
+//   relayout_count_kernel (many workgroups per run): the parked particles
+//     of each patch, added to those totals;
+//   relayout_plan_kernel (one workgroup per run): the number of segments of
+//     each patch K_p = ceil(total / seg_cap), an even split of the total
+//     over them, and each segment's capacity (live + 50 % + 32, or an even
+//     share of the free slots if that does not fit).
+__global__ __launch_bounds__(PLAN_BLOCK) void relayout_tally_kernel(const RunDev *__restrict__ runs,
+                                                                    const int *__restrict__ slots, int force)
 {
     const RunDev &rd = runs[slots[blockIdx.x]];
     __shared__ long long buf[PLAN_BLOCK];
-    __shared__ int s_hist[PLAN_LDS_PATCHES];
     const int tid = threadIdx.x;
     const int nsp = min(rd.ctl->nspill, rd.n_total);
     if (!force && nsp == 0) {
         if (tid == 0) rd.ctl->relayout = 0;
         return;
     }
+    if (tid == 0) rd.ctl->relayout = 1;   // tentative: the planner decides
     const int np = rd.n_patch;
     const int nseg = rd.ctl->nseg;
     for (int p = tid; p < np; p += PLAN_BLOCK) {
@@ -143,42 +148,70 @@ __global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev 
         }
         if (tid == 0) rd.cpre[np] = (int)ncall;
     }
-    // parked particles per patch: LDS histogram when the patch count fits
-    if (np <= PLAN_LDS_PATCHES) {
-        for (int p = tid; p < np; p += PLAN_BLOCK) s_hist[p] = 0;
+}
+
+// Parked particles per patch, added to the totals: workgroup b of nb takes
+// an even slice of the spill store, counts it in an LDS histogram when the
+// patch count fits (global atomics otherwise) and adds the non-zero counts.
+// A wavefront whose parked particles all belong to one patch (the usual
+// case at set-up, when every particle is parked in input order) adds once:
+// 64 lanes on one counter would serialise.
+__global__ __launch_bounds__(BLOCK) void relayout_count_kernel(const RunDev *__restrict__ runs,
+                                                               const int *__restrict__ slots)
+{
+    const RunDev &rd = runs[slots[blockIdx.y]];
+    if (!rd.ctl->relayout) return;
+    __shared__ int s_hist[PLAN_LDS_PATCHES];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int nsp = min(rd.ctl->nspill, rd.n_total);
+    const int np = rd.n_patch;
+    const int nb = gridDim.x;
+    const long long i_begin = (long long)nsp * blockIdx.x / nb, i_end = (long long)nsp * (blockIdx.x + 1) / nb;
+    if (i_begin >= i_end) return;
+    const bool lds = np <= PLAN_LDS_PATCHES;
+    if (lds) {
+        for (int p = tid; p < np; p += BLOCK) s_hist[p] = 0;
         __syncthreads();
-        // a wavefront whose parked particles all belong to one patch (the
-        // usual case at set-up, when every particle is parked in input
-        // order) adds once: 64 lanes on one LDS counter would serialise
-        // (eight rounds of loads in flight per thread)
-        const int lane = tid & 63;
-        constexpr int HU = 8;
-        for (int i0 = 0; i0 < nsp; i0 += HU * PLAN_BLOCK) {
-            int qv[HU];
+    }
+    int *hist = lds ? s_hist : rd.tot;
+    constexpr int HU = 8;   // rounds of loads in flight per thread
+    for (long long i0 = i_begin; i0 < i_end; i0 += HU * BLOCK) {
+        int qv[HU];
 #pragma unroll
-            for (int u = 0; u < HU; ++u) {
-                const int i = i0 + u * PLAN_BLOCK + tid;
-                qv[u] = i < nsp ? gp(rd.spatch)[i] : -1;
-            }
+        for (int u = 0; u < HU; ++u) {
+            const long long i = i0 + u * BLOCK + tid;
+            qv[u] = i < i_end ? gp(rd.spatch)[i] : -1;
+        }
 #pragma unroll
-            for (int u = 0; u < HU; ++u) {
-                const int q = qv[u];
-                const bool v = q >= 0;
-                const int q0 = __shfl(q, 0);
-                if (__all(!v || q == q0)) {
-                    const unsigned long long mv = __ballot(v);
-                    if (lane == 0 && mv) atomicAdd(&s_hist[q0], __popcll(mv));
-                } else if (v) {
-                    atomicAdd(&s_hist[q], 1);
-                }
+        for (int u = 0; u < HU; ++u) {
+            const int q = qv[u];
+            const bool v = q >= 0 && q < np;
+            const int q0 = __shfl(q, 0);
+            if (__all(!v || q == q0)) {
+                const unsigned long long mv = __ballot(v);
+                if (lane == 0 && mv) atomicAdd(&hist[q0], __popcll(mv));
+            } else if (v) {
+                atomicAdd(&hist[q], 1);
             }
         }
-        __syncthreads();
-        for (int p = tid; p < np; p += PLAN_BLOCK) rd.tot[p] += s_hist[p];
-    } else {
-        for (int i = tid; i < nsp; i += PLAN_BLOCK) atomicAdd(&rd.tot[rd.spatch[i]], 1);
     }
-    __syncthreads();
+    if (lds) {
+        __syncthreads();
+        for (int p = tid; p < np; p += BLOCK) {
+            const int c = s_hist[p];
+            if (c) atomicAdd(&rd.tot[p], c);
+        }
+    }
+}
+
+__global__ __launch_bounds__(PLAN_BLOCK) void relayout_plan_kernel(const RunDev *__restrict__ runs,
+                                                                   const int *__restrict__ slots)
+{
+    const RunDev &rd = runs[slots[blockIdx.x]];
+    __shared__ long long buf[PLAN_BLOCK];
+    const int tid = threadIdx.x;
+    if (!rd.ctl->relayout) return;
+    const int np = rd.n_patch;
     const int cs = rd.seg_cap > 0 ? rd.seg_cap : 1;
     const int chunk = (np + PLAN_BLOCK - 1) / PLAN_BLOCK;
     const int p0 = tid * chunk, p1 = min(np, p0 + chunk);
@@ -668,14 +701,23 @@ __global__ __launch_bounds__(BLOCK) void kinetic_kernel(const RunDev *__restrict
 }
 
 // ---------------------------------------------------------------- charge density
+// rho = sum q w S(X - node) at the primal nodes (quadratic shapes).  A
+// particle of a patch with origin p0 and edge P touches nodes p0-1 ..
+// p0+P+1 per axis, so a segment's charge is first summed in an LDS tile of
+// (P+3)^DIM nodes and then added into the global array once per node (one
+// global atomic per tile node instead of 3^DIM per particle).  Parked
+// particles, and any particle found outside its patch's tile, add straight
+// into the global array.  The deterministic mode sums 64-bit fixed-point
+// charges (see to_fixed) in both places.
+// nodes of the largest tile: (P+3)^2 = 1225 for P <= 32 in 2D, (P+3)^3 = 1331
+// for P <= 8 in 3D
+constexpr int RHO_TILE_ALLOC = 11 * 11 * 11;
+static_assert(35 * 35 <= RHO_TILE_ALLOC, "2D charge tile");
+
 template <int DIM, class T>
-__device__ __forceinline__ void rho_one(const RunDev &rd, const Store &s, long long i, int q, double *rho)
+__device__ __forceinline__ void rho_weights(const RunDev &rd, const Part<T> &p, int q, int base[3], double wt[3][3])
 {
-    Part<T> p;
-    load_part<DIM, T>(s, i, p);
     const int pq[3] = {q % rd.np[0], (q / rd.np[0]) % rd.np[1], DIM == 3 ? q / (rd.np[0] * rd.np[1]) : 0};
-    int base[3] = {0, 0, 0};
-    double wt[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         double X;
@@ -687,6 +729,23 @@ __device__ __forceinline__ void rho_one(const RunDev &rd, const Store &s, long l
         base[a] = (int)f - 1;
         shape3(X - f, wt[a][0], wt[a][1], wt[a][2]);
     }
+}
+
+__device__ __forceinline__ void rho_add(double *dst, double v, const RunDev &rd)
+{
+    if (rd.det)
+        atomicAdd((unsigned long long *)dst, to_fixed(v * rd.rscale));
+    else
+        atomicAdd(dst, v);
+}
+
+// one particle straight into the global array
+template <int DIM, class T>
+__device__ __forceinline__ void rho_global(const RunDev &rd, const Part<T> &p, int q, double *rho)
+{
+    int base[3] = {0, 0, 0};
+    double wt[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
+    rho_weights<DIM, T>(rd, p, q, base, wt);
     const double qw = rd.q * (double)p.w;
     const int nk = DIM == 3 ? 3 : 1;
     for (int k = 0; k < nk; ++k)
@@ -695,11 +754,7 @@ __device__ __forceinline__ void rho_one(const RunDev &rd, const Store &s, long l
                 const int gi = wrap1(base[0] + ii, rd.n[0]), gj = wrap1(base[1] + j, rd.n[1]);
                 const int gk = DIM == 3 ? wrap1(base[2] + k, rd.n[2]) : 0;
                 const double v = qw * wt[0][ii] * wt[1][j] * (DIM == 3 ? wt[2][k] : 1.0);
-                double *dst = &rho[gi + (long long)rd.n[0] * (gj + (long long)rd.n[1] * gk)];
-                if (rd.det)   // deterministic mode: 64-bit fixed point (see to_fixed)
-                    atomicAdd((unsigned long long *)dst, to_fixed(v * rd.rscale));
-                else
-                    atomicAdd(dst, v);
+                rho_add(&rho[gi + (long long)rd.n[0] * (gj + (long long)rd.n[1] * gk)], v, rd);
             }
 }
 
@@ -708,16 +763,66 @@ __global__ __launch_bounds__(BLOCK) void rho_kernel(const RunDev *__restrict__ r
                                                     double *__restrict__ rho)
 {
     const RunDev &rd = runs[run];
-    if ((int)blockIdx.x < rd.seg_max) {
-        const int sg = blockIdx.x;
-        if (sg >= rd.ctl->nseg) return;
-        const int cap = rd.sseg[sg + 1] - rd.sseg[sg];
-        const int r = min(rd.scnt[sg], cap);
-        const int q = rd.spat[sg];
-        for (int i = threadIdx.x; i < r; i += BLOCK) rho_one<DIM, T>(rd, rd.st, (long long)rd.sseg[sg] + i, q, rho);
+    if ((int)blockIdx.x >= rd.seg_max) {
+        for (int i = threadIdx.x; i < nspill; i += BLOCK) {
+            Part<T> p;
+            load_part<DIM, T>(rd.sp, i, p);
+            rho_global<DIM, T>(rd, p, rd.spatch[i], rho);
+        }
         return;
     }
-    for (int i = threadIdx.x; i < nspill; i += BLOCK) rho_one<DIM, T>(rd, rd.sp, i, rd.spatch[i], rho);
+    const int sg = blockIdx.x;
+    if (sg >= rd.ctl->nseg) return;
+    __shared__ double s_r[RHO_TILE_ALLOC];
+    const int cap = rd.sseg[sg + 1] - rd.sseg[sg];
+    const int r = min(rd.scnt[sg], cap);
+    if (r <= 0) return;
+    const int q = rd.spat[sg];
+    const int P[3] = {rd.P[0], rd.P[1], DIM == 3 ? rd.P[2] : 1};
+    const int E0 = P[0] + 3, E1 = P[1] + 3, E2 = DIM == 3 ? P[2] + 3 : 1;   // tile extent
+    const int pq[3] = {q % rd.np[0], (q / rd.np[0]) % rd.np[1], DIM == 3 ? q / (rd.np[0] * rd.np[1]) : 0};
+    const int o[3] = {pq[0] * P[0] - 1, pq[1] * P[1] - 1, DIM == 3 ? pq[2] * P[2] - 1 : 0};   // tile origin
+    for (int t = threadIdx.x; t < E0 * E1 * E2; t += BLOCK) s_r[t] = 0.0;   // also the integer 0
+    __syncthreads();
+    const double qw0 = rd.q;
+    for (int i = threadIdx.x; i < r; i += BLOCK) {
+        Part<T> p;
+        load_part<DIM, T>(rd.st, (long long)rd.sseg[sg] + i, p);
+        int base[3] = {0, 0, 0};
+        double wt[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
+        rho_weights<DIM, T>(rd, p, q, base, wt);
+        const int l0 = base[0] - o[0], l1 = base[1] - o[1], l2 = DIM == 3 ? base[2] - o[2] : 0;
+        if (l0 < 0 || l0 + 2 >= E0 || l1 < 0 || l1 + 2 >= E1 || (DIM == 3 && (l2 < 0 || l2 + 2 >= E2))) {
+            rho_global<DIM, T>(rd, p, q, rho);   // not inside the patch's tile
+            continue;
+        }
+        const double qw = qw0 * (double)p.w;
+        const int nk = DIM == 3 ? 3 : 1;
+        for (int k = 0; k < nk; ++k)
+            for (int j = 0; j < 3; ++j)
+                for (int ii = 0; ii < 3; ++ii) {
+                    const double v = qw * wt[0][ii] * wt[1][j] * (DIM == 3 ? wt[2][k] : 1.0);
+                    double *dst = &s_r[((l2 + k) * E1 + (l1 + j)) * E0 + l0 + ii];
+                    if (rd.det)
+                        atomicAdd((unsigned long long *)dst, to_fixed(v * rd.rscale));
+                    else
+                        atomicAdd(dst, v);
+                }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < E0 * E1 * E2; t += BLOCK) {
+        const int a0 = t % E0, a1 = (t / E0) % E1, a2 = t / (E0 * E1);
+        const int gi = wrap1(o[0] + a0, rd.n[0]), gj = wrap1(o[1] + a1, rd.n[1]);
+        const int gk = DIM == 3 ? wrap1(o[2] + a2, rd.n[2]) : 0;
+        double *dst = &rho[gi + (long long)rd.n[0] * (gj + (long long)rd.n[1] * gk)];
+        if (rd.det) {
+            const unsigned long long v = ((const unsigned long long *)s_r)[t];
+            if (v) atomicAdd((unsigned long long *)dst, v);
+        } else {
+            const double v = s_r[t];
+            if (v != 0.0) atomicAdd(dst, v);
+        }
+    }
 }
 
 __global__ void fill_kernel(double *p, long long n, double v)
@@ -761,12 +866,18 @@ static int spill_blocks(int n_total)
     return b < 1 ? 1 : (b > 1024 ? 1024 : b);
 }
 
-hipError_t launch_relayout(int dims, bool split, RunDev *runs, const int *slots, int n_slots, int move_gx,
-                           int commit_gx, int force, hipStream_t s)
+hipError_t launch_relayout(int dims, bool split, RunDev *runs, const int *slots, int n_slots, int count_gx,
+                           int move_gx, int commit_gx, int force, hipStream_t s)
 {
     if (n_slots <= 0) return hipSuccess;
-    relayout_plan_kernel<<<n_slots, PLAN_BLOCK, 0, s>>>(runs, slots, force);
+    relayout_tally_kernel<<<n_slots, PLAN_BLOCK, 0, s>>>(runs, slots, force);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    relayout_count_kernel<<<dim3(count_gx < 1 ? 1 : count_gx, n_slots), BLOCK, 0, s>>>(runs, slots);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    relayout_plan_kernel<<<n_slots, PLAN_BLOCK, 0, s>>>(runs, slots);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
 #define RELAYOUT_BODY(D, TT)                                                                   \
     relayout_move_kernel<D, TT><<<dim3(move_gx, n_slots), BLOCK, 0, s>>>(runs, slots);         \

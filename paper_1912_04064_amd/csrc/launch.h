@@ -48,9 +48,11 @@ hipError_t launch_convert(int dims, bool split, const RunDev *runs, int run, int
                           const double *z, const double *ux, const double *uy, const double *uz, const double *w,
                           const uint32_t *id, hipStream_t s);
 // re-layout of the patch stores of the runs listed in slots[0..n_slots)
-// (plan / move / commit); force = 1 re-lays out even without parked particles
-hipError_t launch_relayout(int dims, bool split, RunDev *runs, const int *slots, int n_slots, int move_gx,
-                           int commit_gx, int force, hipStream_t s);
+// (tally / count parked / plan / move / commit); force = 1 re-lays out even
+// without parked particles; count_gx workgroups per run count the parked
+// particles
+hipError_t launch_relayout(int dims, bool split, RunDev *runs, const int *slots, int n_slots, int count_gx,
+                           int move_gx, int commit_gx, int force, hipStream_t s);
 // export: live particles -> FP64 arrays at per-segment offsets (off[nseg]
 // = start of the spill part)
 hipError_t launch_export(int dims, bool split, const RunDev *runs, int run, int seg_max, int nspill, const int *off,

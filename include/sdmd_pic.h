@@ -265,6 +265,12 @@ typedef struct {
                                          sums (0 otherwise)                */
     int32_t seg_cap;                  /* segment capacity in use           */
     int32_t reserved;
+    double  t_push_kernel_ms;         /* the particle kernels' own duration
+                                         per step over the last
+                                         pic_time_phases call (events tied to
+                                         their launches: kernel start to
+                                         kernel end, without the dispatch
+                                         gaps that t_ms[0] includes)       */
 } pic_diag_t;
 
 /* Particle export (host memory, caller owned).  capacity is the length of

@@ -85,7 +85,8 @@ class PicDiag(C.Structure):
                 ("K", C.c_double), ("t_ms", C.c_double * 4), ("n_relayout", C.c_int64), ("n_spill", C.c_int64),
                 ("err_flags", C.c_int32), ("patch", C.c_int32 * 3), ("gauss_residual", C.c_double),
                 ("kernel_path", C.c_int32 * 4), ("device_bytes", C.c_int64), ("device_bytes_peak", C.c_int64),
-                ("det_quantum", C.c_double * 2), ("seg_cap", C.c_int32), ("reserved", C.c_int32)]
+                ("det_quantum", C.c_double * 2), ("seg_cap", C.c_int32), ("reserved", C.c_int32),
+                ("t_push_kernel_ms", C.c_double)]
 
 
 class PicParticlesOut(C.Structure):

@@ -107,6 +107,7 @@ struct pic_ctx {
     size_t peak_bytes = 0;   // the most held since pic_init
     std::string err;
     double t_ms[4] = {0, 0, 0, 0};
+    double t_push_kernel_ms = 0.0;   // the particle kernels' own duration per step (last pic_time_phases)
 };
 
 // ------------------------------------------------------------------ errors
@@ -1031,10 +1032,16 @@ static int rebuild_items(pic_ctx *c)
 }
 
 // ------------------------------------------------------------------ stepping
-static hipError_t enqueue_push(pic_ctx *c, int par, hipStream_t s)
+// ev0 / ev1 (may be null): recorded at the start of the first particle
+// kernel and at the end of the last one
+static hipError_t enqueue_push(pic_ctx *c, int par, hipStream_t s, hipEvent_t ev0 = nullptr,
+                               hipEvent_t ev1 = nullptr)
 {
-    for (auto &pc : c->pcls) {
-        hipError_t e = launch_push(pc.dims, pc.split, pc.px, pc.pc, c->det, c->d_runs, pc.d, (int)pc.h.size(), par, s);
+    const size_t nc = c->pcls.size();
+    for (size_t k = 0; k < nc; ++k) {
+        auto &pc = c->pcls[k];
+        hipError_t e = launch_push(pc.dims, pc.split, pc.px, pc.pc, c->det, c->d_runs, pc.d, (int)pc.h.size(), par, s,
+                                   k == 0 ? ev0 : nullptr, k + 1 == nc ? ev1 : nullptr);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1333,7 +1340,10 @@ int pic_time_phases(pic_ctx *c, int32_t n_steps)
     // normal step (the host stays ahead of the device), and the stream
     // waits ~200 us first while the host enqueues the opening steps, so
     // each interval holds its kernels only
-    std::vector<hipEvent_t> ev(4 * (size_t)n_steps + 1);
+    // phase events (4 per step and one more) and the particle kernel's own
+    // start / end events (2 per step)
+    std::vector<hipEvent_t> ev(6 * (size_t)n_steps + 1);
+    const size_t kbase = 4 * (size_t)n_steps + 1;
     size_t made = 0;
     int rc = PIC_OK;
     for (; made < ev.size(); ++made)
@@ -1344,7 +1354,7 @@ int pic_time_phases(pic_ctx *c, int32_t n_steps)
     if (e == hipSuccess) e = hipEventRecord(ev[0], c->stream);
     for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
         hipEvent_t *q = &ev[4 * (size_t)k];
-        e = enqueue_push(c, c->par, c->stream);
+        e = enqueue_push(c, c->par, c->stream, ev[kbase + 2 * (size_t)k], ev[kbase + 2 * (size_t)k + 1]);
         if (e == hipSuccess) e = hipEventRecord(q[1], c->stream);
         if (e == hipSuccess) e = enqueue_yee(c, c->par, c->stream);
         if (e == hipSuccess) e = hipEventRecord(q[2], c->stream);
@@ -1355,16 +1365,21 @@ int pic_time_phases(pic_ctx *c, int32_t n_steps)
         if (c->step % c->relayout_every == 0) e = enqueue_relayout(c, c->stream);
         if (e == hipSuccess) e = hipEventRecord(q[4], c->stream);
     }
-    if (e == hipSuccess) e = hipEventSynchronize(ev.back());
+    if (e == hipSuccess) e = hipEventSynchronize(ev[4 * (size_t)n_steps]);
     if (e == hipSuccess) {
-        double sum[4] = {0, 0, 0, 0};
-        for (int k = 0; k < n_steps; ++k)
+        double sum[4] = {0, 0, 0, 0}, kern = 0.0;
+        for (int k = 0; k < n_steps; ++k) {
             for (int i = 0; i < 4; ++i) {
                 float ms = 0;
                 hipEventElapsedTime(&ms, ev[4 * (size_t)k + i], ev[4 * (size_t)k + i + 1]);
                 sum[i] += ms;
             }
+            float ms = 0;
+            hipEventElapsedTime(&ms, ev[kbase + 2 * (size_t)k], ev[kbase + 2 * (size_t)k + 1]);
+            kern += ms;
+        }
         for (int i = 0; i < 4; ++i) c->t_ms[i] = sum[i] / n_steps;
+        c->t_push_kernel_ms = kern / n_steps;
     } else {
         rc = fail_dev(e);
     }
@@ -1539,6 +1554,7 @@ static int diag_impl(pic_ctx *c, int32_t run, pic_diag_t *out, const DiagScratch
     out->U_B = 0.5 * ub * dV;
     out->K = k * dV;
     for (int i = 0; i < 4; ++i) out->t_ms[i] = c->t_ms[i];
+    out->t_push_kernel_ms = c->t_push_kernel_ms;
     {
         // Gauss-law residual against the initial state
         double *gb = ds.gb;

@@ -24,6 +24,8 @@
 // Particles parked in the spill store that belong to this patch are pushed
 // here too (by the patch's first segment) and re-enter through the overflow
 // leaver store.  A segment with nothing to push skips all of this.
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "launch.h"
@@ -875,19 +877,34 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     if (tid == 0) tflag[sg] = 1;
 }
 
-#define PUSH_CASE(D, TT, PXV, PCV)                                                                      \
-    if (dims == D && split == TT::split && px == PXV && pc == PCV) {                                    \
-        if (det)                                                                                        \
-            push_kernel<D, TT, PXV, PCV, true><<<n_items, push_block<D, TT>(), 0, s>>>(runs, items, par);  \
-        else                                                                                            \
-            push_kernel<D, TT, PXV, PCV, false><<<n_items, push_block<D, TT>(), 0, s>>>(runs, items, par); \
-        return hipGetLastError();                                                                       \
+// With events, the launch goes through hipExtLaunchKernelGGL, which records
+// ev0 when the kernel starts and ev1 when it ends (its own duration, without
+// the dispatch gap that events recorded between launches include).
+template <class K>
+static hipError_t push_launch(K kern, int n_items, int block, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                              const RunDev *runs, const int2 *items, int par)
+{
+    if (ev0 || ev1)
+        hipExtLaunchKernelGGL(kern, dim3(n_items), dim3(block), 0, s, ev0, ev1, 0, runs, items, par);
+    else
+        kern<<<n_items, block, 0, s>>>(runs, items, par);
+    return hipGetLastError();
+}
+
+#define PUSH_CASE(D, TT, PXV, PCV)                                                                  \
+    if (dims == D && split == TT::split && px == PXV && pc == PCV) {                                \
+        if (det)                                                                                    \
+            return push_launch(push_kernel<D, TT, PXV, PCV, true>, n_items, push_block<D, TT>(), s, \
+                               ev0, ev1, runs, items, par);                                         \
+        return push_launch(push_kernel<D, TT, PXV, PCV, false>, n_items, push_block<D, TT>(), s,    \
+                           ev0, ev1, runs, items, par);                                             \
     }
 
 // px: exact square/cubic patch edge with a compiled fast path, else 0;
-// pc: LDS sizing class 8 / 16 / 32; det: deterministic mode
+// pc: LDS sizing class 8 / 16 / 32; det: deterministic mode; ev0 / ev1:
+// events recorded at the kernel's start and end (may be null)
 hipError_t launch_push(int dims, bool split, int px, int pc, bool det, const RunDev *runs, const int2 *items,
-                       int n_items, int par, hipStream_t s)
+                       int n_items, int par, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (n_items <= 0) return hipSuccess;
     PUSH_CASE(2, F32S, 8, 8)

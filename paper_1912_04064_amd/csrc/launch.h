@@ -11,7 +11,7 @@ namespace sdmd {
 // px: exact square/cubic patch edge of a compiled fast path (0 = sizes read
 // from the run descriptor); pc: LDS sizing class 8 / 16 / 32
 hipError_t launch_push(int dims, bool split, int px, int pc, bool det, const RunDev *runs, const int2 *items,
-                       int n_items, int par, hipStream_t s);
+                       int n_items, int par, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // transfer (i) + current filter + Maxwell: items (run, region, tile,
 // first-item-of-run flag); tx: x extent of the tile, from

@@ -75,3 +75,91 @@ def kernel_table(trace: List[dict]) -> List[dict]:
              "total_ms": sum(v) * 1e-3, "pct": 100.0 * sum(v) / tot} for k, v in by.items()]
     rows.sort(key=lambda r: -r["total_ms"])
     return rows
+
+
+def copy_scale(recs: List[dict], counter: str, bytes_copied: int) -> Optional[float]:
+    """Bytes per counter unit from the plain device copy of known size that
+    ``bench.py --calib-copy`` runs first: the largest copy dispatch of the
+    run (FETCH_SIZE and WRITE_SIZE count KiB)."""
+    cands = [r for r in recs if "copy" in r["kernel"].lower() and counter in r["counters"]]
+    if not cands:
+        return None
+    r = max(cands, key=lambda x: x["counters"][counter])
+    v = r["counters"][counter]
+    return bytes_copied / (v * 1024.0) if v > 0 else None
+
+
+def window_record(fetch_csv: str, write_csv: str, sq_csv: Optional[str], launches: int,
+                  copy_bytes: int = 512 << 20) -> dict:
+    """Counter figures of the particle kernel over its last `launches`
+    dispatches (the benchmark's replayed window): HBM bytes per launch from
+    FETCH_SIZE and WRITE_SIZE scaled by the calibration copy, and the SQ
+    instruction counts per launch when an SQ pass is given."""
+    F, W = read_counters(fetch_csv), read_counters(write_csv)
+    fs, ws = copy_scale(F, "FETCH_SIZE", copy_bytes), copy_scale(W, "WRITE_SIZE", copy_bytes)
+    mf = mean_counters(select(F, "push_kernel", last=launches))
+    mw = mean_counters(select(W, "push_kernel", last=launches))
+    rec = {"launches": launches, "fetch_kib": mf.get("FETCH_SIZE"), "write_kib": mw.get("WRITE_SIZE"),
+           "fetch_scale": fs, "write_scale": ws}
+    if fs and ws and rec["fetch_kib"] is not None and rec["write_kib"] is not None:
+        rec["bytes_per_launch"] = rec["fetch_kib"] * 1024.0 * fs + rec["write_kib"] * 1024.0 * ws
+    if sq_csv:
+        ms = mean_counters(select(read_counters(sq_csv), "push_kernel", last=launches))
+        for k in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_WAVES", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS",
+                  "SQ_WAIT_INST_LDS", "SQ_WAVE_CYCLES", "SQ_LDS_IDX_ACTIVE"):
+            if k in ms:
+                rec[k] = ms[k]
+        if "SQ_INSTS_VALU" in ms:
+            rec["valu_insts_per_launch"] = ms["SQ_INSTS_VALU"]
+    return rec
+
+
+def _main(argv=None):
+    import argparse
+    import json
+    import os
+    import sys
+    ap = argparse.ArgumentParser(description="summaries of rocprofv3 output for profiles/")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    w = sub.add_parser("window", help="particle-kernel counters of a step window -> traffic.json")
+    w.add_argument("--workload", required=True)
+    w.add_argument("--first", type=int, required=True)
+    w.add_argument("--last", type=int, required=True)
+    w.add_argument("--fetch", required=True)
+    w.add_argument("--write", required=True)
+    w.add_argument("--sq")
+    w.add_argument("--out", required=True)
+    w.add_argument("--command", default="")
+    t = sub.add_parser("trace", help="kernel table of a --kernel-trace run (markdown)")
+    t.add_argument("csv")
+    a = ap.parse_args(argv)
+    if a.cmd == "trace":
+        print("| kernel | calls | avg µs | min µs | max µs | total ms | % |\n|---|---|---|---|---|---|---|")
+        for r in kernel_table(read_trace(a.csv)):
+            name = r["kernel"].split("(")[0].replace("void ", "")
+            print(f"| `{name}` | {r['calls']} | {r['avg_us']:.1f} | {r['min_us']:.1f} | {r['max_us']:.1f} | "
+                  f"{r['total_ms']:.2f} | {r['pct']:.1f} |")
+        return 0
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, here)
+    import bench
+    rec = window_record(a.fetch, a.write, a.sq, a.last - a.first)
+    rec["command"] = a.command
+    data = json.load(open(a.out)) if os.path.exists(a.out) else {}
+    pk = data.setdefault("push_kernel", {})
+    sha = bench.kernel_source_hash()
+    if pk.get("workload") != a.workload or pk.get("source_sha") != sha:
+        pk.clear()
+    pk["workload"] = a.workload
+    pk["source_sha"] = sha
+    pk["source_sha_note"] = ("sha256 of k_push.hip, part.h, sdmd_dev.h with comments and whitespace removed "
+                             "(bench.kernel_source_hash)")
+    pk.setdefault("windows", {})[f"{a.first}-{a.last}"] = rec
+    with open(a.out, "w") as f:
+        json.dump(data, f, indent=1)
+    print(json.dumps(rec, indent=1))
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(_main())

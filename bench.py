@@ -67,6 +67,27 @@ def particle_bytes(wl):
 VALU_PEAK = 256 * 2.4e9   # wavefront VALU instructions per second (no packed FP32)
 
 
+def copy_bandwidth(torch, gib=1.0, reps=5):
+    """HBM bandwidth a plain device-to-device copy reaches on this GPU (read +
+    write bytes over the copy's own time, best of `reps`): the practical
+    ceiling a streaming kernel is measured against beside the 8 TB/s peak."""
+    n = int(gib * (1 << 30)) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 / (best * 1e-3) / 1e9
+
+
 def valu_line(insts, launch_ms):
     if insts is None:
         return None
@@ -518,6 +539,12 @@ def main():
                    "rel_change": (d["U_E"] + d["U_B"] + d["K"]) / (d0["U_E"] + d0["U_B"] + d0["K"]) - 1.0,
                    "gauss_residual": d["gauss_residual"]},
     }
+    # the same kernel against what a plain copy reaches on this GPU (not in
+    # counter runs, whose calibration copy must stay the largest copy)
+    if not args.calib_copy:
+        cbw = copy_bandwidth(torch)
+        out["roofline"]["achievable_copy_GBps"] = cbw
+        out["roofline"]["frac_of_copy"] = achieved / cbw
     if not args.no_full_run and wl.steps > 0:
         # the workload's whole trajectory (its configured step count, the
         # laser entering the plasma and the wake forming): the same figures

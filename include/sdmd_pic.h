@@ -292,16 +292,51 @@ typedef struct {
  * of the broken rule is in pic_last_error(NULL). */
 int pic_init(const pic_config *cfgs, int32_t n_runs, const pic_runtime *rt, pic_ctx **out);
 
-/* Enqueue n_steps SDMD steps for every active run on rt->stream (async). */
+/* Enqueue n_steps SDMD steps for every active run on rt->stream and return
+ * without waiting.  One step is the iteration of sections 2.2 and 3.3 of the
+ * paper on the two decompositions of one domain: per patch, interpolation
+ * of E^n and Bm^n from the patch's copy of its region's fields, push and
+ * Esirkepov order-2 deposition into the patch's own current tile (the
+ * "Particles" timer of section 3.3; methods of section 3.2); transfer (i),
+ * every patch tile summed into its region, optionally smoothed by the
+ * binomial filter; the Maxwell solve (Yee, or the spectral solver) on each
+ * region, with ghost layers exchanged between regions; transfer (ii), each
+ * region's new fields copied into the windows of its patches; and the
+ * particles that left their patch moved to the patch that now holds them.
+ * Runs that have reached their max_steps stay as they are.
+ * n_steps: >= 0 (0 does nothing).  Returns PIC_OK once the work is
+ * enqueued, PIC_E_INVAL for a null context or n_steps < 0, PIC_E_DEVICE if
+ * a launch fails.  Errors the kernels detect while stepping (a position
+ * outside [0, L), a non-finite value, a move of a cell or more in one step,
+ * a store overflow) are latched per run on the device and returned by the
+ * next synchronising call on that run (pic_fields, pic_diag, pic_particles)
+ * as PIC_E_CONFIG, PIC_E_NUMERIC or PIC_E_OVERFLOW. */
 int pic_step(pic_ctx *ctx, int32_t n_steps);
 
-/* Copy the fields of `run` selected by `mask` (PIC_F_*) into dst,
- * components in bit order, each nx*ny*nz FP64 values, layout above.
- * dst_len is the capacity of dst in doubles; dst_on_device != 0 means dst is
- * device memory.  Synchronises the stream. */
+/* Read the fields of `run` as the undecomposed grid of section 2.1 would
+ * hold them: the regions that own the fields in SDMD (section 2.2) are
+ * assembled into one array, ghost layers dropped.  mask selects components
+ * (PIC_F_*); they are written to dst in bit order, each nx*ny*nz FP64 values
+ * in the layout above (x fastest, staggering as listed there).  dst is
+ * caller owned, host memory, or device memory when dst_on_device != 0;
+ * dst_len is its capacity in doubles (PIC_E_INVAL if it is too small, or for
+ * a null pointer or a bad run).  Synchronises the stream and reports the
+ * run's latched kernel errors (see pic_step). */
 int pic_fields(pic_ctx *ctx, int32_t run, uint32_t mask, double *dst, size_t dst_len, int32_t dst_on_device);
 
-/* Fill *out for `run`.  Synchronises the stream. */
+/* Fill *out (caller owned) for `run`: step count, particle count, the
+ * energies of fields and electrons (the energy balance an explicit PIC
+ * scheme is checked with), the Gauss-law residual div E - rho against its
+ * initial value (charge conservation of the Esirkepov deposition, section
+ * 3.2), the patch size of section 2.2's fine decomposition and the split
+ * of dense patches into several work items that section 4 proposes
+ * (segments), re-layout and spill counts, the compiled kernel path, memory
+ * and, after pic_time_phases, the per-phase times that correspond to the
+ * timers of section 3.3.  Allocates device scratch for the charge density
+ * and the residual (16 bytes per cell) and frees it before returning;
+ * PIC_E_NOMEM if that fails or would exceed hbm_budget, PIC_E_INVAL for
+ * null pointers or a bad run.  Synchronises the stream and reports the
+ * run's latched kernel errors (see pic_step). */
 int pic_diag(pic_ctx *ctx, int32_t run, pic_diag_t *out);
 
 /* pic_diag without any device allocation, for callers that cannot allocate

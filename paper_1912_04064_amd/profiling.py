@@ -89,12 +89,19 @@ def copy_scale(recs: List[dict], counter: str, bytes_copied: int) -> Optional[fl
     return bytes_copied / (v * 1024.0) if v > 0 else None
 
 
+LDS_COUNTERS = ("SQ_INSTS_LDS_ATOMIC", "SQ_INSTS_LDS_LOAD", "SQ_INSTS_LDS_STORE", "SQ_INSTS_LDS_ATOMIC_BANDWIDTH",
+                "SQ_INSTS_LDS_LOAD_BANDWIDTH", "SQ_INSTS_LDS_STORE_BANDWIDTH", "SQ_LDS_ADDR_CONFLICT",
+                "SQ_LDS_DATA_FIFO_FULL")
+
+
 def window_record(fetch_csv: str, write_csv: str, sq_csv: Optional[str], launches: int,
-                  copy_bytes: int = 512 << 20) -> dict:
+                  copy_bytes: int = 512 << 20, lds_csv: Optional[str] = None) -> dict:
     """Counter figures of the particle kernel over its last `launches`
     dispatches (the benchmark's replayed window): HBM bytes per launch from
-    FETCH_SIZE and WRITE_SIZE scaled by the calibration copy, and the SQ
-    instruction counts per launch when an SQ pass is given."""
+    FETCH_SIZE and WRITE_SIZE scaled by the calibration copy, the SQ
+    instruction counts per launch when an SQ pass is given, and the LDS
+    instruction mix (loads, stores, atomics and their bandwidth counters)
+    when an LDS pass is given."""
     F, W = read_counters(fetch_csv), read_counters(write_csv)
     fs, ws = copy_scale(F, "FETCH_SIZE", copy_bytes), copy_scale(W, "WRITE_SIZE", copy_bytes)
     mf = mean_counters(select(F, "push_kernel", last=launches))
@@ -111,7 +118,17 @@ def window_record(fetch_csv: str, write_csv: str, sq_csv: Optional[str], launche
                 rec[k] = ms[k]
         if "SQ_INSTS_VALU" in ms:
             rec["valu_insts_per_launch"] = ms["SQ_INSTS_VALU"]
+    if lds_csv:
+        ml = mean_counters(select(read_counters(lds_csv), "push_kernel", last=launches))
+        for k in LDS_COUNTERS:
+            if k in ml:
+                rec[k] = ml[k]
     return rec
+
+
+def counter_table(csv_path: str, kernel: str, last: int) -> List[tuple]:
+    """(counter, per-dispatch mean) of `kernel`'s last `last` dispatches."""
+    return sorted(mean_counters(select(read_counters(csv_path), kernel, last=last)).items())
 
 
 def _main(argv=None):
@@ -128,11 +145,21 @@ def _main(argv=None):
     w.add_argument("--fetch", required=True)
     w.add_argument("--write", required=True)
     w.add_argument("--sq")
+    w.add_argument("--lds")
     w.add_argument("--out", required=True)
     w.add_argument("--command", default="")
     t = sub.add_parser("trace", help="kernel table of a --kernel-trace run (markdown)")
     t.add_argument("csv")
+    c = sub.add_parser("counters", help="mean counters of one kernel's last launches (markdown)")
+    c.add_argument("csv")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--last", type=int, required=True)
     a = ap.parse_args(argv)
+    if a.cmd == "counters":
+        print(f"| counter | mean per launch ({a.kernel}, last {a.last}) |\n|---|---|")
+        for k, v in counter_table(a.csv, a.kernel, a.last):
+            print(f"| {k} | {v:.6g} |")
+        return 0
     if a.cmd == "trace":
         print("| kernel | calls | avg µs | min µs | max µs | total ms | % |\n|---|---|---|---|---|---|---|")
         for r in kernel_table(read_trace(a.csv)):
@@ -143,7 +170,7 @@ def _main(argv=None):
     here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     sys.path.insert(0, here)
     import bench
-    rec = window_record(a.fetch, a.write, a.sq, a.last - a.first)
+    rec = window_record(a.fetch, a.write, a.sq, a.last - a.first, lds_csv=a.lds)
     rec["command"] = a.command
     data = json.load(open(a.out)) if os.path.exists(a.out) else {}
     pk = data.setdefault("push_kernel", {})

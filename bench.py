@@ -375,7 +375,7 @@ def bench_sdsd(args):
         for mode in ("sdmd", "sdsd"):
             nreg = (4, 1) if mode == "sdmd" else (base.n[0] // P, base.n[1] // P)
             wl = dataclasses.replace(base, patch=(P, P), nreg=nreg)
-            ctx = B.Context([wl], graph=not args.no_graph)
+            ctx = B.Context([wl], graph=not args.no_graph, deterministic=args.deterministic)
             ctx.step(args.warmup)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -402,6 +402,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="lwfa")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="deterministic mode (fixed-point current sums, bitwise reproducible)")
     ap.add_argument("--phase-samples", type=int, default=0,
                     help="steps of the timed trajectory replayed with per-kernel events (0 = all)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -453,7 +455,7 @@ def main():
     N = wl.n_particles
     ncell = wl.n_cells
     print(f"[bench] workload {wl.name}: {N} particles, {ncell} cells, {wl.precision}", file=sys.stderr, flush=True)
-    ctx = B.Context([wl], graph=not args.no_graph)
+    ctx = B.Context([wl], graph=not args.no_graph, deterministic=args.deterministic)
     ctx.step(args.warmup)
     torch.cuda.synchronize()
     print(f"[bench] warmup {args.warmup} steps done", file=sys.stderr, flush=True)
@@ -477,7 +479,7 @@ def main():
         """Per-phase kernel times over steps [warm, warm + n) of the same
         trajectory, replayed from the same input with HIP events between the
         phases on the library's stream (kernels back to back)."""
-        c = B.Context([wl], graph=not args.no_graph)
+        c = B.Context([wl], graph=not args.no_graph, deterministic=args.deterministic)
         c.step(warm)
         c.time_phases(n)
         dd = c.diag(0)
@@ -491,7 +493,8 @@ def main():
     push_ph, yee_avg, post_avg, rel_avg, push_avg = replay(args.warmup, nph)
     achieved = alg_push / (push_avg * 1e-3) / 1e9
     step_bytes = N * pb + ncell * 216
-    ctr = push_counters(args.workload, first, last) if nph == args.steps else None
+    # (the counters were taken on the plain kernels, not the fixed-point ones)
+    ctr = push_counters(args.workload, first, last) if nph == args.steps and not args.deterministic else None
 
     # the whole step against HBM: the survey's per-push bytes (52 B of
     # split-form particle traffic with a 4-byte cell index + 216 B of FP64
@@ -516,7 +519,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "cells": list(wl.n), "particles": N, "patch": list(d["patch"][:wl.dims]),
                    "regions": list(wl.nreg), "precision": wl.precision, "solver": wl.solver, "filter": wl.filter,
-                   "graph": not args.no_graph, "run_steps": wl.steps},
+                   "graph": not args.no_graph, "run_steps": wl.steps, "deterministic": args.deterministic},
         "step_hbm_GBps_algorithmic": step_bytes / (ms * 1e-3) / 1e9,
         "step_roofline": {"bytes_per_push": bpp_step, "roofline": step_roof, "unit": "particle-pushes/s",
                           "frac": value / step_roof},
@@ -553,7 +556,7 @@ def main():
         # handed over in host arrays, copied to HBM and binned) timed apart
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        c = B.Context([wl], graph=not args.no_graph)
+        c = B.Context([wl], graph=not args.no_graph, deterministic=args.deterministic)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - ts
         t0 = time.perf_counter()
@@ -564,7 +567,7 @@ def main():
         c.close()
         fph, fy, fq, fr, fp = replay(0, wl.steps)
         fv = N * wl.steps / dtf
-        fctr = push_counters(args.workload, 0, wl.steps)
+        fctr = None if args.deterministic else push_counters(args.workload, 0, wl.steps)
         out["full_run"] = {
             "steps": [0, wl.steps], "value": fv, "ms_per_step": dtf * 1e3 / wl.steps,
             # the same run with its set-up from host buffers (PCIe copies,

@@ -722,6 +722,7 @@ static void fixed_point_scales(const pic_config *cfg, const Layout &L, RunDev &d
     double dmax = 1.0;
     for (int a = 0; a < L.dims; ++a) dmax = std::max(dmax, d.d[a] / cfg->dt);
     const double n = (double)std::max<long long>(L.n_total, 1);
+    d.junit = uq * dmax;
     d.jscale = fixed_scale(uq * dmax, n);
     d.jscale_inv = 1.0 / d.jscale;
     d.rscale = fixed_scale(uq, n);

@@ -10,14 +10,17 @@
 //      workgroup width, the next chunk prefetched): quadratic B-spline
 //      interpolation from the LDS window, Boris push, position update,
 //      Esirkepov order-2 deposition (section 3.2) into the segment's LDS
-//      current tile with FP64 LDS atomics (at most 40 adds in 2D, 144 in 3D:
-//      the 4-node sub-frame that holds both the old and new shapes; a
-//      3-node frame when no particle of the wavefront changes node, and
-//      structurally zero slots masked lane by lane);
+//      current tile with LDS atomics, 64-bit fixed point in the split form
+//      and the deterministic mode, FP64 in the plain FP64 form (at most 40
+//      adds in 2D, 144 in 3D: the 4-node sub-frame that holds both the old
+//      and new shapes; the 3-node core for every particle and the rest only
+//      for the particles that change node, structurally zero slots masked
+//      lane by lane);
 //   3. particles that stay are compacted in place in the patch segment;
 //      particles that leave go to the leaver store with their new patch;
-//   4. the LDS tile is written to the segment's tile slot in HBM, where the
-//      field kernel sums it into the region (transfer (i)).
+//   4. the LDS tile is written to the segment's tile slot in HBM (converted
+//      back to the particle precision from fixed point), where the field
+//      kernel sums it into the region (transfer (i)).
 // The work item is a segment: a patch denser than the segment cap is split
 // into several segments (the paper's task decomposition of one patch) that
 // load the same window and deposit into their own tiles.
@@ -123,16 +126,29 @@ __device__ __forceinline__ void esirkepov_axis_delta(R d0, R D, int ip, R S0[4],
     moved = up || dn;
 }
 
-// One contribution into the LDS tile: an FP64 atomic add, or in the
-// deterministic mode a 64-bit integer add of the contribution in fixed
-// point (js: the run's scale), whose sum does not depend on the order.
-template <bool DET>
+// One contribution into the LDS tile: an FP64 atomic add, or (FIX) a
+// 64-bit integer add of the contribution in fixed point (js: the scale),
+// whose sum does not depend on the order of the adds.
+template <bool FIX>
 __device__ __forceinline__ void tile_add(double *p, double v, double js)
 {
-    if constexpr (DET)
+    if constexpr (FIX)
         atomicAdd((unsigned long long *)p, to_fixed(v * js));
     else
         atomicAdd(p, v);
+}
+
+// Fixed-point scale of one segment's tile in the split form: a power of two
+// 2^e with unit * count * 2^e <= 2^62 and unit * 2^e <= 2^50, so that count
+// contributions of modulus at most unit sum without leaving the signed
+// 64-bit range and each scaled one stays exact in to_fixed.  The tile of a
+// segment receives at most one contribution per particle it pushes (its own
+// and the parked ones of its patch) per node and component.
+__device__ __forceinline__ double seg_fixed_scale(double unit, double count)
+{
+    if (!(unit > 0.0)) return 1.0;
+    const double lim = fmin(0x1p62 / (unit * fmax(count, 1.0)), 0x1p50 / unit);
+    return ldexp(1.0, ilogb(lim));
 }
 
 // Esirkepov deposition of one particle into the LDS tile.  On the 4-slot
@@ -155,7 +171,7 @@ __device__ __forceinline__ void tile_add(double *p, double v, double js)
 // S0u (S0v + DSv/2) + DSu (S0v/2 + DSv/3).
 enum { DEP_CORE = 0, DEP_REST = 1 };
 
-template <int PART, bool DET, class R>
+template <int PART, bool FIX, class R>
 __device__ __forceinline__ void deposit2d(double *Jb, int T0, int TS, const R S0[3][4], const R DS[3][4],
                                           const R cj[3], R cz, bool mx, bool my, bool on, double js)
 {
@@ -183,24 +199,24 @@ __device__ __forceinline__ void deposit2d(double *Jb, int T0, int TS, const R S0
 #pragma unroll
         for (int m = 0; m < NF - 1; ++m)
             if (need(m < 2 && n < 3, (m < 2 || mx) && (n < 3 || my)))
-                tile_add<DET>(&Jb[n * T0 + m], (double)(cs[0][m] * hf[1][n]), js);
+                tile_add<FIX>(&Jb[n * T0 + m], (double)(cs[0][m] * hf[1][n]), js);
 #pragma unroll
     for (int n = 0; n < NF - 1; ++n)
 #pragma unroll
         for (int m = 0; m < NF; ++m)
             if (need(n < 2 && m < 3, (n < 2 || my) && (m < 3 || mx)))
-                tile_add<DET>(&Jb[TS + n * T0 + m], (double)(cs[1][n] * hf[0][m]), js);
+                tile_add<FIX>(&Jb[TS + n * T0 + m], (double)(cs[1][n] * hf[0][m]), js);
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
         const R a = cz * S0[0][m], b = cz * DS[0][m];
 #pragma unroll
         for (int n = 0; n < NF; ++n)
             if (need(m < 3 && n < 3, (m < 3 || mx) && (n < 3 || my)))
-                tile_add<DET>(&Jb[2 * TS + n * T0 + m], (double)(a * hf[1][n] + b * qf[1][n]), js);
+                tile_add<FIX>(&Jb[2 * TS + n * T0 + m], (double)(a * hf[1][n] + b * qf[1][n]), js);
     }
 }
 
-template <int PART, bool DET, class R>
+template <int PART, bool FIX, class R>
 __device__ __forceinline__ void deposit3d(double *Jb, int T0, int TP, int TS, const R S0[3][4], const R DS[3][4],
                                           const R cj[3], const bool mv[3], bool on, double js)
 {
@@ -236,7 +252,7 @@ __device__ __forceinline__ void deposit3d(double *Jb, int T0, int TP, int TS, co
                     const bool core = m < 2 && i < 3 && j < 3;
                     if (PART == DEP_CORE ||
                         (!core && on && (m < 2 || mv[c]) && (i < 3 || mv[u]) && (j < 3 || mv[v])))
-                        tile_add<DET>(&Jb[c * TS + i * su + j * sv + m * sc], (double)(cs[c][m] * tr), js);
+                        tile_add<FIX>(&Jb[c * TS + i * su + j * sv + m * sc], (double)(cs[c][m] * tr), js);
                 }
             }
         }
@@ -287,8 +303,8 @@ __device__ __forceinline__ void frame_axis(R d0, R a1, int ip, R S0[4], R DS[4],
 // The rest of a mover's frame from its record: per axis the old offset d0,
 // the frame function's second argument a1 and the nearest node (packed 8
 // bits per axis in ipk), the current prefactors cj and (2D) cz.  `on`
-// switches the lane off.
-template <int DIM, class T, bool DET>
+// switches the lane off.  FIX: fixed-point tile (see tile_add).
+template <int DIM, class T, bool FIX>
 __device__ __forceinline__ void deposit_rest(const typename T::real d0[3], const typename T::real a1[3], int ipk,
                                              const typename T::real cj[3], typename T::real cz, bool on,
                                              double *tile, int T0, int TP, int TS, double js)
@@ -301,13 +317,13 @@ __device__ __forceinline__ void deposit_rest(const typename T::real d0[3], const
     for (int a = 0; a < DIM; ++a) frame_axis<T, R>(d0[a], a1[a], (ipk >> (8 * a)) & 255, S0[a], DS[a], t0[a], mv[a]);
     double *Jb = tile + (DIM == 3 ? t0[2] * TP + t0[1] * T0 + t0[0] : t0[1] * T0 + t0[0]);
     if constexpr (DIM == 2)
-        deposit2d<DEP_REST, DET, R>(Jb, T0, TS, S0, DS, cj, cz, mv[0], mv[1], on, js);
+        deposit2d<DEP_REST, FIX, R>(Jb, T0, TS, S0, DS, cj, cz, mv[0], mv[1], on, js);
     else
-        deposit3d<DEP_REST, DET, R>(Jb, T0, TP, TS, S0, DS, cj, mv, on, js);
+        deposit3d<DEP_REST, FIX, R>(Jb, T0, TP, TS, S0, DS, cj, mv, on, js);
 }
 
 // drain the mover queue: the rest of each queued mover's frame
-template <int DIM, class T, int QC, bool DET, int NT>
+template <int DIM, class T, int QC, bool FIX, int NT>
 __device__ __forceinline__ void drain_movers(const typename T::real *q, const int *qi, int nq, double *tile, int T0,
                                              int TP, int TS, double js)
 {
@@ -320,7 +336,7 @@ __device__ __forceinline__ void drain_movers(const typename T::real *q, const in
             a1[a] = q[(DIM + a) * QC + e];
             cj[a] = q[(2 * DIM + a) * QC + e];
         }
-        deposit_rest<DIM, T, DET>(d0, a1, qi[e], cj, DIM == 2 ? q[6 * QC + e] : R(0), true, tile, T0, TP, TS, js);
+        deposit_rest<DIM, T, FIX>(d0, a1, qi[e], cj, DIM == 2 ? q[6 * QC + e] : R(0), true, tile, T0, TP, TS, js);
     }
 }
 
@@ -333,15 +349,18 @@ __device__ __forceinline__ void drain_movers(const typename T::real *q, const in
 // a particle are one base address plus immediate offsets.  PX = 0: patch
 // sizes read from the run descriptor.
 //
-// The current tile accumulates in FP64 in both precision forms: on gfx950
-// a wavefront's ds_add_f64 takes ~8.6 clocks of a CU's LDS and a
-// ds_add_f32 ~193 (measured, consecutive addresses); contributions are
-// still computed in the particle precision.
+// The current tile accumulates in 64-bit fixed point (FIX: the split form
+// and the deterministic mode; js: the tile's scale) or in FP64 (the plain
+// FP64 form); contributions are computed in the particle precision.  On
+// gfx950 a wavefront's ds_add_f32 costs ~193 clocks of a CU's LDS against
+// ~8.4 for ds_add_f64, and integer adds serialise far less than FP64 adds
+// when lanes hit the same node (measured: 6.2 against 20.5 clocks when
+// lanes share addresses in pairs).
 // q, qi, qn: the workgroup's mover queue (QC entries) and its counter.
-template <int DIM, class T, int PX, bool DET, int QC>
+template <int DIM, class T, int PX, bool FIX, int QC>
 __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real *__restrict__ win, double *tile,
                                         const int p0[3], const int Prt[3], Part<T> &p, int &err,
-                                        typename T::real *q, int *qi, int *qn)
+                                        typename T::real *q, int *qi, int *qn, double js)
 {
     using R = typename T::real;
     const int P0 = PX ? PX : Prt[0], P1 = PX ? PX : Prt[1], P2 = DIM == 3 ? (PX ? PX : Prt[2]) : 1;
@@ -516,12 +535,11 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
     bool mover = false;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) mover = mover || mv[a];
-    const double js = DET ? rd.jscale : 0.0;
     const R cz = DIM == 2 ? (T::split ? (R)rd.f_q : (R)rd.q) * p.w * (un[2] * ig) : R(0);
     if constexpr (DIM == 2)
-        deposit2d<DEP_CORE, DET, R>(Jb, T0, TS, S0, DS, cj, cz, false, false, true, js);
+        deposit2d<DEP_CORE, FIX, R>(Jb, T0, TS, S0, DS, cj, cz, false, false, true, js);
     else
-        deposit3d<DEP_CORE, DET, R>(Jb, T0, TP, TS, S0, DS, cj, mv, true, js);
+        deposit3d<DEP_CORE, FIX, R>(Jb, T0, TP, TS, S0, DS, cj, mv, true, js);
     const unsigned long long mm = __ballot(mover);
     if (mm) {
         // one queue claim per wavefront, by its first active lane
@@ -549,7 +567,7 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
         }
         // the queue is full: the rest inline, from the same record
         const bool now = mover && !queued;
-        if (__any(now)) deposit_rest<DIM, T, DET>(dp, fa, ipk, cj, cz, now, tile, T0, TP, TS, js);
+        if (__any(now)) deposit_rest<DIM, T, FIX>(dp, fa, ipk, cj, cz, now, tile, T0, TP, TS, js);
     }
 
     p.u[0] = un[0];
@@ -579,9 +597,16 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
 template <int DIM, class T>
 constexpr int push_block() { return DIM == 3 ? (T::split ? 1024 : 512) : 256; }
 
+// Wavefronts per SIMD the compiler must leave room for: the 2D split-form
+// kernel of patches up to 16 cells holds five 256-thread workgroups per CU
+// (its LDS allows that), which needs at most 96 registers per lane; the
+// others are bound by their LDS or registers anyway.
+template <int DIM, class T, int PC>
+constexpr int push_min_waves() { return DIM == 2 && T::split && PC <= 16 ? 5 : 1; }
+
 // DET: deterministic mode (64-bit fixed-point tiles, see to_fixed)
 template <int DIM, class T, int PX, int PC, bool DET>
-__global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunDev *__restrict__ runs,
+__global__ __launch_bounds__((push_block<DIM, T>()), (push_min_waves<DIM, T, PC>())) void push_kernel(const RunDev *__restrict__ runs,
                                                                  const int2 *__restrict__ items, int par)
 {
     using R = typename T::real;
@@ -640,6 +665,11 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     // the spill store only when some are parked for its patch
     const int want = sg == gp(rd.pseg)[q] ? gp(rd.spcnt)[q] : 0;
     const int nsp = want > 0 ? min(rd.ctl->nspill, rd.n_total) : 0;
+    // current tile: 64-bit fixed point in the split form (scale from this
+    // segment's particle count) and in the deterministic mode (the run's
+    // scale, the same for every segment); FP64 in the plain FP64 form
+    constexpr bool FIX = DET || T::split;
+    const double js = DET ? rd.jscale : (T::split ? seg_fixed_scale(rd.junit, (double)n + (double)want) : 0.0);
     SDMD_GLOBAL int *tflag = gp(rd.tflag);
     if (n == 0 && nsp == 0) {
         // nothing to push (a vacuum patch): no window, no tile work; the
@@ -713,7 +743,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
         Part<T> pt = nxt;
         if (i + BLOCK < n) load_part<DIM, T>(sst, (uint32_t)(i + BLOCK), nxt);
         int dest = q;
-        if (valid) dest = push_one<DIM, T, PX, DET, QC>(rd, s_win, s_tile, p0, P, pt, err, s_q, s_qi, &s_qn);
+        if (valid) dest = push_one<DIM, T, PX, FIX, QC>(rd, s_win, s_tile, p0, P, pt, err, s_q, s_qi, &s_qn, js);
         const bool st = valid && dest == q;
         const bool lv = valid && dest != q;
         const unsigned long long ms = __ballot(st), ml = __ballot(lv);
@@ -825,7 +855,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
             int dest = q;
             if (mine) {
                 load_part<DIM, T>(rd.sp, s_sl[j], pt);
-                dest = push_one<DIM, T, PX, DET, QC>(rd, s_win, s_tile, p0, P, pt, err, s_q, s_qi, &s_qn);
+                dest = push_one<DIM, T, PX, FIX, QC>(rd, s_win, s_tile, p0, P, pt, err, s_q, s_qi, &s_qn, js);
             }
             const unsigned long long ml = __ballot(mine);
             int lbase = 0;
@@ -855,7 +885,7 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
     __syncthreads();   // every push of the segment is done: the queue is complete
     // the rest of the movers' frames, from the queue
     if constexpr (QC > 0) {
-        drain_movers<DIM, T, QC, DET, BLOCK>(s_q, s_qi, min(s_qn, QC), s_tile, T0, TPs, TSs, DET ? rd.jscale : 0.0);
+        drain_movers<DIM, T, QC, FIX, BLOCK>(s_q, s_qi, min(s_qn, QC), s_tile, T0, TPs, TSs, js);
         __syncthreads();
     }
     // flush the tile in the tile precision (transfer (i) reads it); the
@@ -866,6 +896,15 @@ __global__ __launch_bounds__((push_block<DIM, T>())) void push_kernel(const RunD
         for (int idx = tid; idx < 3 * TS; idx += BLOCK) {
             const int pl = idx / (T0 * T1), rem = idx - pl * (T0 * T1);
             dst[idx] = st[pl * TPs + rem];
+        }
+    } else if constexpr (FIX) {
+        // back from the segment's fixed point (the scale is a power of two)
+        SDMD_GLOBAL R *dst = gp((R *)rd.tiles) + (long long)sg * 3 * TS;
+        const long long *st = (const long long *)s_tile;
+        const double inv = 1.0 / js;
+        for (int idx = tid; idx < 3 * TS; idx += BLOCK) {
+            const int pl = idx / (T0 * T1), rem = idx - pl * (T0 * T1);
+            dst[idx] = (R)((double)st[pl * TPs + rem] * inv);
         }
     } else {
         SDMD_GLOBAL R *dst = gp((R *)rd.tiles) + (long long)sg * 3 * TS;

@@ -125,6 +125,7 @@ struct RunDev {
     double dt, q, m;
     double qmh;          // (q/m) dt/2
     double jscale, jscale_inv;   // deterministic mode: J contribution -> fixed point, and back
+    double junit;        // bound on one current contribution, |q| w_max max(1, d/dt)
     double rscale, rscale_inv;   // the same for the charge density
     float f_qmh;
     float f_dtd[3];      // dt / d  (split form displacement in cells per unit velocity)

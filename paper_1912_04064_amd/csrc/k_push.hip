@@ -146,9 +146,10 @@ __device__ __forceinline__ void tile_add(double *p, double v, double js)
 // and the parked ones of its patch) per node and component.
 __device__ __forceinline__ double seg_fixed_scale(double unit, double count)
 {
-    if (!(unit > 0.0)) return 1.0;
+    if (!(unit > 0.0) || !(unit < 0x1p1000)) return 1.0;
     const double lim = fmin(0x1p62 / (unit * fmax(count, 1.0)), 0x1p50 / unit);
-    return ldexp(1.0, ilogb(lim));
+    const int e = ilogb(lim);   // INT_MAX when lim overflows (a tiny unit): clamped below
+    return ldexp(1.0, e < -1000 ? -1000 : (e > 1000 ? 1000 : e));
 }
 
 // Esirkepov deposition of one particle into the LDS tile.  On the 4-slot

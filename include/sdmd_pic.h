@@ -67,8 +67,9 @@ extern "C" {
 /* ---- enums -------------------------------------------------------------- */
 #define PIC_FP64        0  /* everything in FP64                             */
 #define PIC_FP32_SPLIT  1  /* particles: FP32 with a split position (integer
-                              cell + FP32 offset in [0,1)), FP32 patch tiles;
-                              region reduction and Maxwell in FP64           */
+                              cell + FP32 offset in [0,1)); currents summed
+                              per segment in 64-bit fixed point, FP32 patch
+                              tiles; region reduction and Maxwell in FP64    */
 #define PIC_BC_PERIODIC 0
 
 /* field solvers (pic_config.field_solver) */
@@ -211,7 +212,9 @@ typedef struct {
  * the kinetic-energy sum (taken in storage order) are not.  The current
  * differs from the FP64 sum by at most half a quantum per contribution.
  * Costs one more FP64 operation and a 64-bit integer subtraction per
- * deposit, and 8-byte current tiles in the FP32 split form. */
+ * deposit in the FP64 form (the split form sums in fixed point anyway),
+ * 8-byte current tiles in HBM in the split form, and no mover queue (every
+ * particle's rest of frame is deposited inline). */
 typedef struct {
     void *(*alloc)(size_t bytes, void *stream, void *user);
     void (*free)(void *ptr, size_t bytes, void *stream, void *user);

@@ -145,9 +145,10 @@ def test_regions_one_vs_four_bitwise():
 
 def _same_run(a, b, tol):
     """Two GPU runs of one input agree to round-off.  The FP64 LDS atomics
-    of the current tiles add contributions from different wavefronts in a
-    timing-dependent order, so J, and through it everything else, can
-    differ in the last bits between any two runs."""
+    of the FP64 form add contributions from different wavefronts in a
+    timing-dependent order, and in both forms the decomposition groups the
+    sums of the field kernel differently, so J, and through it everything
+    else, can differ in the last bits between two runs."""
     for k in ("E", "BH", "Bm", "J"):
         nrm = np.linalg.norm(a[k])
         if nrm > 0:

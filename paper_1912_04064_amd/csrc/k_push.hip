@@ -53,6 +53,28 @@ __host__ __device__ constexpr int lds_plane(int n)
     return DIM == 3 ? (n + 7) / 16 * 16 + 8 : n;
 }
 
+// Element index in the LDS field window of component c (Ex, Ey, Ez, Bmx,
+// Bmy, Bmz) at window node n (x fastest).  3D: one plane of WS elements per
+// component.  2D: the components interpolated from the same nodes with the
+// same weights sit side by side -- (Ex, Bmy) and (Ey, Bmx) -- so that one
+// two-element LDS read fetches both; then Ez and Bmz.
+template <int DIM>
+__device__ __forceinline__ int win_index(int c, int n, int WS)
+{
+    if constexpr (DIM == 3) {
+        return c * WS + n;
+    } else {
+        switch (c) {
+        case 0: return 2 * n;
+        case 4: return 2 * n + 1;
+        case 1: return 2 * WS + 2 * n;
+        case 3: return 2 * WS + 2 * n + 1;
+        case 2: return 4 * WS + n;
+        default: return 5 * WS + n;
+        }
+    }
+}
+
 // Old/new shape factors of one axis on the 4-node sub-frame starting at
 // node ip + k0 (k0 = -2 or -1) of the 5-node Esirkepov frame centred on the
 // old primal node ip.  d0: old offset from ip in [-1/2, 1/2); d1: new
@@ -89,41 +111,75 @@ __device__ __forceinline__ void esirkepov_axis(R d0, R d1, int ip, R S0[4], R DS
 // Three cases by where the new position falls: the same primal node, the
 // next one up (u, v = distances below / above the half-node knot), or the
 // next one down (mirror image).
-template <class R>
+// MIRROR: one set of formulas for both directions (fewer instructions, more
+// values live at once: used where registers allow it, the 2D kernels).
+template <class R, bool MIRROR>
 __device__ __forceinline__ void esirkepov_axis_delta(R d0, R D, int ip, R S0[4], R DS[4], int &t0, bool &moved)
 {
-    R a0, a1, a2;
-    shape3(d0, a0, a1, a2);
-    const R d1 = d0 + D;
-    const bool up = d1 >= R(0.5), dn = d1 < R(-0.5);
-    // same node
-    R c0 = R(-0.5) * D * (R(1) - R(2) * d0 - D);
-    R c1 = -D * (R(2) * d0 + D);
-    R c2 = R(0.5) * D * (R(1) + R(2) * d0 + D);
-    R c3 = R(0);
-    if (up) {
-        const R u = R(0.5) - d0, v = D - u;
-        c0 = R(-0.5) * u * u;
-        c1 = -D + R(0.5) * v * v + u * u;
-        c2 = D - v * v - R(0.5) * u * u;
-        c3 = R(0.5) * v * v;
-    } else if (dn) {
-        const R u = R(0.5) + d0, v = -D - u;
-        c0 = R(0.5) * v * v;
-        c1 = -D - v * v - R(0.5) * u * u;
-        c2 = D + R(0.5) * v * v + u * u;
-        c3 = R(-0.5) * u * u;
+    if constexpr (MIRROR) {
+        R a0, a1, a2;
+        shape3(d0, a0, a1, a2);
+        const R d1 = d0 + D;
+        const bool up = d1 >= R(0.5), dn = d1 < R(-0.5), mv = up || dn;
+        // same node
+        const R t = R(2) * d0 + D;
+        const R s0 = R(-0.5) * D * (R(1) - t);
+        const R s1 = -D * t;
+        const R s2 = R(0.5) * D * (R(1) + t);
+        // next node: the move down is the mirror image of the move up (offset
+        // and displacement negated, frame slots reversed), so one set of
+        // formulas serves both
+        const R e = dn ? -d0 : d0, E = dn ? -D : D;
+        const R u = R(0.5) - e, v = E - u;
+        const R uu = u * u, vv = v * v;
+        const R g0 = R(-0.5) * uu;
+        const R g1 = (uu - E) + R(0.5) * vv;
+        const R g2 = (E - vv) - R(0.5) * uu;
+        const R g3 = R(0.5) * vv;
+        DS[0] = mv ? (dn ? g3 : g0) : s0;
+        DS[1] = mv ? (dn ? g2 : g1) : s1;
+        DS[2] = mv ? (dn ? g1 : g2) : s2;
+        DS[3] = mv ? (dn ? g0 : g3) : R(0);
+        S0[0] = dn ? R(0) : a0;
+        S0[1] = dn ? a0 : a1;
+        S0[2] = dn ? a1 : a2;
+        S0[3] = dn ? a2 : R(0);
+        t0 = ip + (dn ? 0 : 1);
+        moved = mv;
+    } else {
+        R a0, a1, a2;
+        shape3(d0, a0, a1, a2);
+        const R d1 = d0 + D;
+        const bool up = d1 >= R(0.5), dn = d1 < R(-0.5);
+        // same node
+        R c0 = R(-0.5) * D * (R(1) - R(2) * d0 - D);
+        R c1 = -D * (R(2) * d0 + D);
+        R c2 = R(0.5) * D * (R(1) + R(2) * d0 + D);
+        R c3 = R(0);
+        if (up) {
+            const R u = R(0.5) - d0, v = D - u;
+            c0 = R(-0.5) * u * u;
+            c1 = -D + R(0.5) * v * v + u * u;
+            c2 = D - v * v - R(0.5) * u * u;
+            c3 = R(0.5) * v * v;
+        } else if (dn) {
+            const R u = R(0.5) + d0, v = -D - u;
+            c0 = R(0.5) * v * v;
+            c1 = -D - v * v - R(0.5) * u * u;
+            c2 = D + R(0.5) * v * v + u * u;
+            c3 = R(-0.5) * u * u;
+        }
+        S0[0] = dn ? R(0) : a0;
+        S0[1] = dn ? a0 : a1;
+        S0[2] = dn ? a1 : a2;
+        S0[3] = dn ? a2 : R(0);
+        DS[0] = c0;
+        DS[1] = c1;
+        DS[2] = c2;
+        DS[3] = c3;
+        t0 = ip + (dn ? 0 : 1);
+        moved = up || dn;
     }
-    S0[0] = dn ? R(0) : a0;
-    S0[1] = dn ? a0 : a1;
-    S0[2] = dn ? a1 : a2;
-    S0[3] = dn ? a2 : R(0);
-    DS[0] = c0;
-    DS[1] = c1;
-    DS[2] = c2;
-    DS[3] = c3;
-    t0 = ip + (dn ? 0 : 1);
-    moved = up || dn;
 }
 
 // One contribution into the LDS tile: an FP64 atomic add, or (FIX) a
@@ -292,11 +348,11 @@ __host__ __device__ constexpr int mover_fields()
 
 // Esirkepov frame of one axis from the recorded arguments (split form:
 // displacement in cells; FP64 form: new position relative to the node)
-template <class T, class R>
+template <class T, class R, int DIM>
 __device__ __forceinline__ void frame_axis(R d0, R a1, int ip, R S0[4], R DS[4], int &t0, bool &moved)
 {
     if constexpr (T::split)
-        esirkepov_axis_delta<R>(d0, a1, ip, S0, DS, t0, moved);
+        esirkepov_axis_delta<R, DIM == 2>(d0, a1, ip, S0, DS, t0, moved);
     else
         esirkepov_axis<R>(d0, a1, ip, S0, DS, t0, moved);
 }
@@ -315,7 +371,7 @@ __device__ __forceinline__ void deposit_rest(const typename T::real d0[3], const
     int t0[3] = {0, 0, 0};
     bool mv[3] = {false, false, false};
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) frame_axis<T, R>(d0[a], a1[a], (ipk >> (8 * a)) & 255, S0[a], DS[a], t0[a], mv[a]);
+    for (int a = 0; a < DIM; ++a) frame_axis<T, R, DIM>(d0[a], a1[a], (ipk >> (8 * a)) & 255, S0[a], DS[a], t0[a], mv[a]);
     double *Jb = tile + (DIM == 3 ? t0[2] * TP + t0[1] * T0 + t0[0] : t0[1] * T0 + t0[0]);
     if constexpr (DIM == 2)
         deposit2d<DEP_REST, FIX, R>(Jb, T0, TS, S0, DS, cj, cz, mv[0], mv[1], on, js);
@@ -405,19 +461,33 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
     // ---- interpolation from the LDS window (window node = local node + 1)
     R E[3], B[3];
     if constexpr (DIM == 2) {
-        auto sum2 = [&](int c, const R *wx, int bx, const R *wy, int by) {
-            const R *A = win + c * WS + by * W0 + bx;
+        // window layout: see win_index
+        using V2 = typename std::conditional<std::is_same<R, float>::value, float2, double2>::type;
+        auto sum2 = [&](const R *plane, const R *wx, int bx, const R *wy, int by) {
+            const R *A = plane + by * W0 + bx;
             R s = R(0);
 #pragma unroll
-            for (int b = 0; b < 3; ++b) s += wy[b] * (wx[0] * A[b * W0] + wx[1] * A[b * W0 + 1] + wx[2] * A[b * W0 + 2]);
+            for (int b = 0; b < 3; ++b) {
+                const R r = wx[0] * A[b * W0] + wx[1] * A[b * W0 + 1] + wx[2] * A[b * W0 + 2];
+                s = b == 0 ? wy[0] * r : s + wy[b] * r;
+            }
             return s;
         };
-        E[0] = sum2(0, wd[0], lc[0], wp[1], ip[1]);
-        E[1] = sum2(1, wp[0], ip[0], wd[1], lc[1]);
-        E[2] = sum2(2, wp[0], ip[0], wp[1], ip[1]);
-        B[0] = sum2(3, wp[0], ip[0], wd[1], lc[1]);
-        B[1] = sum2(4, wd[0], lc[0], wp[1], ip[1]);
-        B[2] = sum2(5, wd[0], lc[0], wd[1], lc[1]);
+        auto pair2 = [&](const R *plane, const R *wx, int bx, const R *wy, int by, R &s0, R &s1) {
+            const V2 *A = reinterpret_cast<const V2 *>(plane) + by * W0 + bx;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const V2 q0 = A[b * W0], q1 = A[b * W0 + 1], q2 = A[b * W0 + 2];
+                const R r0 = wx[0] * q0.x + wx[1] * q1.x + wx[2] * q2.x;
+                const R r1 = wx[0] * q0.y + wx[1] * q1.y + wx[2] * q2.y;
+                s0 = b == 0 ? wy[0] * r0 : s0 + wy[b] * r0;
+                s1 = b == 0 ? wy[0] * r1 : s1 + wy[b] * r1;
+            }
+        };
+        pair2(win, wd[0], lc[0], wp[1], ip[1], E[0], B[1]);
+        pair2(win + 2 * WS, wp[0], ip[0], wd[1], lc[1], E[1], B[0]);
+        E[2] = sum2(win + 4 * WS, wp[0], ip[0], wp[1], ip[1]);
+        B[2] = sum2(win + 5 * WS, wd[0], lc[0], wd[1], lc[1]);
     } else {
         auto sum3 = [&](int c, const R *wx, int bx, const R *wy, int by, const R *wz, int bz) {
             const R *A = win + c * WS + bz * WP + by * W0 + bx;
@@ -428,9 +498,10 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
                     const R *row = A + k * WP + b * W0;
-                    sk += wy[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2]);
+                    const R r = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2];
+                    sk = b == 0 ? wy[0] * r : sk + wy[b] * r;
                 }
-                s += wz[k] * sk;
+                s = k == 0 ? wz[0] * sk : s + wz[k] * sk;
             }
             return s;
         };
@@ -495,7 +566,7 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
             }
             const R xn = p.pos[a] + delta;
             fa[a] = delta;
-            frame_axis<T, R>(dp[a], delta, ip[a], S0[a], DS[a], t0[a], mv[a]);
+            frame_axis<T, R, DIM>(dp[a], delta, ip[a], S0[a], DS[a], t0[a], mv[a]);
             const R f = floor(xn);
             int sh = (int)f;
             R xi2 = xn - f;
@@ -515,7 +586,7 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
                 X1 = X0[a];
             }
             fa[a] = (R)(X1 - (double)ipg[a]);
-            frame_axis<T, R>(dp[a], fa[a], ip[a], S0[a], DS[a], t0[a], mv[a]);
+            frame_axis<T, R, DIM>(dp[a], fa[a], ip[a], S0[a], DS[a], t0[a], mv[a]);
             const double L = rd.L[a];
             if (xn >= L) xn -= L;
             if (xn < 0.0) xn += L;
@@ -617,7 +688,7 @@ __global__ __launch_bounds__((push_block<DIM, T>()), (push_min_waves<DIM, T, PC>
     constexpr int NW = BLOCK / 64;
     constexpr int SPC = 1024;                          // spill entries scanned per round
     constexpr int SPK = (SPC + BLOCK - 1) / BLOCK;
-    __shared__ R s_win[6 * WN];
+    __shared__ __align__(16) R s_win[6 * WN];
     __shared__ double s_tile[3 * TN];
     __shared__ int s_wsum[NW], s_left, s_sw[NW];
     __shared__ int s_hole[BLOCK];
@@ -706,7 +777,7 @@ __global__ __launch_bounds__((push_block<DIM, T>()), (push_min_waves<DIM, T, PC>
                 const int wx = rem % W0, tq = rem / W0, wy = tq % W1, wz = tq / W1;
                 const int comp = c < 3 ? f_E(par) + c : F_BM + (c - 3);
                 const SDMD_GLOBAL double *A = gp((const double *)rcomp(rd, region, comp));
-                wd[u] = c * WSs + wz * WPs + wy * W0 + wx;
+                wd[u] = win_index<DIM>(c, wz * WPs + wy * W0 + wx, WSs);
                 wv[u] = A[rindex(rd, o[0] - 1 + wx, o[1] - 1 + wy, DIM == 3 ? o[2] - 1 + wz : 0)];
             }
         }

@@ -760,30 +760,41 @@ __global__ __launch_bounds__((push_block<DIM, T>()), (push_min_waves<DIM, T, PC>
         return;
     }
 
-    // transfer (ii): region E^n, Bm^n -> LDS window.  Each thread loads up
-    // to WB nodes before storing any, so the fill of a 16 x 16 (2D) or 8^3
-    // (3D) patch's window waits on memory once instead of once per node.
-    constexpr int WB = 9;
-    for (int i0 = 0; i0 < 6 * WS; i0 += WB * BLOCK) {
-        double wv[WB];
-        int wd[WB];
+    // transfer (ii): region E^n, Bm^n -> LDS window.  A thread takes WB
+    // window nodes (stride BLOCK) at a time and loads all six components of
+    // each before storing any, so the fill of a 16 x 16 (2D) or 8^3 (3D)
+    // patch's window waits on memory once; a node's index arithmetic is
+    // shared by its six loads, whose bases are uniform.
+    constexpr int WB = 2;
+    const SDMD_GLOBAL double *Ereg = gp((const double *)rcomp(rd, region, f_E(par)));
+    const SDMD_GLOBAL double *Breg = gp((const double *)rcomp(rd, region, F_BM));
+    const long long cst = rd.rsize;   // component stride of a region
+    for (int n0 = 0; n0 < WS; n0 += WB * BLOCK) {
+        double wv[WB][6];
+        int wl[WB];
 #pragma unroll
         for (int u = 0; u < WB; ++u) {
-            const int idx = i0 + u * BLOCK + tid;
-            wd[u] = -1;
-            wv[u] = 0.0;
-            if (idx < 6 * WS) {
-                const int c = idx / WS, rem = idx - c * WS;
-                const int wx = rem % W0, tq = rem / W0, wy = tq % W1, wz = tq / W1;
-                const int comp = c < 3 ? f_E(par) + c : F_BM + (c - 3);
-                const SDMD_GLOBAL double *A = gp((const double *)rcomp(rd, region, comp));
-                wd[u] = win_index<DIM>(c, wz * WPs + wy * W0 + wx, WSs);
-                wv[u] = A[rindex(rd, o[0] - 1 + wx, o[1] - 1 + wy, DIM == 3 ? o[2] - 1 + wz : 0)];
+            const int nd = n0 + u * BLOCK + tid;
+            wl[u] = -1;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) wv[u][c] = 0.0;
+            if (nd < WS) {
+                const int wx = nd % W0, tq = nd / W0, wy = tq % W1, wz = tq / W1;
+                wl[u] = wz * WPs + wy * W0 + wx;
+                const long long g = rindex(rd, o[0] - 1 + wx, o[1] - 1 + wy, DIM == 3 ? o[2] - 1 + wz : 0);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    wv[u][c] = Ereg[g + c * cst];
+                    wv[u][3 + c] = Breg[g + c * cst];
+                }
             }
         }
 #pragma unroll
         for (int u = 0; u < WB; ++u)
-            if (wd[u] >= 0) s_win[wd[u]] = (R)wv[u];
+            if (wl[u] >= 0) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) s_win[win_index<DIM>(c, wl[u], WSs)] = (R)wv[u][c];
+            }
     }
     for (int idx = tid; idx < 3 * TSs; idx += BLOCK) s_tile[idx] = 0.0;
     if (tid == 0) {

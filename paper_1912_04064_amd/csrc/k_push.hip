@@ -463,8 +463,14 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
     if constexpr (DIM == 2) {
         // window layout: see win_index
         using V2 = typename std::conditional<std::is_same<R, float>::value, float2, double2>::type;
-        auto sum2 = [&](const R *plane, const R *wx, int bx, const R *wy, int by) {
-            const R *A = plane + by * W0 + bx;
+        // The element offset of a stencil's first node is kept in one
+        // register (the empty asm hides its sum from the compiler), so the
+        // nine reads take the rest of their offsets from the instructions'
+        // immediate fields.
+        auto sum2 = [&](int plane, const R *wx, int bx, const R *wy, int by) {
+            int o = plane + by * W0 + bx;
+            asm("" : "+v"(o));
+            const R *A = win + o;
             R s = R(0);
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
@@ -473,8 +479,10 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
             }
             return s;
         };
-        auto pair2 = [&](const R *plane, const R *wx, int bx, const R *wy, int by, R &s0, R &s1) {
-            const V2 *A = reinterpret_cast<const V2 *>(plane) + by * W0 + bx;
+        auto pair2 = [&](int plane, const R *wx, int bx, const R *wy, int by, R &s0, R &s1) {
+            int o = plane / 2 + by * W0 + bx;   // in pairs
+            asm("" : "+v"(o));
+            const V2 *A = reinterpret_cast<const V2 *>(win) + o;
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 const V2 q0 = A[b * W0], q1 = A[b * W0 + 1], q2 = A[b * W0 + 2];
@@ -484,20 +492,25 @@ __device__ __forceinline__ int push_one(const RunDev &rd, const typename T::real
                 s1 = b == 0 ? wy[0] * r1 : s1 + wy[b] * r1;
             }
         };
-        pair2(win, wd[0], lc[0], wp[1], ip[1], E[0], B[1]);
-        pair2(win + 2 * WS, wp[0], ip[0], wd[1], lc[1], E[1], B[0]);
-        E[2] = sum2(win + 4 * WS, wp[0], ip[0], wp[1], ip[1]);
-        B[2] = sum2(win + 5 * WS, wd[0], lc[0], wd[1], lc[1]);
+        pair2(0, wd[0], lc[0], wp[1], ip[1], E[0], B[1]);
+        pair2(2 * WS, wp[0], ip[0], wd[1], lc[1], E[1], B[0]);
+        E[2] = sum2(4 * WS, wp[0], ip[0], wp[1], ip[1]);
+        B[2] = sum2(5 * WS, wd[0], lc[0], wd[1], lc[1]);
     } else {
+        // one register per plane of the stencil holds its first node's
+        // offset (as in 2D); the plane's nine reads add immediates to it
         auto sum3 = [&](int c, const R *wx, int bx, const R *wy, int by, const R *wz, int bz) {
-            const R *A = win + c * WS + bz * WP + by * W0 + bx;
+            const int o0 = c * WS + bz * WP + by * W0 + bx;
             R s = R(0);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
+                int o = o0 + k * WP;
+                asm("" : "+v"(o));
+                const R *A = win + o;
                 R sk = R(0);
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
-                    const R *row = A + k * WP + b * W0;
+                    const R *row = A + b * W0;
                     const R r = wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2];
                     sk = b == 0 ? wy[0] * r : sk + wy[b] * r;
                 }
@@ -688,8 +701,16 @@ __global__ __launch_bounds__((push_block<DIM, T>()), (push_min_waves<DIM, T, PC>
     constexpr int NW = BLOCK / 64;
     constexpr int SPC = 1024;                          // spill entries scanned per round
     constexpr int SPK = (SPC + BLOCK - 1) / BLOCK;
-    __shared__ __align__(16) R s_win[6 * WN];
-    __shared__ double s_tile[3 * TN];
+    // The window sits at LDS address 0, so the interpolation's paired
+    // reads of neighbouring nodes take their offsets from the instruction's
+    // immediate fields instead of an address add per read; the tile follows.
+    struct alignas(16) WinTile {
+        R win[6 * WN];
+        double tile[3 * TN];
+    };
+    __shared__ WinTile s_wt;
+    R *const s_win = s_wt.win;
+    double *const s_tile = s_wt.tile;
     __shared__ int s_wsum[NW], s_left, s_sw[NW];
     __shared__ int s_hole[BLOCK];
     __shared__ int s_sl[SPC];                          // this patch's parked particles found in a round

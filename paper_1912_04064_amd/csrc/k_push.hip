@@ -755,16 +755,18 @@ __global__ __launch_bounds__((push_block<DIM, T>()), (push_min_waves<DIM, T, PC>
     int n = __builtin_amdgcn_readfirstlane(gp(rd.scnt)[sg]);
     n = n < cap ? n : cap;
     // parked particles are pushed by the patch's first segment, which scans
-    // the spill store only when some are parked for its patch
-    const int want = sg == gp(rd.pseg)[q] ? gp(rd.spcnt)[q] : 0;
-    const int nsp = want > 0 ? min(rd.ctl->nspill, rd.n_total) : 0;
-    // current tile: 64-bit fixed point in the split form (scale from this
-    // segment's particle count) and in the deterministic mode (the run's
-    // scale, the same for every segment); FP64 in the plain FP64 form
-    constexpr bool FIX = DET || T::split;
-    const double js = DET ? rd.jscale : (T::split ? seg_fixed_scale(rd.junit, (double)n + (double)want) : 0.0);
+    // the spill store only when some are parked for its patch.  Their count
+    // is loaded here but read only after the window loads have gone out;
+    // only an empty segment waits for it first.  (The empty asm statements
+    // keep the compiler from moving those waits.)
+    int first = gp(rd.pseg)[q], cnt = gp(rd.spcnt)[q];
     SDMD_GLOBAL int *tflag = gp(rd.tflag);
-    if (n == 0 && nsp == 0) {
+    int idle = 1;   // 0: nothing to push
+    if (n == 0) {
+        idle = sg == first ? cnt : 0;
+        asm volatile("" : "+v"(idle));
+    }
+    if (idle == 0) {
         // nothing to push (a vacuum patch): no window, no tile work; the
         // tile in HBM is cleared only if an earlier step left current in it
         const int dirty = tflag[sg];
@@ -793,21 +795,18 @@ __global__ __launch_bounds__((push_block<DIM, T>()), (push_min_waves<DIM, T, PC>
     for (int n0 = 0; n0 < WS; n0 += WB * BLOCK) {
         double wv[WB][6];
         int wl[WB];
+        // lanes past the window's end load its last node again and store
+        // nothing: no branch between the loads, so they wait on memory once
 #pragma unroll
         for (int u = 0; u < WB; ++u) {
-            const int nd = n0 + u * BLOCK + tid;
-            wl[u] = -1;
+            const int nr = n0 + u * BLOCK + tid, nd = nr < WS ? nr : WS - 1;
+            const int wx = nd % W0, tq = nd / W0, wy = tq % W1, wz = tq / W1;
+            wl[u] = nr < WS ? wz * WPs + wy * W0 + wx : -1;
+            const long long g = rindex(rd, o[0] - 1 + wx, o[1] - 1 + wy, DIM == 3 ? o[2] - 1 + wz : 0);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) wv[u][c] = 0.0;
-            if (nd < WS) {
-                const int wx = nd % W0, tq = nd / W0, wy = tq % W1, wz = tq / W1;
-                wl[u] = wz * WPs + wy * W0 + wx;
-                const long long g = rindex(rd, o[0] - 1 + wx, o[1] - 1 + wy, DIM == 3 ? o[2] - 1 + wz : 0);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    wv[u][c] = Ereg[g + c * cst];
-                    wv[u][3 + c] = Breg[g + c * cst];
-                }
+            for (int c = 0; c < 3; ++c) {
+                wv[u][c] = Ereg[g + c * cst];
+                wv[u][3 + c] = Breg[g + c * cst];
             }
         }
 #pragma unroll
@@ -818,6 +817,13 @@ __global__ __launch_bounds__((push_block<DIM, T>()), (push_min_waves<DIM, T, PC>
             }
     }
     for (int idx = tid; idx < 3 * TSs; idx += BLOCK) s_tile[idx] = 0.0;
+    asm volatile("" : "+v"(first), "+v"(cnt));
+    const int want = sg == first ? cnt : 0;
+    // current tile: 64-bit fixed point in the split form (scale from this
+    // segment's particle count) and in the deterministic mode (the run's
+    // scale, the same for every segment); FP64 in the plain FP64 form
+    constexpr bool FIX = DET || T::split;
+    const double js = DET ? rd.jscale : (T::split ? seg_fixed_scale(rd.junit, (double)n + (double)want) : 0.0);
     if (tid == 0) {
         s_left = 0;
         s_qn = 0;
@@ -929,6 +935,7 @@ __global__ __launch_bounds__((push_block<DIM, T>()), (push_min_waves<DIM, T, PC>
     // rounds of SPC entries, all loads of a round in flight at once; the
     // round's matches are listed in LDS and pushed.
     int found = 0;   // parked particles of this patch pushed so far (uniform)
+    const int nsp = want > 0 ? min(rd.ctl->nspill, rd.n_total) : 0;
     for (int c0 = 0; c0 < nsp && found < want; c0 += SPC) {
         if (tid == 0) s_ns = 0;
         __syncthreads();

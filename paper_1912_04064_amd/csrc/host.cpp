@@ -10,8 +10,9 @@
 //         launches of each spectral run)
 //   post  (ghost chunks + leaver insertion)              -- Sync
 // and every `relayout_every` steps a re-layout check (three launches that
-// exit at once unless some patch overflowed).  The two-step sequence
-// (E/B buffer parity 0 then 1) is captured once in a hipGraph and replayed.
+// exit at once unless some patch overflowed).  Runs of 2 and 8 steps (E/B
+// buffer parity 0 then 1, repeated) and a whole re-layout period with its
+// check are captured once in hipGraphs and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -101,6 +102,8 @@ struct pic_ctx {
     int relayout_every = 16;
     bool use_graph = true;
     hipGraphExec_t g2 = nullptr;      // two steps
+    hipGraphExec_t g8 = nullptr;      // eight steps
+    hipGraphExec_t gK = nullptr;      // relayout_every steps and the re-layout check after them
     hipGraphExec_t grel = nullptr;    // re-layout check
     bool graphs_valid = false;
     size_t bytes = 0;        // device bytes held now
@@ -1093,9 +1096,10 @@ static hipError_t enqueue_relayout(pic_ctx *c, hipStream_t s)
 
 static void drop_graphs(pic_ctx *c)
 {
-    if (c->g2) hipGraphExecDestroy(c->g2);
-    if (c->grel) hipGraphExecDestroy(c->grel);
-    c->g2 = c->grel = nullptr;
+    for (hipGraphExec_t *g : {&c->g2, &c->g8, &c->gK, &c->grel}) {
+        if (*g) hipGraphExecDestroy(*g);
+        *g = nullptr;
+    }
     c->graphs_valid = false;
 }
 
@@ -1103,11 +1107,18 @@ static int build_graphs(pic_ctx *c)
 {
     drop_graphs(c);
     if (!c->use_graph) return PIC_OK;
-    for (int k = 0; k < 2; ++k) {
+    // Each graph launch costs the GPU a gap of several microseconds, so the
+    // common stretches of steps are captured whole: 2 and 8 steps, and a
+    // full re-layout period with its check.  Steps come in pairs (E/B
+    // buffer parity 0 then 1).
+    const int K = c->relayout_every;
+    for (int k = 0; k < 4; ++k) {
         hipGraph_t g = nullptr;
+        const int nsteps = k == 0 ? 2 : (k == 1 ? 0 : (k == 2 ? 8 : K));
         HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = (k == 0) ? enqueue_step(c, 0, c->cap_stream) : enqueue_relayout(c, c->cap_stream);
-        if (e == hipSuccess && k == 0) e = enqueue_step(c, 1, c->cap_stream);
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < nsteps && e == hipSuccess; ++i) e = enqueue_step(c, i & 1, c->cap_stream);
+        if (e == hipSuccess && (k == 1 || k == 3)) e = enqueue_relayout(c, c->cap_stream);
         hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
             if (g) hipGraphDestroy(g);
@@ -1118,7 +1129,7 @@ static int build_graphs(pic_ctx *c)
         hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         hipGraphDestroy(g);
         if (e3 != hipSuccess) return set_err(c, PIC_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e3));
-        (k == 0 ? c->g2 : c->grel) = ex;
+        (k == 0 ? c->g2 : (k == 1 ? c->grel : (k == 2 ? c->g8 : c->gK))) = ex;
     }
     c->graphs_valid = true;
     return PIC_OK;
@@ -1305,7 +1316,17 @@ int pic_step(pic_ctx *c, int32_t n_steps)
     while (left > 0) {
         const int K = c->relayout_every;
         const int to_check = K - (int)(c->step % K);
-        if (c->use_graph && c->g2 && c->par == 0 && left >= 2 && to_check >= 2) {
+        if (c->use_graph && c->gK && c->par == 0 && to_check == K && left >= K) {
+            HIPCHK(c, hipGraphLaunch(c->gK, c->stream));   // a whole period and its check
+            advance(c, K);
+            left -= K;
+            continue;
+        }
+        if (c->use_graph && c->g8 && c->par == 0 && left >= 8 && to_check >= 8) {
+            HIPCHK(c, hipGraphLaunch(c->g8, c->stream));
+            advance(c, 8);
+            left -= 8;
+        } else if (c->use_graph && c->g2 && c->par == 0 && left >= 2 && to_check >= 2) {
             HIPCHK(c, hipGraphLaunch(c->g2, c->stream));
             advance(c, 2);
             left -= 2;

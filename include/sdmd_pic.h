@@ -102,7 +102,8 @@ extern "C" {
 
 /* pic_runtime.flags */
 #define PIC_RT_NO_GRAPH   (1 << 0)  /* launch kernels one by one instead of
-                                       replaying a captured hipGraph          */
+                                       replaying captured hipGraphs (of 2
+                                       and 8 steps and of a re-layout period) */
 
 typedef struct pic_ctx pic_ctx;
 

@@ -3,16 +3,21 @@
 //
 // The field kernel has already summed the patch tiles into the region's J
 // (transfer (i) of section 2.2, and the current filter).  Then:
-//   pack     region E^n, B^n, J -> 9 complex arrays of the grid;
-//   fft      1D transforms along x, y (, z), one workgroup per grid line,
-//            the line held in LDS (iterative radix-2, bit-reversed load);
-//   kspace   per wavevector: move each component to its staggered position
-//            (phase e^{-i k.s}), advance E, B exactly over dt with J held at
-//            J^{n+1/2} (equations below), move back;
-//   ifft     inverse transforms of E, B;
-//   unpack   real parts / (nx ny nz) -> E^{n+1}, B^{n+1} and Bm^{n+1} =
-//            B^{n+1} in the other E/B buffer; the post kernel exchanges the
-//            ghost layers as for the Yee update.
+//   fft x    region E^n, B^n, J (real) -> 9 complex arrays of the grid,
+//            transformed along x (one workgroup per batch of x lines, the
+//            lines held in LDS: iterative radix-2, bit-reversed load);
+//   fft y    (3D) along y;
+//   line     along the last axis, all 9 components of one line in LDS:
+//            forward transform, the exact step of every wavevector of the
+//            line (move each component to its staggered position, phase
+//            e^{-i k.s}; advance E, B over dt with J held at J^{n+1/2},
+//            equations below; move back), inverse transform of E, B;
+//            lines too long for the LDS take the three steps as separate
+//            launches over the whole grid instead;
+//   ifft y   (3D) inverse along y;
+//   ifft x   inverse along x -> real parts / (nx ny nz) = E^{n+1},
+//            B^{n+1} and Bm^{n+1} = B^{n+1} in the other E/B buffer; the
+//            post kernel exchanges the ghost layers as for the Yee update.
 // With the lattice wavenumber k~_a = 2 sin(k_a d_a / 2) / d_a, w = |k~|,
 // kappa = k~ / w, C = cos(w dt), S = sin(w dt):
 //   E' = C E + (1 - C) kappa (kappa.E) + i S kappa x B - (S/w) J
@@ -41,38 +46,10 @@ __device__ __forceinline__ int stag(int comp, int a)
     return c == a ? 0 : 1;                               // B: across the other two
 }
 
-// region <-> grid arrays (one region of the run: its interior is the grid)
-__global__ void spec_pack_kernel(const RunDev *__restrict__ runs, int run, int par)
+// the region component behind grid array c (0..8: E, B, J) at parity par
+__device__ __forceinline__ int src_comp(int c, int par)
 {
-    const RunDev &rd = runs[run];
-    if (rd.ctl->remaining[par] == 0) return;
-    const long long ncell = (long long)rd.n[0] * rd.n[1] * rd.n[2];
-    const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
-    if (gid >= ncell) return;
-    const int i = (int)(gid % rd.n[0]), j = (int)((gid / rd.n[0]) % rd.n[1]), k = (int)(gid / ((long long)rd.n[0] * rd.n[1]));
-    const long long p = rindex(rd, i, j, k);
-    const int src[9] = {f_E(par), f_E(par) + 1, f_E(par) + 2, f_B(par), f_B(par) + 1, f_B(par) + 2, F_J, F_J + 1, F_J + 2};
-#pragma unroll
-    for (int c = 0; c < 9; ++c) rd.spec[c * ncell + gid] = make_double2(rcomp(rd, 0, src[c])[p], 0.0);
-}
-
-__global__ void spec_unpack_kernel(const RunDev *__restrict__ runs, int run, int par)
-{
-    const RunDev &rd = runs[run];
-    if (rd.ctl->remaining[par] == 0) return;
-    const long long ncell = (long long)rd.n[0] * rd.n[1] * rd.n[2];
-    const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
-    if (gid >= ncell) return;
-    const int i = (int)(gid % rd.n[0]), j = (int)((gid / rd.n[0]) % rd.n[1]), k = (int)(gid / ((long long)rd.n[0] * rd.n[1]));
-    const long long p = rindex(rd, i, j, k);
-    const double inv = 1.0 / (double)ncell;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        rcomp(rd, 0, f_E(1 - par) + c)[p] = rd.spec[c * ncell + gid].x * inv;
-        const double b = rd.spec[(3 + c) * ncell + gid].x * inv;
-        rcomp(rd, 0, f_B(1 - par) + c)[p] = b;
-        rcomp(rd, 0, F_BM + c)[p] = b;
-    }
+    return c < 3 ? f_E(par) + c : (c < 6 ? f_B(par) + c - 3 : F_J + c - 6);
 }
 
 // 1D transforms of length N = n[axis] along `axis` of components [c0, c0+nc)
@@ -91,6 +68,11 @@ __host__ __device__ inline int fft_lines_per_group(int N, int axis, const int n[
     return nl;
 }
 
+// IN_REGION: the lines are read from the region's real E^n, B^n, J (the
+// first forward transform); OUT_REGION: the real parts, divided by the
+// number of cells, are written to the region's E^{n+1}, B^{n+1} and Bm (the
+// last inverse transform).
+template <bool IN_REGION, bool OUT_REGION>
 __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restrict__ runs, int run, int par, int axis,
                                                          int c0, int sign)
 {
@@ -122,7 +104,13 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
         stride = (long long)n0 * n1;
         lstep = 1;
     }
-    double2 *a = rd.spec + (long long)(c0 + blockIdx.y) * ncell + o;
+    const int comp = c0 + blockIdx.y;
+    double2 *a = rd.spec + (long long)comp * ncell + o;
+    // grid offset -> region element (the region's interior is the grid)
+    auto relem = [&](long long g) {
+        const int i = (int)(g % n0), j = (int)((g / n0) % n1), k = (int)(g / ((long long)n0 * n1));
+        return rindex(rd, i, j, k);
+    };
     int logn = 0;
     while ((1 << logn) < N) ++logn;
     const int tid = threadIdx.x;
@@ -142,7 +130,10 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
             j = e / NL;
         }
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
-        buf[l * N + r] = a[l * lstep + j * stride];
+        if constexpr (IN_REGION)
+            buf[l * N + r] = make_double2(rcomp(rd, 0, src_comp(comp, par))[relem(o + l * lstep + j * stride)], 0.0);
+        else
+            buf[l * N + r] = a[l * lstep + j * stride];
     }
     __syncthreads();
     for (int len = 2; len <= N; len <<= 1) {
@@ -165,32 +156,37 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
             l = e % NL;
             j = e / NL;
         }
-        a[l * lstep + j * stride] = buf[l * N + j];
+        if constexpr (OUT_REGION) {
+            const long long p = relem(o + l * lstep + j * stride);
+            const double v = buf[l * N + j].x / (double)ncell;
+            if (comp < 3) {
+                rcomp(rd, 0, f_E(1 - par) + comp)[p] = v;
+            } else {
+                rcomp(rd, 0, f_B(1 - par) + comp - 3)[p] = v;
+                rcomp(rd, 0, F_BM + comp - 3)[p] = v;
+            }
+        } else {
+            a[l * lstep + j * stride] = buf[l * N + j];
+        }
     }
 }
 
-// exact step of every wavevector
-__global__ void spec_kspace_kernel(const RunDev *__restrict__ runs, int run, int par)
+// The exact step of one wavevector: F[0..8] = E, B, J at grid index idx
+// (as transformed, at the grid positions); on return F[0..5] hold E^{n+1},
+// B^{n+1} at the grid positions.
+__device__ __forceinline__ void kspace_step(const RunDev &rd, const int idx[3], double2 F[9])
 {
-    const RunDev &rd = runs[run];
-    if (rd.ctl->remaining[par] == 0) return;
-    const long long ncell = (long long)rd.n[0] * rd.n[1] * rd.n[2];
-    const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
-    if (gid >= ncell) return;
-    const int idx[3] = {(int)(gid % rd.n[0]), (int)((gid / rd.n[0]) % rd.n[1]),
-                        (int)(gid / ((long long)rd.n[0] * rd.n[1]))};
-    double k[3] = {0, 0, 0}, kt[3] = {0, 0, 0};
-    for (int a = 0; a < rd.dims; ++a) {
-        const int m = idx[a] < (rd.n[a] + 1) / 2 ? idx[a] : idx[a] - rd.n[a];   // signed frequency
-        k[a] = 2.0 * M_PI * (double)m / rd.L[a];
-        kt[a] = 2.0 * sin(0.5 * k[a] * rd.d[a]) / rd.d[a];
-    }
     // fields at their physical (staggered) positions: a component shifted
-    // by half a cell along axis a picks up e^{-i k_a d_a / 2}
+    // by half a cell along axis a picks up e^{-i k_a d_a / 2}; the same
+    // sine gives the lattice wavenumber
+    double kt[3] = {0, 0, 0};
     double2 hs[3] = {make_double2(1, 0), make_double2(1, 0), make_double2(1, 0)};
     for (int a = 0; a < rd.dims; ++a) {
+        const int m = idx[a] < (rd.n[a] + 1) / 2 ? idx[a] : idx[a] - rd.n[a];   // signed frequency
+        const double k = 2.0 * M_PI * (double)m / rd.L[a];
         double sn, cs;
-        sincos(0.5 * k[a] * rd.d[a], &sn, &cs);
+        sincos(0.5 * k * rd.d[a], &sn, &cs);
+        kt[a] = 2.0 * sn / rd.d[a];
         hs[a] = make_double2(cs, sn);                           // e^{+i k_a d_a / 2}
     }
     auto shift = [&](int c) {                                   // e^{+i k.s_c}
@@ -199,11 +195,10 @@ __global__ void spec_kspace_kernel(const RunDev *__restrict__ runs, int run, int
             if (stag(c, a)) z = cmul(z, hs[a]);
         return z;
     };
-    double2 F[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
         const double2 z = shift(c);
-        F[c] = cmul(rd.spec[c * ncell + gid], make_double2(z.x, -z.y));
+        F[c] = cmul(F[c], make_double2(z.x, -z.y));
     }
     const double dt = rd.dt;
     const double w = sqrt(kt[0] * kt[0] + kt[1] * kt[1] + kt[2] * kt[2]);
@@ -216,7 +211,9 @@ __global__ void spec_kspace_kernel(const RunDev *__restrict__ runs, int run, int
         }
     } else {
         const double kap[3] = {kt[0] / w, kt[1] / w, kt[2] / w};
-        const double C = cos(w * dt), S = sin(w * dt), Sw = S / w, C1w = (1.0 - C) / w;
+        double S, C;
+        sincos(w * dt, &S, &C);
+        const double Sw = S / w, C1w = (1.0 - C) / w;
         double2 kE = make_double2(0, 0), kJ = make_double2(0, 0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -242,23 +239,134 @@ __global__ void spec_kspace_kernel(const RunDev *__restrict__ runs, int run, int
     }
     // back to the grid positions
 #pragma unroll
-    for (int c = 0; c < 6; ++c) rd.spec[c * ncell + gid] = cmul(c < 3 ? En[c] : Bn[c - 3], shift(c));
+    for (int c = 0; c < 6; ++c) F[c] = cmul(c < 3 ? En[c] : Bn[c - 3], shift(c));
+}
+
+// exact step of every wavevector of the grid (lines too long for spec_line_kernel)
+__global__ void spec_kspace_kernel(const RunDev *__restrict__ runs, int run, int par)
+{
+    const RunDev &rd = runs[run];
+    if (rd.ctl->remaining[par] == 0) return;
+    const long long ncell = (long long)rd.n[0] * rd.n[1] * rd.n[2];
+    const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (gid >= ncell) return;
+    const int idx[3] = {(int)(gid % rd.n[0]), (int)((gid / rd.n[0]) % rd.n[1]),
+                        (int)(gid / ((long long)rd.n[0] * rd.n[1]))};
+    double2 F[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) F[c] = rd.spec[c * ncell + gid];
+    kspace_step(rd, idx, F);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) rd.spec[c * ncell + gid] = F[c];
+}
+
+// One line along the last axis, all 9 components in LDS: forward transform
+// (bit-reversed load, decimation in time), the exact step of each of the
+// line's wavevectors, inverse transform of the 6 E and B components
+// (decimation in frequency: natural order in, bit-reversed order out, read
+// back bit-reversed on the store).  The lines are dealt to the XCDs in
+// contiguous bands (workgroup l runs on XCD l % 8), so the lines a cache
+// line of the grid holds are read on one XCD.
+constexpr int SPEC_LINE_MAX = 256;   // 9 x 256 complex values: 36 KB of LDS (dynamic LDS stays under 64 KB)
+
+__global__ __launch_bounds__(BLOCK) void spec_line_kernel(const RunDev *__restrict__ runs, int run, int par)
+{
+    extern __shared__ double2 sm[];
+    const RunDev &rd = runs[run];
+    if (rd.ctl->remaining[par] == 0) return;
+    const int dims = rd.dims, ax = dims - 1;
+    const int n0 = rd.n[0], n1 = rd.n[1];
+    const long long ncell = (long long)n0 * n1 * rd.n[2];
+    const int N = rd.n[ax];
+    const long long nlines = ncell / N;
+    const long long band = (nlines + 7) / 8;
+    const long long line = (long long)(blockIdx.x & 7) * band + (blockIdx.x >> 3);
+    if ((blockIdx.x >> 3) >= band || line >= nlines) return;
+    const long long stride = nlines;   // the last axis is the slowest: its lines are every nlines-th element
+    double2 *buf = sm, *tw = sm + 9 * N;
+    int logn = 0;
+    while ((1 << logn) < N) ++logn;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < N / 2; k += BLOCK) {
+        double sn, cs;
+        sincospi((double)(-2 * k) / (double)N, &sn, &cs);
+        tw[k] = make_double2(cs, sn);   // forward twiddles e^{-2 pi i k / N}; the inverse uses their conjugates
+    }
+    for (int e = tid; e < 9 * N; e += BLOCK) {
+        const int c = e / N, j = e - c * N;
+        const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
+        buf[c * N + r] = rd.spec[c * ncell + line + j * stride];
+    }
+    __syncthreads();
+    // forward: decimation in time on bit-reversed input
+    for (int len = 2; len <= N; len <<= 1) {
+        const int half = len >> 1, step = N / len;
+        for (int t = tid; t < 9 * (N / 2); t += BLOCK) {
+            const int c = t / (N / 2), b = t - c * (N / 2);
+            const int pos = b % half, i = c * N + (b / half) * len + pos;
+            const double2 u = buf[i], v = cmul(buf[i + half], tw[pos * step]);
+            buf[i] = make_double2(u.x + v.x, u.y + v.y);
+            buf[i + half] = make_double2(u.x - v.x, u.y - v.y);
+        }
+        __syncthreads();
+    }
+    // the exact step of each wavevector of the line
+    const int i0 = (int)(line % n0), i1 = dims == 3 ? (int)(line / n0) : 0;
+    for (int j = tid; j < N; j += BLOCK) {
+        const int idx[3] = {i0, dims == 3 ? i1 : j, dims == 3 ? j : 0};
+        double2 F[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) F[c] = buf[c * N + j];
+        kspace_step(rd, idx, F);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) buf[c * N + j] = F[c];
+    }
+    __syncthreads();
+    // inverse: decimation in frequency with the conjugate twiddles
+    for (int len = N; len >= 2; len >>= 1) {
+        const int half = len >> 1, step = N / len;
+        for (int t = tid; t < 6 * (N / 2); t += BLOCK) {
+            const int c = t / (N / 2), b = t - c * (N / 2);
+            const int pos = b % half, i = c * N + (b / half) * len + pos;
+            const double2 u = buf[i], v = buf[i + half];
+            const double2 w = make_double2(tw[pos * step].x, -tw[pos * step].y);
+            buf[i] = make_double2(u.x + v.x, u.y + v.y);
+            buf[i + half] = cmul(make_double2(u.x - v.x, u.y - v.y), w);
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < 6 * N; e += BLOCK) {
+        const int c = e / N, j = e - c * N;
+        const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
+        rd.spec[c * ncell + line + j * stride] = buf[c * N + r];
+    }
 }
 
 hipError_t launch_spectral(const RunDev *runs, int run, int dims, const int n[3], int par, hipStream_t s)
 {
     const long long ncell = (long long)n[0] * n[1] * n[2];
-    const unsigned nb = (unsigned)((ncell + BLOCK - 1) / BLOCK);
-    spec_pack_kernel<<<nb, BLOCK, 0, s>>>(runs, run, par);
-    auto fft = [&](int a, int ncomp, int sign) {
+    const int last = dims - 1;
+    auto fft = [&](auto kern, int a, int ncomp, int sign) {
         const int nl = fft_lines_per_group(n[a], a, n);
         const size_t lds = ((size_t)nl * n[a] + n[a] / 2) * sizeof(double2);
-        spec_fft_kernel<<<dim3((unsigned)(ncell / n[a] / nl), ncomp), BLOCK, lds, s>>>(runs, run, par, a, 0, sign);
+        kern<<<dim3((unsigned)(ncell / n[a] / nl), ncomp), BLOCK, lds, s>>>(runs, run, par, a, 0, sign);
     };
-    for (int a = 0; a < dims; ++a) fft(a, 9, -1);
-    spec_kspace_kernel<<<nb, BLOCK, 0, s>>>(runs, run, par);
-    for (int a = 0; a < dims; ++a) fft(a, 6, +1);
-    spec_unpack_kernel<<<nb, BLOCK, 0, s>>>(runs, run, par);
+    // forward along x, reading the region's fields; then the middle axis (3D)
+    fft(spec_fft_kernel<true, false>, 0, 9, -1);
+    for (int a = 1; a < last; ++a) fft(spec_fft_kernel<false, false>, a, 9, -1);
+    if (n[last] <= SPEC_LINE_MAX) {
+        const long long nlines = ncell / n[last];
+        const unsigned grid = (unsigned)(8 * ((nlines + 7) / 8));
+        const size_t lds = ((size_t)9 * n[last] + n[last] / 2) * sizeof(double2);
+        spec_line_kernel<<<grid, BLOCK, lds, s>>>(runs, run, par);
+    } else {
+        fft(spec_fft_kernel<false, false>, last, 9, -1);
+        spec_kspace_kernel<<<(unsigned)((ncell + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(runs, run, par);
+        fft(spec_fft_kernel<false, false>, last, 6, +1);
+    }
+    // inverse along the middle axis (3D), then along x into the region
+    for (int a = last - 1; a >= 1; --a) fft(spec_fft_kernel<false, false>, a, 6, +1);
+    fft(spec_fft_kernel<false, true>, 0, 6, +1);
     return hipGetLastError();
 }
 

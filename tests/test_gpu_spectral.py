@@ -97,6 +97,20 @@ def test_spectral_steps_match_oracle(prec, tol1, tol20):
         assert np.minimum(dx, L - dx).max() < 1e-13
 
 
+def test_spectral_long_last_axis_matches_oracle():
+    """Lines along the last axis longer than the fused line kernel takes
+    (512 > 256 nodes) go through separate transform and k-space launches;
+    both routes must give the oracle's step."""
+    say("case: spectral thermal 16x512 fp64 (unfused last axis)")
+    wl = dataclasses.replace(WL.thermal_2d(n=(16, 512), ppc=2, vth=0.05, patch=(8, 8), precision="fp64"),
+                             solver="psatd", dt=0.09)
+    Fo, _, _ = oracle_psatd(wl, 5)
+    Fg, _ = gpu_fields(wl, 5)
+    e = fam_err(Fg, Fo)
+    say(f"5-step {e}")
+    assert max(e.values()) < 1e-10
+
+
 def test_spectral_3d_and_filter_match_oracle():
     say("case: spectral 3D fp64 with filter")
     wl = dataclasses.replace(WL.cylinder_3d(n=(16, 16, 16), radius=3.0, ppc_bg=2, ppc_cyl=16, patch=(4, 4, 4),

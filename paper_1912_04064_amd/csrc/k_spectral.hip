@@ -52,6 +52,80 @@ __device__ __forceinline__ int src_comp(int c, int par)
     return c < 3 ? f_E(par) + c : (c < 6 ? f_B(par) + c - 3 : F_J + c - 6);
 }
 
+// Radix-2 stages on `lines` lines of N values in LDS (twiddles tw[k] =
+// e^{sign 2 pi i k / N}, k < N/2).  Two consecutive stages are done per
+// pass with the four values they touch held in registers, so a transform
+// of 2^m points takes ceil(m / 2) barrier-separated passes instead of m.
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
+
+// decimation in time, bit-reversed input -> natural output
+__device__ __forceinline__ void fft_dit(double2 *buf, const double2 *tw, int N, int lines)
+{
+    const int tid = threadIdx.x;
+    int h = 1;   // half-length of the first stage of the pass
+    for (; 4 * h <= N; h *= 4) {
+        const int q4 = N / 4, st2 = N / (2 * h), st4 = N / (4 * h);
+        for (int t = tid; t < lines * q4; t += BLOCK) {
+            const int c = t / q4, q = t - c * q4, blk = q / h, pos = q - blk * h;
+            const int b = c * N + blk * 4 * h + pos;
+            const double2 w1 = tw[pos * st2];
+            const double2 t1 = cmul(buf[b + h], w1), t3 = cmul(buf[b + 3 * h], w1);
+            const double2 a0 = buf[b], a2 = buf[b + 2 * h];
+            const double2 b0 = cadd(a0, t1), b1 = csub(a0, t1), b2 = cadd(a2, t3), b3 = csub(a2, t3);
+            const double2 u2 = cmul(b2, tw[pos * st4]), u3 = cmul(b3, tw[(pos + h) * st4]);
+            buf[b] = cadd(b0, u2);
+            buf[b + 2 * h] = csub(b0, u2);
+            buf[b + h] = cadd(b1, u3);
+            buf[b + 3 * h] = csub(b1, u3);
+        }
+        __syncthreads();
+    }
+    if (2 * h == N) {   // an odd number of stages: the last one alone
+        for (int t = tid; t < lines * (N / 2); t += BLOCK) {
+            const int c = t / (N / 2), pos = t - c * (N / 2), i = c * N + pos;
+            const double2 u = buf[i], v = cmul(buf[i + h], tw[pos]);
+            buf[i] = cadd(u, v);
+            buf[i + h] = csub(u, v);
+        }
+        __syncthreads();
+    }
+}
+
+// decimation in frequency with the conjugate twiddles (the inverse of the
+// forward table), natural input -> bit-reversed output
+__device__ __forceinline__ void ifft_dif(double2 *buf, const double2 *tw, int N, int lines)
+{
+    const int tid = threadIdx.x;
+    int len = N;
+    for (; len >= 4; len /= 4) {
+        const int h = len / 4, q4 = N / 4, st4 = N / len, st2 = N / (2 * h);
+        for (int t = tid; t < lines * q4; t += BLOCK) {
+            const int c = t / q4, q = t - c * q4, blk = q / h, pos = q - blk * h;
+            const int b = c * N + blk * len + pos;
+            const double2 a0 = buf[b], a1 = buf[b + h], a2 = buf[b + 2 * h], a3 = buf[b + 3 * h];
+            const double2 b0 = cadd(a0, a2), b2 = cmul(csub(a0, a2), conjd(tw[pos * st4]));
+            const double2 b1 = cadd(a1, a3), b3 = cmul(csub(a1, a3), conjd(tw[(pos + h) * st4]));
+            const double2 w = conjd(tw[pos * st2]);
+            buf[b] = cadd(b0, b1);
+            buf[b + h] = cmul(csub(b0, b1), w);
+            buf[b + 2 * h] = cadd(b2, b3);
+            buf[b + 3 * h] = cmul(csub(b2, b3), w);
+        }
+        __syncthreads();
+    }
+    if (len == 2) {   // an odd number of stages: the last one alone (twiddle 1)
+        for (int t = tid; t < lines * (N / 2); t += BLOCK) {
+            const int i = 2 * t;
+            const double2 u = buf[i], v = buf[i + 1];
+            buf[i] = cadd(u, v);
+            buf[i + 1] = csub(u, v);
+        }
+        __syncthreads();
+    }
+}
+
 // 1D transforms of length N = n[axis] along `axis` of components [c0, c0+nc)
 // of the grid arrays; sign -1 forward, +1 inverse (unscaled).  A workgroup
 // transforms NL = max(1, FFT_BATCH / N) lines held in LDS (iterative
@@ -136,17 +210,7 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
             buf[l * N + r] = a[l * lstep + j * stride];
     }
     __syncthreads();
-    for (int len = 2; len <= N; len <<= 1) {
-        const int half = len >> 1, step = N / len;
-        for (int t = tid; t < tot / 2; t += BLOCK) {
-            const int l = t / (N / 2), b = t - l * (N / 2);
-            const int pos = b % half, i = l * N + (b / half) * len + pos;
-            const double2 u = buf[i], v = cmul(buf[i + half], tw[pos * step]);
-            buf[i] = make_double2(u.x + v.x, u.y + v.y);
-            buf[i + half] = make_double2(u.x - v.x, u.y - v.y);
-        }
-        __syncthreads();
-    }
+    fft_dit(buf, tw, N, NL);
     for (int e = tid; e < tot; e += BLOCK) {
         int l, j;
         if (axis == 0) {
@@ -298,18 +362,7 @@ __global__ __launch_bounds__(BLOCK) void spec_line_kernel(const RunDev *__restri
         buf[c * N + r] = rd.spec[c * ncell + line + j * stride];
     }
     __syncthreads();
-    // forward: decimation in time on bit-reversed input
-    for (int len = 2; len <= N; len <<= 1) {
-        const int half = len >> 1, step = N / len;
-        for (int t = tid; t < 9 * (N / 2); t += BLOCK) {
-            const int c = t / (N / 2), b = t - c * (N / 2);
-            const int pos = b % half, i = c * N + (b / half) * len + pos;
-            const double2 u = buf[i], v = cmul(buf[i + half], tw[pos * step]);
-            buf[i] = make_double2(u.x + v.x, u.y + v.y);
-            buf[i + half] = make_double2(u.x - v.x, u.y - v.y);
-        }
-        __syncthreads();
-    }
+    fft_dit(buf, tw, N, 9);   // forward, bit-reversed input
     // the exact step of each wavevector of the line
     const int i0 = (int)(line % n0), i1 = dims == 3 ? (int)(line / n0) : 0;
     for (int j = tid; j < N; j += BLOCK) {
@@ -322,19 +375,7 @@ __global__ __launch_bounds__(BLOCK) void spec_line_kernel(const RunDev *__restri
         for (int c = 0; c < 6; ++c) buf[c * N + j] = F[c];
     }
     __syncthreads();
-    // inverse: decimation in frequency with the conjugate twiddles
-    for (int len = N; len >= 2; len >>= 1) {
-        const int half = len >> 1, step = N / len;
-        for (int t = tid; t < 6 * (N / 2); t += BLOCK) {
-            const int c = t / (N / 2), b = t - c * (N / 2);
-            const int pos = b % half, i = c * N + (b / half) * len + pos;
-            const double2 u = buf[i], v = buf[i + half];
-            const double2 w = make_double2(tw[pos * step].x, -tw[pos * step].y);
-            buf[i] = make_double2(u.x + v.x, u.y + v.y);
-            buf[i + half] = cmul(make_double2(u.x - v.x, u.y - v.y), w);
-        }
-        __syncthreads();
-    }
+    ifft_dif(buf, tw, N, 6);   // inverse of E and B, bit-reversed output
     for (int e = tid; e < 6 * N; e += BLOCK) {
         const int c = e / N, j = e - c * N;
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;

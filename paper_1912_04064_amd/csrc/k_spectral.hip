@@ -53,77 +53,79 @@ __device__ __forceinline__ int src_comp(int c, int par)
 }
 
 // Radix-2 stages on `lines` lines of N values in LDS (twiddles tw[k] =
-// e^{sign 2 pi i k / N}, k < N/2).  Two consecutive stages are done per
-// pass with the four values they touch held in registers, so a transform
-// of 2^m points takes ceil(m / 2) barrier-separated passes instead of m.
+// e^{sign 2 pi i k / N}, k < N/2).  A pass takes the 2^R values that R
+// consecutive stages touch into registers (R = 3, then 2 or 1 for the
+// last stages), so a transform of 2^m points takes ceil(m / 3)
+// barrier-separated passes instead of m.
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
 
+// One pass of R stages whose first (DIT) or last (DIF) stage has half-length
+// h: the values at b + k h, k < 2^R, b = block * 2^R h + pos, pos < h.  DIT
+// stage s pairs k and k + 2^s (bit s of k clear) with the twiddle of the
+// pair's offset pos + (k mod 2^s) h in its block of 2^{s+1} h; DIF runs the
+// stages in the opposite order with (u + v, (u - v) conj(w)).
+template <int R, bool DIF>
+__device__ __forceinline__ void fft_pass(double2 *buf, const double2 *tw, int N, int lines, int h)
+{
+    constexpr int K = 1 << R;
+    const int groups = N / K;
+    for (int t = threadIdx.x; t < lines * groups; t += BLOCK) {
+        const int c = t / groups, q = t - c * groups, blk = q / h, pos = q - blk * h;
+        const int b = c * N + blk * K * h + pos;
+        double2 v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = buf[b + k * h];
+#pragma unroll
+        for (int ss = 0; ss < R; ++ss) {
+            const int s = DIF ? R - 1 - ss : ss;
+            const int half = h << s, st = N / (2 * half);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (k & (1 << s)) continue;
+                const int k2 = k + (1 << s);
+                const double2 w = tw[(pos + (k & ((1 << s) - 1)) * h) * st];
+                if constexpr (DIF) {
+                    const double2 u = v[k], x = v[k2];
+                    v[k] = cadd(u, x);
+                    v[k2] = cmul(csub(u, x), conjd(w));
+                } else {
+                    const double2 x = cmul(v[k2], w);
+                    v[k2] = csub(v[k], x);
+                    v[k] = cadd(v[k], x);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) buf[b + k * h] = v[k];
+    }
+    __syncthreads();
+}
+
 // decimation in time, bit-reversed input -> natural output
 __device__ __forceinline__ void fft_dit(double2 *buf, const double2 *tw, int N, int lines)
 {
-    const int tid = threadIdx.x;
-    int h = 1;   // half-length of the first stage of the pass
-    for (; 4 * h <= N; h *= 4) {
-        const int q4 = N / 4, st2 = N / (2 * h), st4 = N / (4 * h);
-        for (int t = tid; t < lines * q4; t += BLOCK) {
-            const int c = t / q4, q = t - c * q4, blk = q / h, pos = q - blk * h;
-            const int b = c * N + blk * 4 * h + pos;
-            const double2 w1 = tw[pos * st2];
-            const double2 t1 = cmul(buf[b + h], w1), t3 = cmul(buf[b + 3 * h], w1);
-            const double2 a0 = buf[b], a2 = buf[b + 2 * h];
-            const double2 b0 = cadd(a0, t1), b1 = csub(a0, t1), b2 = cadd(a2, t3), b3 = csub(a2, t3);
-            const double2 u2 = cmul(b2, tw[pos * st4]), u3 = cmul(b3, tw[(pos + h) * st4]);
-            buf[b] = cadd(b0, u2);
-            buf[b + 2 * h] = csub(b0, u2);
-            buf[b + h] = cadd(b1, u3);
-            buf[b + 3 * h] = csub(b1, u3);
-        }
-        __syncthreads();
+    int h = 1;   // half-length of the first stage of the next pass
+    for (; 8 * h <= N; h *= 8) fft_pass<3, false>(buf, tw, N, lines, h);
+    if (4 * h <= N) {
+        fft_pass<2, false>(buf, tw, N, lines, h);
+        h *= 4;
     }
-    if (2 * h == N) {   // an odd number of stages: the last one alone
-        for (int t = tid; t < lines * (N / 2); t += BLOCK) {
-            const int c = t / (N / 2), pos = t - c * (N / 2), i = c * N + pos;
-            const double2 u = buf[i], v = cmul(buf[i + h], tw[pos]);
-            buf[i] = cadd(u, v);
-            buf[i + h] = csub(u, v);
-        }
-        __syncthreads();
-    }
+    if (2 * h <= N) fft_pass<1, false>(buf, tw, N, lines, h);
 }
 
 // decimation in frequency with the conjugate twiddles (the inverse of the
 // forward table), natural input -> bit-reversed output
 __device__ __forceinline__ void ifft_dif(double2 *buf, const double2 *tw, int N, int lines)
 {
-    const int tid = threadIdx.x;
-    int len = N;
-    for (; len >= 4; len /= 4) {
-        const int h = len / 4, q4 = N / 4, st4 = N / len, st2 = N / (2 * h);
-        for (int t = tid; t < lines * q4; t += BLOCK) {
-            const int c = t / q4, q = t - c * q4, blk = q / h, pos = q - blk * h;
-            const int b = c * N + blk * len + pos;
-            const double2 a0 = buf[b], a1 = buf[b + h], a2 = buf[b + 2 * h], a3 = buf[b + 3 * h];
-            const double2 b0 = cadd(a0, a2), b2 = cmul(csub(a0, a2), conjd(tw[pos * st4]));
-            const double2 b1 = cadd(a1, a3), b3 = cmul(csub(a1, a3), conjd(tw[(pos + h) * st4]));
-            const double2 w = conjd(tw[pos * st2]);
-            buf[b] = cadd(b0, b1);
-            buf[b + h] = cmul(csub(b0, b1), w);
-            buf[b + 2 * h] = cadd(b2, b3);
-            buf[b + 3 * h] = cmul(csub(b2, b3), w);
-        }
-        __syncthreads();
+    int len = N;   // block length of the first stage of the next pass
+    for (; len >= 8; len /= 8) fft_pass<3, true>(buf, tw, N, lines, len / 8);
+    if (len >= 4) {
+        fft_pass<2, true>(buf, tw, N, lines, len / 4);
+        len /= 4;
     }
-    if (len == 2) {   // an odd number of stages: the last one alone (twiddle 1)
-        for (int t = tid; t < lines * (N / 2); t += BLOCK) {
-            const int i = 2 * t;
-            const double2 u = buf[i], v = buf[i + 1];
-            buf[i] = cadd(u, v);
-            buf[i + 1] = csub(u, v);
-        }
-        __syncthreads();
-    }
+    if (len >= 2) fft_pass<1, true>(buf, tw, N, lines, len / 2);
 }
 
 // 1D transforms of length N = n[axis] along `axis` of components [c0, c0+nc)

@@ -182,10 +182,11 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
     }
     const int comp = c0 + blockIdx.y;
     double2 *a = rd.spec + (long long)comp * ncell + o;
-    // grid offset -> region element (the region's interior is the grid)
-    auto relem = [&](long long g) {
-        const int i = (int)(g % n0), j = (int)((g / n0) % n1), k = (int)(g / ((long long)n0 * n1));
-        return rindex(rd, i, j, k);
+    // element j of x line l of the batch -> region element (the region's
+    // interior is the grid; the region reads and writes are along x only)
+    auto relem = [&](int l, int j) {
+        const long long line = o / n0 + l;
+        return rindex(rd, 0, (int)(line % n1), (int)(line / n1)) + j;
     };
     int logn = 0;
     while ((1 << logn) < N) ++logn;
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
         }
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
         if constexpr (IN_REGION)
-            buf[l * N + r] = make_double2(rcomp(rd, 0, src_comp(comp, par))[relem(o + l * lstep + j * stride)], 0.0);
+            buf[l * N + r] = make_double2(rcomp(rd, 0, src_comp(comp, par))[relem(l, j)], 0.0);
         else
             buf[l * N + r] = a[l * lstep + j * stride];
     }
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
             j = e / NL;
         }
         if constexpr (OUT_REGION) {
-            const long long p = relem(o + l * lstep + j * stride);
+            const long long p = relem(l, j);
             const double v = buf[l * N + j].x / (double)ncell;
             if (comp < 3) {
                 rcomp(rd, 0, f_E(1 - par) + comp)[p] = v;

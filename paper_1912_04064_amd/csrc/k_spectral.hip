@@ -327,30 +327,35 @@ __global__ void spec_kspace_kernel(const RunDev *__restrict__ runs, int run, int
     for (int c = 0; c < 6; ++c) rd.spec[c * ncell + gid] = F[c];
 }
 
-// One line along the last axis, all 9 components in LDS: forward transform
-// (bit-reversed load, decimation in time), the exact step of each of the
-// line's wavevectors, inverse transform of the 6 E and B components
-// (decimation in frequency: natural order in, bit-reversed order out, read
-// back bit-reversed on the store).  The lines are dealt to the XCDs in
-// contiguous bands (workgroup l runs on XCD l % 8), so the lines a cache
-// line of the grid holds are read on one XCD.
-constexpr int SPEC_LINE_MAX = 256;   // 9 x 256 complex values: 36 KB of LDS (dynamic LDS stays under 64 KB)
+// NL adjacent lines along the last axis (adjacent in x), all 9 components
+// in LDS: forward transform (bit-reversed load, decimation in time), the
+// exact step of each of the lines' wavevectors, inverse transform of the 6
+// E and B components (decimation in frequency: natural order in,
+// bit-reversed order out, read back bit-reversed on the store).  Taking
+// adjacent x lines together makes every grid row a contiguous read of NL
+// values.  The line groups are dealt to the XCDs in contiguous bands
+// (workgroup l runs on XCD l % 8), so the neighbouring groups that share the
+// grid's cache lines run on one XCD.
+constexpr int SPEC_LINE_MAX = 256;   // nodes of the last axis the line kernel takes
 
+template <int NL>
 __global__ __launch_bounds__(BLOCK) void spec_line_kernel(const RunDev *__restrict__ runs, int run, int par)
 {
-    extern __shared__ double2 sm[];
+    __shared__ double2 sm[NL * 9 * SPEC_LINE_MAX + SPEC_LINE_MAX / 2];
     const RunDev &rd = runs[run];
     if (rd.ctl->remaining[par] == 0) return;
     const int dims = rd.dims, ax = dims - 1;
     const int n0 = rd.n[0], n1 = rd.n[1];
     const long long ncell = (long long)n0 * n1 * rd.n[2];
     const int N = rd.n[ax];
-    const long long nlines = ncell / N;
-    const long long band = (nlines + 7) / 8;
-    const long long line = (long long)(blockIdx.x & 7) * band + (blockIdx.x >> 3);
-    if ((blockIdx.x >> 3) >= band || line >= nlines) return;
+    const long long nlines = ncell / N, ngroups = nlines / NL;
+    const long long band = (ngroups + 7) / 8;
+    const long long grp = (long long)(blockIdx.x & 7) * band + (blockIdx.x >> 3);
+    if ((blockIdx.x >> 3) >= band || grp >= ngroups) return;
+    const long long line0 = grp * NL;
     const long long stride = nlines;   // the last axis is the slowest: its lines are every nlines-th element
-    double2 *buf = sm, *tw = sm + 9 * N;
+    // layout: component-major, then line, then node: the 6 E and B lines first
+    double2 *buf = sm, *tw = sm + NL * 9 * N;
     int logn = 0;
     while ((1 << logn) < N) ++logn;
     const int tid = threadIdx.x;
@@ -359,30 +364,31 @@ __global__ __launch_bounds__(BLOCK) void spec_line_kernel(const RunDev *__restri
         sincospi((double)(-2 * k) / (double)N, &sn, &cs);
         tw[k] = make_double2(cs, sn);   // forward twiddles e^{-2 pi i k / N}; the inverse uses their conjugates
     }
-    for (int e = tid; e < 9 * N; e += BLOCK) {
-        const int c = e / N, j = e - c * N;
+    for (int e = tid; e < 9 * NL * N; e += BLOCK) {
+        const int l = e % NL, j = (e / NL) % N, c = e / (NL * N);
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
-        buf[c * N + r] = rd.spec[c * ncell + line + j * stride];
+        buf[(c * NL + l) * N + r] = rd.spec[c * ncell + line0 + l + j * stride];
     }
     __syncthreads();
-    fft_dit(buf, tw, N, 9);   // forward, bit-reversed input
-    // the exact step of each wavevector of the line
-    const int i0 = (int)(line % n0), i1 = dims == 3 ? (int)(line / n0) : 0;
-    for (int j = tid; j < N; j += BLOCK) {
-        const int idx[3] = {i0, dims == 3 ? i1 : j, dims == 3 ? j : 0};
+    fft_dit(buf, tw, N, 9 * NL);   // forward, bit-reversed input
+    // the exact step of each wavevector of the lines
+    for (int e = tid; e < NL * N; e += BLOCK) {
+        const int l = e % NL, j = e / NL;
+        const long long line = line0 + l;
+        const int idx[3] = {(int)(line % n0), dims == 3 ? (int)(line / n0) : j, dims == 3 ? j : 0};
         double2 F[9];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) F[c] = buf[c * N + j];
+        for (int c = 0; c < 9; ++c) F[c] = buf[(c * NL + l) * N + j];
         kspace_step(rd, idx, F);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) buf[c * N + j] = F[c];
+        for (int c = 0; c < 6; ++c) buf[(c * NL + l) * N + j] = F[c];
     }
     __syncthreads();
-    ifft_dif(buf, tw, N, 6);   // inverse of E and B, bit-reversed output
-    for (int e = tid; e < 6 * N; e += BLOCK) {
-        const int c = e / N, j = e - c * N;
+    ifft_dif(buf, tw, N, 6 * NL);   // inverse of E and B, bit-reversed output
+    for (int e = tid; e < 6 * NL * N; e += BLOCK) {
+        const int l = e % NL, j = (e / NL) % N, c = e / (NL * N);
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
-        rd.spec[c * ncell + line + j * stride] = buf[c * N + r];
+        rd.spec[c * ncell + line0 + l + j * stride] = buf[(c * NL + l) * N + r];
     }
 }
 
@@ -399,10 +405,14 @@ hipError_t launch_spectral(const RunDev *runs, int run, int dims, const int n[3]
     fft(spec_fft_kernel<true, false>, 0, 9, -1);
     for (int a = 1; a < last; ++a) fft(spec_fft_kernel<false, false>, a, 9, -1);
     if (n[last] <= SPEC_LINE_MAX) {
+        // two adjacent x lines per workgroup (n[0] is a power of two, at least one patch of 4 cells)
         const long long nlines = ncell / n[last];
-        const unsigned grid = (unsigned)(8 * ((nlines + 7) / 8));
-        const size_t lds = ((size_t)9 * n[last] + n[last] / 2) * sizeof(double2);
-        spec_line_kernel<<<grid, BLOCK, lds, s>>>(runs, run, par);
+        if (nlines % 2 == 0) {
+            const long long ngroups = nlines / 2;
+            spec_line_kernel<2><<<(unsigned)(8 * ((ngroups + 7) / 8)), BLOCK, 0, s>>>(runs, run, par);
+        } else {
+            spec_line_kernel<1><<<(unsigned)(8 * ((nlines + 7) / 8)), BLOCK, 0, s>>>(runs, run, par);
+        }
     } else {
         fft(spec_fft_kernel<false, false>, last, 9, -1);
         spec_kspace_kernel<<<(unsigned)((ncell + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(runs, run, par);

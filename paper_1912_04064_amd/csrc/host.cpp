@@ -398,7 +398,7 @@ static int make_layout(const pic_config *cfg, const int P[3], bool det, Layout &
     b += 7 * align256((size_t)(L.n_patch + 1) * 4) + 7 * align256((size_t)(L.seg_max + 1) * 4);
     b += 2 * (size_t)L.cap_total * per + align256((size_t)L.cap_total * 4);
     b += 2 * (size_t)std::max<long long>(L.n_total, 1) * (per + 4);
-    if (cfg->field_solver == PIC_SOLVER_PSATD) b += align256((size_t)9 * ncell * 16);
+    if (cfg->field_solver == PIC_SOLVER_PSATD) b += align256((size_t)SPEC_ARRAYS * ncell * 16);
     b += align256((size_t)ncell * 8);   // initial Gauss residual
     b += 64 * 256;   // per-array rounding and the control block
     L.resident = b;
@@ -835,7 +835,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg_in)
     ok = ok && d.lpatch && d.spatch && d.lopatch && d.nlv && d.tflag;
     d.spec = nullptr;
     if (d.solver == PIC_SOLVER_PSATD) {
-        d.spec = (double2 *)run_alloc(c, r, (size_t)9 * r.ncell * 16);
+        d.spec = (double2 *)run_alloc(c, r, (size_t)SPEC_ARRAYS * r.ncell * 16);
         ok = ok && d.spec;
     }
     r.gauss0 = (double *)run_alloc(c, r, (size_t)r.ncell * 8);

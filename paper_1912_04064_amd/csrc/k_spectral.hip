@@ -2,22 +2,41 @@
 // with one periodic region and power-of-two grids.
 //
 // The field kernel has already summed the patch tiles into the region's J
-// (transfer (i) of section 2.2, and the current filter).  Then:
-//   fft x    region E^n, B^n, J (real) -> 9 complex arrays of the grid,
-//            transformed along x (one workgroup per batch of x lines, the
-//            lines held in LDS: iterative radix-2, bit-reversed load);
+// (transfer (i) of section 2.2, and the current filter).  The 9 real
+// components E, B, J are transformed two at a time: array p holds
+// component 2p in its real and component 2p + 1 in its imaginary part
+// (5 complex arrays, the last with Jz alone), so every transform carries
+// two real fields.  Then:
+//   fft x    region E^n, B^n, J (real) -> the 5 packed arrays, transformed
+//            along x (one workgroup per batch of x lines, the lines held in
+//            LDS: iterative radix-2, bit-reversed load);
 //   fft y    (3D) along y;
-//   line     along the last axis, all 9 components of one line in LDS:
-//            forward transform, the exact step of every wavevector of the
-//            line (move each component to its staggered position, phase
+//   line     along the last axis, a line and its mirror line (all other
+//            wavevector components negated) in LDS: forward transform,
+//            then for each wavevector k and its mirror -k together: split
+//            the packed pairs (the transform A of a real field has
+//            A(-k) = conj A(k), so Z = A + iB gives A = (Z(k) + conj
+//            Z(-k)) / 2 and B = (Z(k) - conj Z(-k)) / 2i), the exact step
+//            (move each component to its staggered position, phase
 //            e^{-i k.s}; advance E, B over dt with J held at J^{n+1/2},
-//            equations below; move back), inverse transform of E, B;
-//            lines too long for the LDS take the three steps as separate
-//            launches over the whole grid instead;
+//            equations below; move back), repack E, B in pairs, inverse
+//            transform of the 3 E/B arrays; lines too long for the LDS
+//            take the three steps as separate launches over the whole
+//            grid instead;
 //   ifft y   (3D) inverse along y;
-//   ifft x   inverse along x -> real parts / (nx ny nz) = E^{n+1},
-//            B^{n+1} and Bm^{n+1} = B^{n+1} in the other E/B buffer; the
-//            post kernel exchanges the ghost layers as for the Yee update.
+//   ifft x   inverse along x -> real and imaginary parts / (nx ny nz) =
+//            E^{n+1}, B^{n+1} and Bm^{n+1} = B^{n+1} in the other E/B
+//            buffer; the post kernel exchanges the ghost layers as for the
+//            Yee update.
+// The update takes the real part of each inverse transform, that is, the
+// Hermitian part (A'(k) + conj A'(-k)) / 2 of each stepped spectrum.  On the
+// Yee lattice the step maps conj A(k) at -k to the conjugate of its result
+// at k for every wavevector, the Nyquist planes included: each lattice
+// wavenumber k~_a enters multiplied by a half-cell shift e^{-+i k_a d_a / 2}
+// along the same axis, and where the sampled -pi/d stands for +pi/d both
+// change sign together.  So the stepped spectra are Hermitian, the step at k
+// gives the one at -k by conjugation, and the inverse transform of the
+// repacked Z' = A' + iB' returns A' and B' as its real and imaginary parts.
 // With the lattice wavenumber k~_a = 2 sin(k_a d_a / 2) / d_a, w = |k~|,
 // kappa = k~ / w, C = cos(w dt), S = sin(w dt):
 //   E' = C E + (1 - C) kappa (kappa.E) + i S kappa x B - (S/w) J
@@ -129,7 +148,7 @@ __device__ __forceinline__ void ifft_dif(double2 *buf, const double2 *tw, int N,
 }
 
 // 1D transforms of length N = n[axis] along `axis` of components [c0, c0+nc)
-// of the grid arrays; sign -1 forward, +1 inverse (unscaled).  A workgroup
+// of the packed grid arrays; sign -1 forward, +1 inverse (unscaled).  A workgroup
 // transforms NL = max(1, FFT_BATCH / N) lines held in LDS (iterative
 // radix-2, bit-reversed load, one twiddle table per workgroup).  Lines along
 // y or z are taken NL adjacent in x, so every row of the batch is a
@@ -144,10 +163,11 @@ __host__ __device__ inline int fft_lines_per_group(int N, int axis, const int n[
     return nl;
 }
 
-// IN_REGION: the lines are read from the region's real E^n, B^n, J (the
-// first forward transform); OUT_REGION: the real parts, divided by the
-// number of cells, are written to the region's E^{n+1}, B^{n+1} and Bm (the
-// last inverse transform).
+// IN_REGION: the lines of packed array c are read from the region's real
+// components 2c and 2c + 1 of E^n, B^n, J (the first forward transform);
+// OUT_REGION: the real and imaginary parts, divided by the number of cells,
+// are written to components 2c and 2c + 1 of the region's E^{n+1}, B^{n+1}
+// and Bm (the last inverse transform).
 template <bool IN_REGION, bool OUT_REGION>
 __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restrict__ runs, int run, int par, int axis,
                                                          int c0, int sign)
@@ -207,9 +227,11 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
             j = e / NL;
         }
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
-        if constexpr (IN_REGION)
-            buf[l * N + r] = make_double2(rcomp(rd, 0, src_comp(comp, par))[relem(l, j)], 0.0);
-        else
+        if constexpr (IN_REGION) {
+            const long long q = relem(l, j);
+            buf[l * N + r] = make_double2(rcomp(rd, 0, src_comp(2 * comp, par))[q],
+                                          2 * comp + 1 < 9 ? rcomp(rd, 0, src_comp(2 * comp + 1, par))[q] : 0.0);
+        } else
             buf[l * N + r] = a[l * lstep + j * stride];
     }
     __syncthreads();
@@ -225,12 +247,17 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
         }
         if constexpr (OUT_REGION) {
             const long long p = relem(l, j);
-            const double v = buf[l * N + j].x / (double)ncell;
-            if (comp < 3) {
-                rcomp(rd, 0, f_E(1 - par) + comp)[p] = v;
-            } else {
-                rcomp(rd, 0, f_B(1 - par) + comp - 3)[p] = v;
-                rcomp(rd, 0, F_BM + comp - 3)[p] = v;
+            const double2 z = buf[l * N + j];
+            const double v[2] = {z.x / (double)ncell, z.y / (double)ncell};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int c = 2 * comp + h;
+                if (c < 3) {
+                    rcomp(rd, 0, f_E(1 - par) + c)[p] = v[h];
+                } else {
+                    rcomp(rd, 0, f_B(1 - par) + c - 3)[p] = v[h];
+                    rcomp(rd, 0, F_BM + c - 3)[p] = v[h];
+                }
             }
         } else {
             a[l * lstep + j * stride] = buf[l * N + j];
@@ -309,8 +336,43 @@ __device__ __forceinline__ void kspace_step(const RunDev &rd, const int idx[3], 
     for (int c = 0; c < 6; ++c) F[c] = cmul(c < 3 ? En[c] : Bn[c - 3], shift(c));
 }
 
-// exact step of every wavevector of the grid (lines too long for spec_line_kernel)
-__global__ void spec_kspace_kernel(const RunDev *__restrict__ runs, int run, int par)
+// The step of wavevector k (grid index idx) and, by conjugation, of its
+// mirror -k: pa, pb point at the packed arrays' values at k and -k, ps
+// apart.  Splits the 5 pairs into the 9 spectra at k, steps them and writes
+// the 3 repacked E/B pairs at k and at -k (at a wavevector that is its own
+// mirror, the spectra of the real fields are real).
+__device__ __forceinline__ void spec_pair_step(const RunDev &rd, double2 *pa, double2 *pb, long long ps,
+                                               const int idx[3])
+{
+    double2 F[9];
+#pragma unroll
+    for (int p = 0; p < SPEC_ARRAYS; ++p) {
+        const double2 z = pa[p * ps], zm = conjd(pb[p * ps]);
+        F[2 * p] = make_double2(0.5 * (z.x + zm.x), 0.5 * (z.y + zm.y));
+        if (2 * p + 1 < 9) F[2 * p + 1] = make_double2(0.5 * (z.y - zm.y), -0.5 * (z.x - zm.x));
+    }
+    kspace_step(rd, idx, F);
+    const bool self = pa == pb;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        double2 u = F[2 * p], v = F[2 * p + 1];
+        if (self) u.y = v.y = 0.0;
+        pa[p * ps] = make_double2(u.x - v.y, u.y + v.x);                 // u + i v
+        if (!self) pb[p * ps] = make_double2(u.x + v.y, v.x - u.y);      // conj u + i conj v
+    }
+}
+
+// the mirror index (-i mod n) on every axis
+__device__ __forceinline__ void mirror_index(const RunDev &rd, const int idx[3], int m[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) m[a] = (rd.n[a] - idx[a]) & (rd.n[a] - 1);
+}
+
+// exact step of every wavevector of the grid (lines too long for
+// spec_line_kernel): one thread per wavevector pair, taken by the one of
+// the two with the lower linear index
+__global__ __launch_bounds__(BLOCK) void spec_kspace_kernel(const RunDev *__restrict__ runs, int run, int par)
 {
     const RunDev &rd = runs[run];
     if (rd.ctl->remaining[par] == 0) return;
@@ -319,43 +381,72 @@ __global__ void spec_kspace_kernel(const RunDev *__restrict__ runs, int run, int
     if (gid >= ncell) return;
     const int idx[3] = {(int)(gid % rd.n[0]), (int)((gid / rd.n[0]) % rd.n[1]),
                         (int)(gid / ((long long)rd.n[0] * rd.n[1]))};
-    double2 F[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) F[c] = rd.spec[c * ncell + gid];
-    kspace_step(rd, idx, F);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) rd.spec[c * ncell + gid] = F[c];
+    int idxm[3];
+    mirror_index(rd, idx, idxm);
+    const long long gm = idxm[0] + (long long)rd.n[0] * (idxm[1] + (long long)rd.n[1] * idxm[2]);
+    if (gm < gid) return;
+    spec_pair_step(rd, rd.spec + gid, rd.spec + gm, ncell, idx);
 }
 
-// NL adjacent lines along the last axis (adjacent in x), all 9 components
-// in LDS: forward transform (bit-reversed load, decimation in time), the
-// exact step of each of the lines' wavevectors, inverse transform of the 6
-// E and B components (decimation in frequency: natural order in,
-// bit-reversed order out, read back bit-reversed on the store).  Taking
-// adjacent x lines together makes every grid row a contiguous read of NL
-// values.  The line groups are dealt to the XCDs in contiguous bands
-// (workgroup l runs on XCD l % 8), so the neighbouring groups that share the
-// grid's cache lines run on one XCD.
+// Two lines along the last axis in LDS, all 5 packed arrays: a line and its
+// mirror line, or two lines that are their own mirrors (x and, in 3D, y
+// each 0 or n/2).  Forward transform (bit-reversed load, decimation in
+// time), the paired step of each wavevector, inverse transform of the 3
+// E/B arrays (decimation in frequency: natural order in, bit-reversed order
+// out, read back bit-reversed on the store).  The line pairs are dealt to
+// the XCDs in contiguous bands (workgroup l runs on XCD l % 8), so pairs
+// that share the grid's cache lines run on one XCD.
 constexpr int SPEC_LINE_MAX = 256;   // nodes of the last axis the line kernel takes
 
-template <int NL>
+// line pair g of the plane across the last axis (lines x + n0 y; 2D: y = 0,
+// n1 = 1): pairs (x, y) with (-x, -y) for 0 < x < n0/2; the columns x = 0
+// and x = n0/2 pair (x, y) with (x, -y) for 0 < y < n1/2, and their four
+// self-mirror lines y = 0, n1/2 go two to a group.  Returns whether the two
+// lines are each their own mirror.
+__device__ __forceinline__ bool line_pair(long long g, int dims, int n0, int n1, long long L[2])
+{
+    const int hx = n0 / 2;
+    if (dims == 2) {
+        L[0] = g == 0 ? 0 : g;
+        L[1] = g == 0 ? hx : n0 - g;
+        return g == 0;
+    }
+    const int gx = (int)(g % hx), y = (int)(g / hx), hy = n1 / 2;
+    if (gx > 0) {
+        L[0] = gx + (long long)n0 * y;
+        L[1] = (n0 - gx) + (long long)n0 * ((n1 - y) & (n1 - 1));
+        return false;
+    }
+    if (y == 0 || y == hy) {
+        const int x = y == 0 ? 0 : hx;
+        L[0] = x;
+        L[1] = x + (long long)n0 * hy;
+        return true;
+    }
+    const int x = y < hy ? 0 : hx, yy = y < hy ? y : y - hy;
+    L[0] = x + (long long)n0 * yy;
+    L[1] = x + (long long)n0 * (n1 - yy);
+    return false;
+}
+
 __global__ __launch_bounds__(BLOCK) void spec_line_kernel(const RunDev *__restrict__ runs, int run, int par)
 {
-    __shared__ double2 sm[NL * 9 * SPEC_LINE_MAX + SPEC_LINE_MAX / 2];
+    __shared__ double2 sm[2 * SPEC_ARRAYS * SPEC_LINE_MAX + SPEC_LINE_MAX / 2];
     const RunDev &rd = runs[run];
     if (rd.ctl->remaining[par] == 0) return;
     const int dims = rd.dims, ax = dims - 1;
     const int n0 = rd.n[0], n1 = rd.n[1];
     const long long ncell = (long long)n0 * n1 * rd.n[2];
     const int N = rd.n[ax];
-    const long long nlines = ncell / N, ngroups = nlines / NL;
+    const long long nlines = ncell / N, ngroups = nlines / 2;
     const long long band = (ngroups + 7) / 8;
     const long long grp = (long long)(blockIdx.x & 7) * band + (blockIdx.x >> 3);
     if ((blockIdx.x >> 3) >= band || grp >= ngroups) return;
-    const long long line0 = grp * NL;
+    long long L[2];
+    const bool selfpair = line_pair(grp, dims, n0, n1, L);
     const long long stride = nlines;   // the last axis is the slowest: its lines are every nlines-th element
-    // layout: component-major, then line, then node: the 6 E and B lines first
-    double2 *buf = sm, *tw = sm + NL * 9 * N;
+    // layout: array-major, then line, then node: the 3 E/B arrays first
+    double2 *buf = sm, *tw = sm + 2 * SPEC_ARRAYS * N;
     int logn = 0;
     while ((1 << logn) < N) ++logn;
     const int tid = threadIdx.x;
@@ -364,31 +455,29 @@ __global__ __launch_bounds__(BLOCK) void spec_line_kernel(const RunDev *__restri
         sincospi((double)(-2 * k) / (double)N, &sn, &cs);
         tw[k] = make_double2(cs, sn);   // forward twiddles e^{-2 pi i k / N}; the inverse uses their conjugates
     }
-    for (int e = tid; e < 9 * NL * N; e += BLOCK) {
-        const int l = e % NL, j = (e / NL) % N, c = e / (NL * N);
+    for (int e = tid; e < 2 * SPEC_ARRAYS * N; e += BLOCK) {
+        const int l = e & 1, j = (e >> 1) % N, p = e / (2 * N);
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
-        buf[(c * NL + l) * N + r] = rd.spec[c * ncell + line0 + l + j * stride];
+        buf[(2 * p + l) * N + r] = rd.spec[p * ncell + L[l] + j * stride];
     }
     __syncthreads();
-    fft_dit(buf, tw, N, 9 * NL);   // forward, bit-reversed input
-    // the exact step of each wavevector of the lines
-    for (int e = tid; e < NL * N; e += BLOCK) {
-        const int l = e % NL, j = e / NL;
-        const long long line = line0 + l;
-        const int idx[3] = {(int)(line % n0), dims == 3 ? (int)(line / n0) : j, dims == 3 ? j : 0};
-        double2 F[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) F[c] = buf[(c * NL + l) * N + j];
-        kspace_step(rd, idx, F);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) buf[(c * NL + l) * N + j] = F[c];
+    fft_dit(buf, tw, N, 2 * SPEC_ARRAYS);   // forward, bit-reversed input
+    // the paired steps: (line 0, j) with (line 1, -j), or within each
+    // self-mirror line j with -j for j <= N/2
+    const int half = N / 2 + 1, ntask = selfpair ? 2 * half : N;
+    for (int t = tid; t < ntask; t += BLOCK) {
+        const int l = selfpair ? t / half : 0, j = selfpair ? t - l * half : t;
+        const int lm = selfpair ? l : 1, jm = (N - j) & (N - 1);
+        const long long ln = L[l];
+        const int idx[3] = {(int)(ln % n0), dims == 3 ? (int)(ln / n0) : j, dims == 3 ? j : 0};
+        spec_pair_step(rd, buf + l * N + j, buf + lm * N + jm, 2 * N, idx);
     }
     __syncthreads();
-    ifft_dif(buf, tw, N, 6 * NL);   // inverse of E and B, bit-reversed output
-    for (int e = tid; e < 6 * NL * N; e += BLOCK) {
-        const int l = e % NL, j = (e / NL) % N, c = e / (NL * N);
+    ifft_dif(buf, tw, N, 2 * 3);   // inverse of the E/B arrays, bit-reversed output
+    for (int e = tid; e < 2 * 3 * N; e += BLOCK) {
+        const int l = e & 1, j = (e >> 1) % N, p = e / (2 * N);
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
-        rd.spec[c * ncell + line0 + l + j * stride] = buf[(c * NL + l) * N + r];
+        rd.spec[p * ncell + L[l] + j * stride] = buf[(2 * p + l) * N + r];
     }
 }
 
@@ -402,25 +491,22 @@ hipError_t launch_spectral(const RunDev *runs, int run, int dims, const int n[3]
         kern<<<dim3((unsigned)(ncell / n[a] / nl), ncomp), BLOCK, lds, s>>>(runs, run, par, a, 0, sign);
     };
     // forward along x, reading the region's fields; then the middle axis (3D)
-    fft(spec_fft_kernel<true, false>, 0, 9, -1);
-    for (int a = 1; a < last; ++a) fft(spec_fft_kernel<false, false>, a, 9, -1);
+    fft(spec_fft_kernel<true, false>, 0, SPEC_ARRAYS, -1);
+    for (int a = 1; a < last; ++a) fft(spec_fft_kernel<false, false>, a, SPEC_ARRAYS, -1);
     if (n[last] <= SPEC_LINE_MAX) {
-        // two adjacent x lines per workgroup (n[0] is a power of two, at least one patch of 4 cells)
-        const long long nlines = ncell / n[last];
-        if (nlines % 2 == 0) {
-            const long long ngroups = nlines / 2;
-            spec_line_kernel<2><<<(unsigned)(8 * ((ngroups + 7) / 8)), BLOCK, 0, s>>>(runs, run, par);
-        } else {
-            spec_line_kernel<1><<<(unsigned)(8 * ((nlines + 7) / 8)), BLOCK, 0, s>>>(runs, run, par);
-        }
+        // a pair of lines per workgroup (the plane across the last axis has
+        // an even number of lines: n[0] is a power of two of at least one
+        // patch of 4 cells)
+        const long long ngroups = ncell / n[last] / 2;
+        spec_line_kernel<<<(unsigned)(8 * ((ngroups + 7) / 8)), BLOCK, 0, s>>>(runs, run, par);
     } else {
-        fft(spec_fft_kernel<false, false>, last, 9, -1);
+        fft(spec_fft_kernel<false, false>, last, SPEC_ARRAYS, -1);
         spec_kspace_kernel<<<(unsigned)((ncell + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(runs, run, par);
-        fft(spec_fft_kernel<false, false>, last, 6, +1);
+        fft(spec_fft_kernel<false, false>, last, 3, +1);
     }
     // inverse along the middle axis (3D), then along x into the region
-    for (int a = last - 1; a >= 1; --a) fft(spec_fft_kernel<false, false>, a, 6, +1);
-    fft(spec_fft_kernel<false, true>, 0, 6, +1);
+    for (int a = last - 1; a >= 1; --a) fft(spec_fft_kernel<false, false>, a, 3, +1);
+    fft(spec_fft_kernel<false, true>, 0, 3, +1);
     return hipGetLastError();
 }
 

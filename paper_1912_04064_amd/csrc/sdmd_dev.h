@@ -44,6 +44,7 @@ __host__ __device__ inline int f_E(int par) { return F_E0 + 3 * par; }
 __host__ __device__ inline int f_B(int par) { return F_B0 + 3 * par; }
 
 constexpr int BLOCK = 256;     // threads per workgroup of the step kernels
+constexpr int SPEC_ARRAYS = 5;   // spectral solver: the 9 real E, B, J components, two per complex array
 
 // A re-layout moves each patch's particles in chunks of MOVE_CHUNK, one
 // workgroup per chunk; at most n_patch + ceil(N / MOVE_CHUNK) chunks exist.
@@ -144,7 +145,7 @@ struct RunDev {
     int *lpatch, *spatch;
     int *nlv;            // [seg_max] leavers of each segment this step, in lv at sseg[s]
     int *tflag;          // [seg_max] 1 when the segment's tile in HBM may hold non-zero values
-    double2 *spec;       // spectral solver: 9 complex arrays [E, B, J][z][y][x] of the grid
+    double2 *spec;       // spectral solver: SPEC_ARRAYS complex arrays [z][y][x] of the grid (components packed in pairs)
     Store lo;            // overflow leavers (parked particles re-entering)
     int *lopatch;
     Ctl *ctl;

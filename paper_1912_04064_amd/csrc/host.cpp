@@ -398,7 +398,7 @@ static int make_layout(const pic_config *cfg, const int P[3], bool det, Layout &
     b += 7 * align256((size_t)(L.n_patch + 1) * 4) + 7 * align256((size_t)(L.seg_max + 1) * 4);
     b += 2 * (size_t)L.cap_total * per + align256((size_t)L.cap_total * 4);
     b += 2 * (size_t)std::max<long long>(L.n_total, 1) * (per + 4);
-    if (cfg->field_solver == PIC_SOLVER_PSATD) b += align256((size_t)SPEC_ARRAYS * ncell * 16);
+    if (cfg->field_solver == PIC_SOLVER_PSATD) b += align256((size_t)SPEC_ARRAYS * ncell * 16) + align256((size_t)SPEC_TW_LEN * 16);
     b += align256((size_t)ncell * 8);   // initial Gauss residual
     b += 64 * 256;   // per-array rounding and the control block
     L.resident = b;
@@ -834,9 +834,11 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg_in)
     d.tflag = (int *)run_alloc(c, r, sb);
     ok = ok && d.lpatch && d.spatch && d.lopatch && d.nlv && d.tflag;
     d.spec = nullptr;
+    d.spec_tw = nullptr;
     if (d.solver == PIC_SOLVER_PSATD) {
         d.spec = (double2 *)run_alloc(c, r, (size_t)SPEC_ARRAYS * r.ncell * 16);
-        ok = ok && d.spec;
+        d.spec_tw = (double2 *)run_alloc(c, r, (size_t)SPEC_TW_LEN * 16);
+        ok = ok && d.spec && d.spec_tw;
     }
     r.gauss0 = (double *)run_alloc(c, r, (size_t)r.ncell * 8);
     ok = ok && r.gauss0;
@@ -857,6 +859,7 @@ static int setup_run(pic_ctx *c, int slot, const pic_config *cfg_in)
     HIPCHK(c, hipMemsetAsync(d.nlv, 0, sb, s));
     HIPCHK(c, hipMemsetAsync(d.tflag, 0, sb, s));
     HIPCHK(c, hipMemsetAsync(d.ctl, 0, sizeof(Ctl), s));
+    if (d.spec_tw) HIPCHK(c, launch_spec_twiddles(d.spec_tw, s));
     {
         Ctl init;
         memset(&init, 0, sizeof init);

@@ -50,7 +50,29 @@
 
 namespace sdmd {
 
-constexpr int FFT_MAX = 2048;   // longest transform line
+constexpr int FFT_MAX = SPEC_TW_LEN;   // longest transform line
+
+// twiddle tables e^{-2 pi i k / N}, k < N/2, of N = 2, 4, .., FFT_MAX one
+// after the other (the table of N starts at N/2 - 1): shared by every
+// transform of the run from HBM (the L1 and L2 caches hold them), so the
+// line kernel's LDS holds the data alone
+__global__ void spec_twiddle_kernel(double2 *tw)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= FFT_MAX - 1) return;
+    int N = 2;
+    while (N - 1 <= i) N *= 2;
+    const int k = i - (N / 2 - 1);
+    double sn, cs;
+    sincospi((double)(-2 * k) / (double)N, &sn, &cs);
+    tw[i] = make_double2(cs, sn);
+}
+
+hipError_t launch_spec_twiddles(double2 *tw, hipStream_t s)
+{
+    spec_twiddle_kernel<<<(FFT_MAX + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(tw);
+    return hipGetLastError();
+}
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
@@ -72,7 +94,7 @@ __device__ __forceinline__ int src_comp(int c, int par)
 }
 
 // Radix-2 stages on `lines` lines of N values in LDS (twiddles tw[k] =
-// e^{sign 2 pi i k / N}, k < N/2).  A pass takes the 2^R values that R
+// e^{-2 pi i k / N}, k < N/2).  A pass takes the 2^R values that R
 // consecutive stages touch into registers (R = 3, then 2 or 1 for the
 // last stages), so a transform of 2^m points takes ceil(m / 3)
 // barrier-separated passes instead of m.
@@ -150,10 +172,11 @@ __device__ __forceinline__ void ifft_dif(double2 *buf, const double2 *tw, int N,
 // 1D transforms of length N = n[axis] along `axis` of components [c0, c0+nc)
 // of the packed grid arrays; sign -1 forward, +1 inverse (unscaled).  A workgroup
 // transforms NL = max(1, FFT_BATCH / N) lines held in LDS (iterative
-// radix-2, bit-reversed load, one twiddle table per workgroup).  Lines along
+// radix-2, bit-reversed load; an inverse transform conjugates its input and
+// its output).  Lines along
 // y or z are taken NL adjacent in x, so every row of the batch is a
 // contiguous read.  Grid: x = batch of lines, y = component.
-constexpr int FFT_BATCH = 2048;   // complex values per workgroup: 32 KB of LDS + the twiddles
+constexpr int FFT_BATCH = 2048;   // complex values per workgroup: 32 KB of LDS
 
 __host__ __device__ inline int fft_lines_per_group(int N, int axis, const int n[3])
 {
@@ -183,7 +206,8 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
     const long long groups = ncell / N / NL;
     const long long gidx = blockIdx.x;
     if (gidx >= groups) return;
-    double2 *buf = sm, *tw = sm + NL * N;
+    double2 *buf = sm;
+    const double2 *tw = rd.spec_tw + (N / 2 - 1);
     // first line of the group and the offset between its lines
     long long o, stride, lstep;
     if (axis == 0) {
@@ -211,11 +235,6 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
     int logn = 0;
     while ((1 << logn) < N) ++logn;
     const int tid = threadIdx.x;
-    for (int k = tid; k < N / 2; k += BLOCK) {
-        double sn, cs;
-        sincospi((double)(sign * 2 * k) / (double)N, &sn, &cs);
-        tw[k] = make_double2(cs, sn);
-    }
     const int tot = NL * N;
     for (int e = tid; e < tot; e += BLOCK) {
         int l, j;
@@ -231,11 +250,13 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
             const long long q = relem(l, j);
             buf[l * N + r] = make_double2(rcomp(rd, 0, src_comp(2 * comp, par))[q],
                                           2 * comp + 1 < 9 ? rcomp(rd, 0, src_comp(2 * comp + 1, par))[q] : 0.0);
-        } else
-            buf[l * N + r] = a[l * lstep + j * stride];
+        } else {
+            const double2 v = a[l * lstep + j * stride];
+            buf[l * N + r] = sign > 0 ? conjd(v) : v;
+        }
     }
     __syncthreads();
-    fft_dit(buf, tw, N, NL);
+    fft_dit(buf, tw, N, NL);   // the inverse as conj(forward(conj(x)))
     for (int e = tid; e < tot; e += BLOCK) {
         int l, j;
         if (axis == 0) {
@@ -247,7 +268,7 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
         }
         if constexpr (OUT_REGION) {
             const long long p = relem(l, j);
-            const double2 z = buf[l * N + j];
+            const double2 z = conjd(buf[l * N + j]);   // written by an inverse transform only
             const double v[2] = {z.x / (double)ncell, z.y / (double)ncell};
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -260,7 +281,8 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
                 }
             }
         } else {
-            a[l * lstep + j * stride] = buf[l * N + j];
+            const double2 v = buf[l * N + j];
+            a[l * lstep + j * stride] = sign > 0 ? conjd(v) : v;
         }
     }
 }
@@ -429,9 +451,9 @@ __device__ __forceinline__ bool line_pair(long long g, int dims, int n0, int n1,
     return false;
 }
 
-__global__ __launch_bounds__(BLOCK) void spec_line_kernel(const RunDev *__restrict__ runs, int run, int par)
+__global__ __launch_bounds__(BLOCK, 4) void spec_line_kernel(const RunDev *__restrict__ runs, int run, int par)
 {
-    __shared__ double2 sm[2 * SPEC_ARRAYS * SPEC_LINE_MAX + SPEC_LINE_MAX / 2];
+    __shared__ double2 buf[2 * SPEC_ARRAYS * SPEC_LINE_MAX];
     const RunDev &rd = runs[run];
     if (rd.ctl->remaining[par] == 0) return;
     const int dims = rd.dims, ax = dims - 1;
@@ -446,15 +468,10 @@ __global__ __launch_bounds__(BLOCK) void spec_line_kernel(const RunDev *__restri
     const bool selfpair = line_pair(grp, dims, n0, n1, L);
     const long long stride = nlines;   // the last axis is the slowest: its lines are every nlines-th element
     // layout: array-major, then line, then node: the 3 E/B arrays first
-    double2 *buf = sm, *tw = sm + 2 * SPEC_ARRAYS * N;
+    const double2 *tw = rd.spec_tw + (N / 2 - 1);   // forward twiddles; the inverse uses their conjugates
     int logn = 0;
     while ((1 << logn) < N) ++logn;
     const int tid = threadIdx.x;
-    for (int k = tid; k < N / 2; k += BLOCK) {
-        double sn, cs;
-        sincospi((double)(-2 * k) / (double)N, &sn, &cs);
-        tw[k] = make_double2(cs, sn);   // forward twiddles e^{-2 pi i k / N}; the inverse uses their conjugates
-    }
     for (int e = tid; e < 2 * SPEC_ARRAYS * N; e += BLOCK) {
         const int l = e & 1, j = (e >> 1) % N, p = e / (2 * N);
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
@@ -487,7 +504,7 @@ hipError_t launch_spectral(const RunDev *runs, int run, int dims, const int n[3]
     const int last = dims - 1;
     auto fft = [&](auto kern, int a, int ncomp, int sign) {
         const int nl = fft_lines_per_group(n[a], a, n);
-        const size_t lds = ((size_t)nl * n[a] + n[a] / 2) * sizeof(double2);
+        const size_t lds = (size_t)nl * n[a] * sizeof(double2);
         kern<<<dim3((unsigned)(ncell / n[a] / nl), ncomp), BLOCK, lds, s>>>(runs, run, par, a, 0, sign);
     };
     // forward along x, reading the region's fields; then the middle axis (3D)

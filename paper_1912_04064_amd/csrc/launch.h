@@ -25,6 +25,8 @@ hipError_t launch_yee(int dims, bool split, int tx, bool filt, bool det, const R
 // step, inverse transforms, unpack into the other E/B buffer (the field
 // kernel has already written J)
 hipError_t launch_spectral(const RunDev *runs, int run, int dims, const int n[3], int par, hipStream_t s);
+// the spectral solver's twiddle tables (RunDev::spec_tw), once at set-up
+hipError_t launch_spec_twiddles(double2 *tw, hipStream_t s);
 
 // ghost synchronisation of the new fields + insertion of the leavers:
 // items (run, kind, a, b); kind 0 ghost chunk starting at a, kind 1 insert

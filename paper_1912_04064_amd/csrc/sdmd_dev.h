@@ -45,6 +45,7 @@ __host__ __device__ inline int f_B(int par) { return F_B0 + 3 * par; }
 
 constexpr int BLOCK = 256;     // threads per workgroup of the step kernels
 constexpr int SPEC_ARRAYS = 5;   // spectral solver: the 9 real E, B, J components, two per complex array
+constexpr int SPEC_TW_LEN = 2048;   // spectral solver: longest transform, and entries of the twiddle tables
 
 // A re-layout moves each patch's particles in chunks of MOVE_CHUNK, one
 // workgroup per chunk; at most n_patch + ceil(N / MOVE_CHUNK) chunks exist.
@@ -146,6 +147,7 @@ struct RunDev {
     int *nlv;            // [seg_max] leavers of each segment this step, in lv at sseg[s]
     int *tflag;          // [seg_max] 1 when the segment's tile in HBM may hold non-zero values
     double2 *spec;       // spectral solver: SPEC_ARRAYS complex arrays [z][y][x] of the grid (components packed in pairs)
+    double2 *spec_tw;    // spectral solver: e^{-2 pi i k / N}, k < N/2, for every N = 2..SPEC_TW_LEN, the table of N from N/2 - 1
     Store lo;            // overflow leavers (parked particles re-entering)
     int *lopatch;
     Ctl *ctl;

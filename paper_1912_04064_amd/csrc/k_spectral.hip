@@ -103,30 +103,33 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
 
 // One pass of R stages whose first (DIT) or last (DIF) stage has half-length
-// h: the values at b + k h, k < 2^R, b = block * 2^R h + pos, pos < h.  DIT
-// stage s pairs k and k + 2^s (bit s of k clear) with the twiddle of the
-// pair's offset pos + (k mod 2^s) h in its block of 2^{s+1} h; DIF runs the
-// stages in the opposite order with (u + v, (u - v) conj(w)).
+// h = 2^logh, on lines of N = 2^logn values: the values at b + k h, k <
+// 2^R, b = block * 2^R h + pos, pos < h.  DIT stage s pairs k and k + 2^s
+// (bit s of k clear) with the twiddle of the pair's offset pos + (k mod
+// 2^s) h in its block of 2^{s+1} h; DIF runs the stages in the opposite
+// order with (u + v, (u - v) conj(w)).  All sizes are powers of two, so the
+// index arithmetic is shifts and masks.
 template <int R, bool DIF>
-__device__ __forceinline__ void fft_pass(double2 *buf, const double2 *tw, int N, int lines, int h)
+__device__ __forceinline__ void fft_pass(double2 *buf, const double2 *tw, int logn, int lines, int logh)
 {
     constexpr int K = 1 << R;
-    const int groups = N / K;
-    for (int t = threadIdx.x; t < lines * groups; t += BLOCK) {
-        const int c = t / groups, q = t - c * groups, blk = q / h, pos = q - blk * h;
-        const int b = c * N + blk * K * h + pos;
+    const int lg = logn - R;   // log2 of the groups of a line
+    const int h = 1 << logh;
+    for (int t = threadIdx.x; t < (lines << lg); t += BLOCK) {
+        const int c = t >> lg, q = t & ((1 << lg) - 1), blk = q >> logh, pos = q & (h - 1);
+        const int b = (c << logn) + (blk << (R + logh)) + pos;
         double2 v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = buf[b + k * h];
 #pragma unroll
         for (int ss = 0; ss < R; ++ss) {
             const int s = DIF ? R - 1 - ss : ss;
-            const int half = h << s, st = N / (2 * half);
+            const int sh = logn - 1 - logh - s;   // the table step N / 2^{s+1} h
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 if (k & (1 << s)) continue;
                 const int k2 = k + (1 << s);
-                const double2 w = tw[(pos + (k & ((1 << s) - 1)) * h) * st];
+                const double2 w = tw[(pos + ((k & ((1 << s) - 1)) << logh)) << sh];
                 if constexpr (DIF) {
                     const double2 u = v[k], x = v[k2];
                     v[k] = cadd(u, x);
@@ -145,28 +148,28 @@ __device__ __forceinline__ void fft_pass(double2 *buf, const double2 *tw, int N,
 }
 
 // decimation in time, bit-reversed input -> natural output
-__device__ __forceinline__ void fft_dit(double2 *buf, const double2 *tw, int N, int lines)
+__device__ __forceinline__ void fft_dit(double2 *buf, const double2 *tw, int logn, int lines)
 {
-    int h = 1;   // half-length of the first stage of the next pass
-    for (; 8 * h <= N; h *= 8) fft_pass<3, false>(buf, tw, N, lines, h);
-    if (4 * h <= N) {
-        fft_pass<2, false>(buf, tw, N, lines, h);
-        h *= 4;
+    int logh = 0;   // half-length of the first stage of the next pass
+    for (; logh + 3 <= logn; logh += 3) fft_pass<3, false>(buf, tw, logn, lines, logh);
+    if (logh + 2 <= logn) {
+        fft_pass<2, false>(buf, tw, logn, lines, logh);
+        logh += 2;
     }
-    if (2 * h <= N) fft_pass<1, false>(buf, tw, N, lines, h);
+    if (logh + 1 <= logn) fft_pass<1, false>(buf, tw, logn, lines, logh);
 }
 
 // decimation in frequency with the conjugate twiddles (the inverse of the
 // forward table), natural input -> bit-reversed output
-__device__ __forceinline__ void ifft_dif(double2 *buf, const double2 *tw, int N, int lines)
+__device__ __forceinline__ void ifft_dif(double2 *buf, const double2 *tw, int logn, int lines)
 {
-    int len = N;   // block length of the first stage of the next pass
-    for (; len >= 8; len /= 8) fft_pass<3, true>(buf, tw, N, lines, len / 8);
-    if (len >= 4) {
-        fft_pass<2, true>(buf, tw, N, lines, len / 4);
-        len /= 4;
+    int loglen = logn;   // block length of the first stage of the next pass
+    for (; loglen >= 3; loglen -= 3) fft_pass<3, true>(buf, tw, logn, lines, loglen - 3);
+    if (loglen >= 2) {
+        fft_pass<2, true>(buf, tw, logn, lines, loglen - 2);
+        loglen -= 2;
     }
-    if (len >= 2) fft_pass<1, true>(buf, tw, N, lines, len / 2);
+    if (loglen >= 1) fft_pass<1, true>(buf, tw, logn, lines, loglen - 1);
 }
 
 // 1D transforms of length N = n[axis] along `axis` of components [c0, c0+nc)
@@ -208,15 +211,18 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
     if (gidx >= groups) return;
     double2 *buf = sm;
     const double2 *tw = rd.spec_tw + (N / 2 - 1);
+    // the grid sizes are powers of two: index arithmetic in shifts and masks
+    const int logn = __builtin_ctz(N), lognl = __builtin_ctz(NL), logn0 = __builtin_ctz(n0),
+              logn1 = __builtin_ctz(n1);
     // first line of the group and the offset between its lines
     long long o, stride, lstep;
     if (axis == 0) {
-        o = gidx * NL * (long long)n0;
+        o = (gidx * NL) << logn0;
         stride = 1;
         lstep = n0;
     } else if (axis == 1) {
         const long long first = gidx * NL;                      // lines enumerate (x, z), x fastest
-        o = (first % n0) + (first / n0) * (long long)n0 * n1;
+        o = (first & (n0 - 1)) + ((first >> logn0) << (logn0 + logn1));
         stride = n0;
         lstep = 1;
     } else {
@@ -228,48 +234,45 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
     double2 *a = rd.spec + (long long)comp * ncell + o;
     // element j of x line l of the batch -> region element (the region's
     // interior is the grid; the region reads and writes are along x only)
+    const long long line0 = gidx * NL;
     auto relem = [&](int l, int j) {
-        const long long line = o / n0 + l;
-        return rindex(rd, 0, (int)(line % n1), (int)(line / n1)) + j;
+        const long long line = line0 + l;
+        return rindex(rd, 0, (int)(line & (n1 - 1)), (int)(line >> logn1)) + j;
     };
-    int logn = 0;
-    while ((1 << logn) < N) ++logn;
+    auto place = [&](int e, int &l, int &j) {
+        if (axis == 0) {
+            j = e & (N - 1);
+            l = e >> logn;
+        } else {
+            l = e & (NL - 1);
+            j = e >> lognl;
+        }
+    };
     const int tid = threadIdx.x;
     const int tot = NL * N;
     for (int e = tid; e < tot; e += BLOCK) {
         int l, j;
-        if (axis == 0) {
-            j = e % N;
-            l = e / N;
-        } else {
-            l = e % NL;
-            j = e / NL;
-        }
+        place(e, l, j);
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
         if constexpr (IN_REGION) {
             const long long q = relem(l, j);
-            buf[l * N + r] = make_double2(rcomp(rd, 0, src_comp(2 * comp, par))[q],
-                                          2 * comp + 1 < 9 ? rcomp(rd, 0, src_comp(2 * comp + 1, par))[q] : 0.0);
+            buf[(l << logn) + r] = make_double2(rcomp(rd, 0, src_comp(2 * comp, par))[q],
+                                                2 * comp + 1 < 9 ? rcomp(rd, 0, src_comp(2 * comp + 1, par))[q] : 0.0);
         } else {
             const double2 v = a[l * lstep + j * stride];
-            buf[l * N + r] = sign > 0 ? conjd(v) : v;
+            buf[(l << logn) + r] = sign > 0 ? conjd(v) : v;
         }
     }
     __syncthreads();
-    fft_dit(buf, tw, N, NL);   // the inverse as conj(forward(conj(x)))
+    fft_dit(buf, tw, logn, NL);   // the inverse as conj(forward(conj(x)))
+    const double scale = 1.0 / (double)ncell;   // a power of two: exact
     for (int e = tid; e < tot; e += BLOCK) {
         int l, j;
-        if (axis == 0) {
-            j = e % N;
-            l = e / N;
-        } else {
-            l = e % NL;
-            j = e / NL;
-        }
+        place(e, l, j);
         if constexpr (OUT_REGION) {
             const long long p = relem(l, j);
-            const double2 z = conjd(buf[l * N + j]);   // written by an inverse transform only
-            const double v[2] = {z.x / (double)ncell, z.y / (double)ncell};
+            const double2 z = conjd(buf[(l << logn) + j]);   // written by an inverse transform only
+            const double v[2] = {z.x * scale, z.y * scale};
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int c = 2 * comp + h;
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
                 }
             }
         } else {
-            const double2 v = buf[l * N + j];
+            const double2 v = buf[(l << logn) + j];
             a[l * lstep + j * stride] = sign > 0 ? conjd(v) : v;
         }
     }
@@ -326,10 +329,11 @@ __device__ __forceinline__ void kspace_step(const RunDev &rd, const int idx[3], 
             Bn[c] = F[3 + c];
         }
     } else {
-        const double kap[3] = {kt[0] / w, kt[1] / w, kt[2] / w};
+        const double iw = 1.0 / w;
+        const double kap[3] = {kt[0] * iw, kt[1] * iw, kt[2] * iw};
         double S, C;
         sincos(w * dt, &S, &C);
-        const double Sw = S / w, C1w = (1.0 - C) / w;
+        const double Sw = S * iw, C1w = (1.0 - C) * iw;
         double2 kE = make_double2(0, 0), kJ = make_double2(0, 0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -401,8 +405,8 @@ __global__ __launch_bounds__(BLOCK) void spec_kspace_kernel(const RunDev *__rest
     const long long ncell = (long long)rd.n[0] * rd.n[1] * rd.n[2];
     const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
     if (gid >= ncell) return;
-    const int idx[3] = {(int)(gid % rd.n[0]), (int)((gid / rd.n[0]) % rd.n[1]),
-                        (int)(gid / ((long long)rd.n[0] * rd.n[1]))};
+    const int l0 = __builtin_ctz(rd.n[0]), l1 = __builtin_ctz(rd.n[1]);   // powers of two
+    const int idx[3] = {(int)(gid & (rd.n[0] - 1)), (int)((gid >> l0) & (rd.n[1] - 1)), (int)(gid >> (l0 + l1))};
     int idxm[3];
     mirror_index(rd, idx, idxm);
     const long long gm = idxm[0] + (long long)rd.n[0] * (idxm[1] + (long long)rd.n[1] * idxm[2]);
@@ -469,16 +473,15 @@ __global__ __launch_bounds__(BLOCK, 4) void spec_line_kernel(const RunDev *__res
     const long long stride = nlines;   // the last axis is the slowest: its lines are every nlines-th element
     // layout: array-major, then line, then node: the 3 E/B arrays first
     const double2 *tw = rd.spec_tw + (N / 2 - 1);   // forward twiddles; the inverse uses their conjugates
-    int logn = 0;
-    while ((1 << logn) < N) ++logn;
+    const int logn = __builtin_ctz(N), logn0 = __builtin_ctz(n0);   // powers of two
     const int tid = threadIdx.x;
     for (int e = tid; e < 2 * SPEC_ARRAYS * N; e += BLOCK) {
-        const int l = e & 1, j = (e >> 1) % N, p = e / (2 * N);
+        const int l = e & 1, j = (e >> 1) & (N - 1), p = e >> (logn + 1);
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
         buf[(2 * p + l) * N + r] = rd.spec[p * ncell + L[l] + j * stride];
     }
     __syncthreads();
-    fft_dit(buf, tw, N, 2 * SPEC_ARRAYS);   // forward, bit-reversed input
+    fft_dit(buf, tw, logn, 2 * SPEC_ARRAYS);   // forward, bit-reversed input
     // the paired steps: (line 0, j) with (line 1, -j), or within each
     // self-mirror line j with -j for j <= N/2
     const int half = N / 2 + 1, ntask = selfpair ? 2 * half : N;
@@ -486,13 +489,13 @@ __global__ __launch_bounds__(BLOCK, 4) void spec_line_kernel(const RunDev *__res
         const int l = selfpair ? t / half : 0, j = selfpair ? t - l * half : t;
         const int lm = selfpair ? l : 1, jm = (N - j) & (N - 1);
         const long long ln = L[l];
-        const int idx[3] = {(int)(ln % n0), dims == 3 ? (int)(ln / n0) : j, dims == 3 ? j : 0};
+        const int idx[3] = {(int)(ln & (n0 - 1)), dims == 3 ? (int)(ln >> logn0) : j, dims == 3 ? j : 0};
         spec_pair_step(rd, buf + l * N + j, buf + lm * N + jm, 2 * N, idx);
     }
     __syncthreads();
-    ifft_dif(buf, tw, N, 2 * 3);   // inverse of the E/B arrays, bit-reversed output
+    ifft_dif(buf, tw, logn, 2 * 3);   // inverse of the E/B arrays, bit-reversed output
     for (int e = tid; e < 2 * 3 * N; e += BLOCK) {
-        const int l = e & 1, j = (e >> 1) % N, p = e / (2 * N);
+        const int l = e & 1, j = (e >> 1) & (N - 1), p = e >> (logn + 1);
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
         rd.spec[p * ncell + L[l] + j * stride] = buf[(2 * p + l) * N + r];
     }

@@ -77,7 +77,7 @@ def test_spectral_vacuum_wave_exact_on_gpu(dims, m, e_dir):
     assert err < 1e-11
 
 
-@pytest.mark.parametrize("dims,n", [(2, (32, 16)), (3, (8, 16, 8)), (2, (16, 512))])
+@pytest.mark.parametrize("dims,n", [(2, (32, 16)), (3, (8, 16, 8)), (2, (16, 512)), (3, (4, 8, 512))])
 def test_spectral_white_noise_fields_match_oracle(dims, n):
     """Random E, B (no particles) carry every wavevector at full amplitude,
     the Nyquist planes of each axis included.  The oracle steps every
@@ -85,7 +85,7 @@ def test_spectral_white_noise_fields_match_oracle(dims, n):
     the inverse; the GPU transforms the real components two to a complex
     array, steps k and obtains -k by conjugation, so this checks the
     splitting, the repacking and the symmetry of the step everywhere.  The
-    512-node last axis takes the separate k-space launch."""
+    512-node last axes take the separate k-space launch."""
     say(f"case: spectral white noise dims={dims} n={n}")
     d = (0.1, 0.15, 0.12)[:dims]
     dt = 0.9 * min(d)

@@ -109,13 +109,13 @@ __device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -
 // 2^s) h in its block of 2^{s+1} h; DIF runs the stages in the opposite
 // order with (u + v, (u - v) conj(w)).  All sizes are powers of two, so the
 // index arithmetic is shifts and masks.
-template <int R, bool DIF>
+template <int R, bool DIF, int NTH = BLOCK>
 __device__ __forceinline__ void fft_pass(double2 *buf, const double2 *tw, int logn, int lines, int logh)
 {
     constexpr int K = 1 << R;
     const int lg = logn - R;   // log2 of the groups of a line
     const int h = 1 << logh;
-    for (int t = threadIdx.x; t < (lines << lg); t += BLOCK) {
+    for (int t = threadIdx.x; t < (lines << lg); t += NTH) {
         const int c = t >> lg, q = t & ((1 << lg) - 1), blk = q >> logh, pos = q & (h - 1);
         const int b = (c << logn) + (blk << (R + logh)) + pos;
         double2 v[K];
@@ -148,28 +148,30 @@ __device__ __forceinline__ void fft_pass(double2 *buf, const double2 *tw, int lo
 }
 
 // decimation in time, bit-reversed input -> natural output
+template <int NTH = BLOCK>
 __device__ __forceinline__ void fft_dit(double2 *buf, const double2 *tw, int logn, int lines)
 {
     int logh = 0;   // half-length of the first stage of the next pass
-    for (; logh + 3 <= logn; logh += 3) fft_pass<3, false>(buf, tw, logn, lines, logh);
+    for (; logh + 3 <= logn; logh += 3) fft_pass<3, false, NTH>(buf, tw, logn, lines, logh);
     if (logh + 2 <= logn) {
-        fft_pass<2, false>(buf, tw, logn, lines, logh);
+        fft_pass<2, false, NTH>(buf, tw, logn, lines, logh);
         logh += 2;
     }
-    if (logh + 1 <= logn) fft_pass<1, false>(buf, tw, logn, lines, logh);
+    if (logh + 1 <= logn) fft_pass<1, false, NTH>(buf, tw, logn, lines, logh);
 }
 
 // decimation in frequency with the conjugate twiddles (the inverse of the
 // forward table), natural input -> bit-reversed output
+template <int NTH = BLOCK>
 __device__ __forceinline__ void ifft_dif(double2 *buf, const double2 *tw, int logn, int lines)
 {
     int loglen = logn;   // block length of the first stage of the next pass
-    for (; loglen >= 3; loglen -= 3) fft_pass<3, true>(buf, tw, logn, lines, loglen - 3);
+    for (; loglen >= 3; loglen -= 3) fft_pass<3, true, NTH>(buf, tw, logn, lines, loglen - 3);
     if (loglen >= 2) {
-        fft_pass<2, true>(buf, tw, logn, lines, loglen - 2);
+        fft_pass<2, true, NTH>(buf, tw, logn, lines, loglen - 2);
         loglen -= 2;
     }
-    if (loglen >= 1) fft_pass<1, true>(buf, tw, logn, lines, loglen - 1);
+    if (loglen >= 1) fft_pass<1, true, NTH>(buf, tw, logn, lines, loglen - 1);
 }
 
 // 1D transforms of length N = n[axis] along `axis` of components [c0, c0+nc)
@@ -414,90 +416,122 @@ __global__ __launch_bounds__(BLOCK) void spec_kspace_kernel(const RunDev *__rest
     spec_pair_step(rd, rd.spec + gid, rd.spec + gm, ncell, idx);
 }
 
-// Two lines along the last axis in LDS, all 5 packed arrays: a line and its
-// mirror line, or two lines that are their own mirrors (x and, in 3D, y
-// each 0 or n/2).  Forward transform (bit-reversed load, decimation in
-// time), the paired step of each wavevector, inverse transform of the 3
-// E/B arrays (decimation in frequency: natural order in, bit-reversed order
-// out, read back bit-reversed on the store).  The line pairs are dealt to
-// the XCDs in contiguous bands (workgroup l runs on XCD l % 8), so pairs
-// that share the grid's cache lines run on one XCD.
+// Four lines along the last axis in LDS, all 5 packed arrays, as two
+// units of a line and its mirror line (or of two lines that are their own
+// mirrors: x and, in 3D, y each 0 or n/2).  Forward transform (bit-reversed
+// load, decimation in time), the paired step of each wavevector, inverse
+// transform of the 3 E/B arrays (decimation in frequency: natural order in,
+// bit-reversed order out, read back bit-reversed on the store).  Most
+// workgroups take the lines x, x + 1 of a row and their mirrors -x - 1, -x
+// of the mirror row, so every grid row is read as two contiguous pairs of
+// values.  The workgroups are dealt to the XCDs in contiguous bands
+// (workgroup l runs on XCD l % 8), so those that share the grid's cache
+// lines run on one XCD.
 constexpr int SPEC_LINE_MAX = 256;   // nodes of the last axis the line kernel takes
+constexpr int SPEC_LINE_THREADS = 2 * BLOCK;
 
-// line pair g of the plane across the last axis (lines x + n0 y; 2D: y = 0,
-// n1 = 1): pairs (x, y) with (-x, -y) for 0 < x < n0/2; the columns x = 0
-// and x = n0/2 pair (x, y) with (x, -y) for 0 < y < n1/2, and their four
-// self-mirror lines y = 0, n1/2 go two to a group.  Returns whether the two
-// lines are each their own mirror.
-__device__ __forceinline__ bool line_pair(long long g, int dims, int n0, int n1, long long L[2])
+// the self-mirror or mirror unit of the columns x = 0, n0/2 in row y (lines
+// x + n0 y; 2D: n1 = 1, y = 0): rows 0 and n1/2 pair the lines of the two
+// columns that are their own mirrors; row y < n1/2 pairs (0, y) with (0, -y),
+// row y > n1/2 pairs (n0/2, y - n1/2) with its mirror
+__device__ __forceinline__ bool column_unit(int y, int dims, int n0, int n1, int &a, int &b)
 {
-    const int hx = n0 / 2;
+    const int hx = n0 / 2, hy = n1 / 2;
     if (dims == 2) {
-        L[0] = g == 0 ? 0 : g;
-        L[1] = g == 0 ? hx : n0 - g;
-        return g == 0;
-    }
-    const int gx = (int)(g % hx), y = (int)(g / hx), hy = n1 / 2;
-    if (gx > 0) {
-        L[0] = gx + (long long)n0 * y;
-        L[1] = (n0 - gx) + (long long)n0 * ((n1 - y) & (n1 - 1));
-        return false;
+        a = 0;
+        b = hx;
+        return true;
     }
     if (y == 0 || y == hy) {
         const int x = y == 0 ? 0 : hx;
-        L[0] = x;
-        L[1] = x + (long long)n0 * hy;
+        a = x;
+        b = x + n0 * hy;
         return true;
     }
     const int x = y < hy ? 0 : hx, yy = y < hy ? y : y - hy;
-    L[0] = x + (long long)n0 * yy;
-    L[1] = x + (long long)n0 * (n1 - yy);
+    a = x + n0 * yy;
+    b = x + n0 * (n1 - yy);
     return false;
 }
 
-__global__ __launch_bounds__(BLOCK, 4) void spec_line_kernel(const RunDev *__restrict__ runs, int run, int par)
+// line group g: lines L[0..3] and, per unit, its two buffer lines and
+// whether they are their own mirrors.  With A = n0/4 - 1 groups of adjacent
+// pairs per row: group y A + i takes (x, y), (x + 1, y), (-x - 1, -y),
+// (-x, -y) for x = 2i + 1 (units: lines 0 and 3, 1 and 2); the last n1
+// groups take row y's line (n0/2 - 1, y) with its mirror and the column
+// unit of row y (units: lines 0 and 1, 2 and 3).
+__device__ __forceinline__ void line_group(int g, int dims, int n0, int n1, int L[4], int ul[2][2], bool self[2])
 {
-    __shared__ double2 buf[2 * SPEC_ARRAYS * SPEC_LINE_MAX];
+    const int rows = dims == 3 ? n1 : 1, A = n0 / 4 - 1;
+    if (g < A * rows) {
+        const int y = g / A, x = 2 * (g % A) + 1, my = (n1 - y) & (n1 - 1);
+        L[0] = x + n0 * y;
+        L[1] = L[0] + 1;
+        L[2] = (n0 - x - 1) + n0 * my;
+        L[3] = L[2] + 1;
+        ul[0][0] = 0; ul[0][1] = 3;
+        ul[1][0] = 1; ul[1][1] = 2;
+        self[0] = self[1] = false;
+        return;
+    }
+    const int y = g - A * rows, my = (n1 - y) & (n1 - 1);
+    L[0] = (n0 / 2 - 1) + n0 * y;
+    L[1] = (n0 / 2 + 1) + n0 * my;
+    self[0] = false;
+    self[1] = column_unit(y, dims, n0, n1, L[2], L[3]);
+    ul[0][0] = 0; ul[0][1] = 1;
+    ul[1][0] = 2; ul[1][1] = 3;
+}
+
+__global__ __launch_bounds__(SPEC_LINE_THREADS, 4) void spec_line_kernel(const RunDev *__restrict__ runs, int run,
+                                                                      int par)
+{
+    constexpr int NTH = SPEC_LINE_THREADS;
+    __shared__ double2 buf[4 * SPEC_ARRAYS * SPEC_LINE_MAX];
     const RunDev &rd = runs[run];
     if (rd.ctl->remaining[par] == 0) return;
     const int dims = rd.dims, ax = dims - 1;
     const int n0 = rd.n[0], n1 = rd.n[1];
     const long long ncell = (long long)n0 * n1 * rd.n[2];
     const int N = rd.n[ax];
-    const long long nlines = ncell / N, ngroups = nlines / 2;
+    const long long nlines = ncell / N, ngroups = nlines / 4;
     const long long band = (ngroups + 7) / 8;
     const long long grp = (long long)(blockIdx.x & 7) * band + (blockIdx.x >> 3);
     if ((blockIdx.x >> 3) >= band || grp >= ngroups) return;
-    long long L[2];
-    const bool selfpair = line_pair(grp, dims, n0, n1, L);
+    int L[4], ul[2][2];   // lines of the plane: at most 2048 x 2048
+    bool self[2];
+    line_group((int)grp, dims, n0, n1, L, ul, self);
     const long long stride = nlines;   // the last axis is the slowest: its lines are every nlines-th element
     // layout: array-major, then line, then node: the 3 E/B arrays first
     const double2 *tw = rd.spec_tw + (N / 2 - 1);   // forward twiddles; the inverse uses their conjugates
     const int logn = __builtin_ctz(N), logn0 = __builtin_ctz(n0);   // powers of two
     const int tid = threadIdx.x;
-    for (int e = tid; e < 2 * SPEC_ARRAYS * N; e += BLOCK) {
-        const int l = e & 1, j = (e >> 1) & (N - 1), p = e >> (logn + 1);
+    for (int e = tid; e < 4 * SPEC_ARRAYS * N; e += NTH) {
+        const int l = e & 3, j = (e >> 2) & (N - 1), p = e >> (logn + 2);
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
-        buf[(2 * p + l) * N + r] = rd.spec[p * ncell + L[l] + j * stride];
+        buf[(4 * p + l) * N + r] = rd.spec[p * ncell + L[l] + j * stride];
     }
     __syncthreads();
-    fft_dit(buf, tw, logn, 2 * SPEC_ARRAYS);   // forward, bit-reversed input
-    // the paired steps: (line 0, j) with (line 1, -j), or within each
-    // self-mirror line j with -j for j <= N/2
-    const int half = N / 2 + 1, ntask = selfpair ? 2 * half : N;
-    for (int t = tid; t < ntask; t += BLOCK) {
-        const int l = selfpair ? t / half : 0, j = selfpair ? t - l * half : t;
-        const int lm = selfpair ? l : 1, jm = (N - j) & (N - 1);
-        const long long ln = L[l];
-        const int idx[3] = {(int)(ln & (n0 - 1)), dims == 3 ? (int)(ln >> logn0) : j, dims == 3 ? j : 0};
-        spec_pair_step(rd, buf + l * N + j, buf + lm * N + jm, 2 * N, idx);
+    fft_dit<NTH>(buf, tw, logn, 4 * SPEC_ARRAYS);   // forward, bit-reversed input
+    // the paired steps, unit by unit: (line a, j) with (line b, -j), or
+    // within each self-mirror line j with -j for j <= N/2
+    const int half = N / 2 + 1;
+    const int nt0 = self[0] ? 2 * half : N, ntask = nt0 + (self[1] ? 2 * half : N);
+    for (int t = tid; t < ntask; t += NTH) {
+        const int u = t < nt0 ? 0 : 1, tu = t - (u ? nt0 : 0);
+        const int w = self[u] ? tu / half : 0;   // which line of a self unit
+        const int l = ul[u][w], j = self[u] ? tu - w * half : tu;
+        const int lm = self[u] ? l : ul[u][1], jm = (N - j) & (N - 1);
+        const int ln = L[l];
+        const int idx[3] = {ln & (n0 - 1), dims == 3 ? ln >> logn0 : j, dims == 3 ? j : 0};
+        spec_pair_step(rd, buf + l * N + j, buf + lm * N + jm, 4 * N, idx);
     }
     __syncthreads();
-    ifft_dif(buf, tw, logn, 2 * 3);   // inverse of the E/B arrays, bit-reversed output
-    for (int e = tid; e < 2 * 3 * N; e += BLOCK) {
-        const int l = e & 1, j = (e >> 1) & (N - 1), p = e >> (logn + 1);
+    ifft_dif<NTH>(buf, tw, logn, 4 * 3);   // inverse of the E/B arrays, bit-reversed output
+    for (int e = tid; e < 4 * 3 * N; e += NTH) {
+        const int l = e & 3, j = (e >> 2) & (N - 1), p = e >> (logn + 2);
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
-        rd.spec[p * ncell + L[l] + j * stride] = buf[(2 * p + l) * N + r];
+        rd.spec[p * ncell + L[l] + j * stride] = buf[(4 * p + l) * N + r];
     }
 }
 
@@ -514,11 +548,10 @@ hipError_t launch_spectral(const RunDev *runs, int run, int dims, const int n[3]
     fft(spec_fft_kernel<true, false>, 0, SPEC_ARRAYS, -1);
     for (int a = 1; a < last; ++a) fft(spec_fft_kernel<false, false>, a, SPEC_ARRAYS, -1);
     if (n[last] <= SPEC_LINE_MAX) {
-        // a pair of lines per workgroup (the plane across the last axis has
-        // an even number of lines: n[0] is a power of two of at least one
-        // patch of 4 cells)
-        const long long ngroups = ncell / n[last] / 2;
-        spec_line_kernel<<<(unsigned)(8 * ((ngroups + 7) / 8)), BLOCK, 0, s>>>(runs, run, par);
+        // four lines per workgroup (n[0], and n[1] in 3D, are powers of two
+        // of at least one patch of 4 cells)
+        const long long ngroups = ncell / n[last] / 4;
+        spec_line_kernel<<<(unsigned)(8 * ((ngroups + 7) / 8)), SPEC_LINE_THREADS, 0, s>>>(runs, run, par);
     } else {
         fft(spec_fft_kernel<false, false>, last, SPEC_ARRAYS, -1);
         spec_kspace_kernel<<<(unsigned)((ncell + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(runs, run, par);

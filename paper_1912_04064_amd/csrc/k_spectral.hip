@@ -182,6 +182,7 @@ __device__ __forceinline__ void ifft_dif(double2 *buf, const double2 *tw, int lo
 // y or z are taken NL adjacent in x, so every row of the batch is a
 // contiguous read.  Grid: x = batch of lines, y = component.
 constexpr int FFT_BATCH = 2048;   // complex values per workgroup: 32 KB of LDS
+constexpr int SPEC_FFT_THREADS = 2 * BLOCK;   // four of these workgroups share a CU's LDS: 32 wavefronts
 
 __host__ __device__ inline int fft_lines_per_group(int N, int axis, const int n[3])
 {
@@ -197,7 +198,7 @@ __host__ __device__ inline int fft_lines_per_group(int N, int axis, const int n[
 // are written to components 2c and 2c + 1 of the region's E^{n+1}, B^{n+1}
 // and Bm (the last inverse transform).
 template <bool IN_REGION, bool OUT_REGION>
-__global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restrict__ runs, int run, int par, int axis,
+__global__ __launch_bounds__(SPEC_FFT_THREADS) void spec_fft_kernel(const RunDev *__restrict__ runs, int run, int par, int axis,
                                                          int c0, int sign)
 {
     extern __shared__ double2 sm[];
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
     };
     const int tid = threadIdx.x;
     const int tot = NL * N;
-    for (int e = tid; e < tot; e += BLOCK) {
+    for (int e = tid; e < tot; e += SPEC_FFT_THREADS) {
         int l, j;
         place(e, l, j);
         const int r = logn ? (int)(__brev((unsigned)j) >> (32 - logn)) : 0;
@@ -266,9 +267,9 @@ __global__ __launch_bounds__(BLOCK) void spec_fft_kernel(const RunDev *__restric
         }
     }
     __syncthreads();
-    fft_dit(buf, tw, logn, NL);   // the inverse as conj(forward(conj(x)))
+    fft_dit<SPEC_FFT_THREADS>(buf, tw, logn, NL);   // the inverse as conj(forward(conj(x)))
     const double scale = 1.0 / (double)ncell;   // a power of two: exact
-    for (int e = tid; e < tot; e += BLOCK) {
+    for (int e = tid; e < tot; e += SPEC_FFT_THREADS) {
         int l, j;
         place(e, l, j);
         if constexpr (OUT_REGION) {
@@ -542,7 +543,7 @@ hipError_t launch_spectral(const RunDev *runs, int run, int dims, const int n[3]
     auto fft = [&](auto kern, int a, int ncomp, int sign) {
         const int nl = fft_lines_per_group(n[a], a, n);
         const size_t lds = (size_t)nl * n[a] * sizeof(double2);
-        kern<<<dim3((unsigned)(ncell / n[a] / nl), ncomp), BLOCK, lds, s>>>(runs, run, par, a, 0, sign);
+        kern<<<dim3((unsigned)(ncell / n[a] / nl), ncomp), SPEC_FFT_THREADS, lds, s>>>(runs, run, par, a, 0, sign);
     };
     // forward along x, reading the region's fields; then the middle axis (3D)
     fft(spec_fft_kernel<true, false>, 0, SPEC_ARRAYS, -1);

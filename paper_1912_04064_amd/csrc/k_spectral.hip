@@ -182,7 +182,7 @@ __device__ __forceinline__ void ifft_dif(double2 *buf, const double2 *tw, int lo
 // y or z are taken NL adjacent in x, so every row of the batch is a
 // contiguous read.  Grid: x = batch of lines, y = component.
 constexpr int FFT_BATCH = 2048;   // complex values per workgroup: 32 KB of LDS
-constexpr int SPEC_FFT_THREADS = 2 * BLOCK;   // four of these workgroups share a CU's LDS: 32 wavefronts
+constexpr int SPEC_FFT_THREADS = 2 * BLOCK;   // three workgroups per CU (24 wavefronts; 20 at 256 threads)
 
 __host__ __device__ inline int fft_lines_per_group(int N, int axis, const int n[3])
 {

@@ -9,10 +9,11 @@
 // two real fields.  Then:
 //   fft x    region E^n, B^n, J (real) -> the 5 packed arrays, transformed
 //            along x (one workgroup per batch of x lines, the lines held in
-//            LDS: iterative radix-2, bit-reversed load);
+//            LDS: iterative radix-2, bit-reversed load; twiddles from a
+//            table of the run);
 //   fft y    (3D) along y;
-//   line     along the last axis, a line and its mirror line (all other
-//            wavevector components negated) in LDS: forward transform,
+//   line     along the last axis, lines with their mirror lines (all
+//            other wavevector components negated) in LDS: forward transform,
 //            then for each wavevector k and its mirror -k together: split
 //            the packed pairs (the transform A of a real field has
 //            A(-k) = conj A(k), so Z = A + iB gives A = (Z(k) + conj

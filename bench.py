@@ -48,6 +48,9 @@ def workload(name):
                              name="thermal2048x256")
     if name == "cyl3d":
         return WL.cylinder_3d()
+    if name == "cyl3d_psatd":
+        import dataclasses
+        return dataclasses.replace(WL.cylinder_3d(), solver="psatd", name="cyl512x128x128_psatd")
     if name == "cyl3d_small":
         return WL.cylinder_3d(n=(128, 32, 32), radius=4.0)
     raise SystemExit(f"unknown workload {name}")

@@ -179,9 +179,9 @@ __device__ __forceinline__ void ifft_dif(double2 *buf, const double2 *tw, int lo
 // of the packed grid arrays; sign -1 forward, +1 inverse (unscaled).  A workgroup
 // transforms NL = max(1, FFT_BATCH / N) lines held in LDS (iterative
 // radix-2, bit-reversed load; an inverse transform conjugates its input and
-// its output).  Lines along
-// y or z are taken NL adjacent in x, so every row of the batch is a
-// contiguous read.  Grid: x = batch of lines, y = component.
+// its output).  Lines along y or z are taken NL adjacent in x, so every row
+// of the batch is a contiguous read.  Grid: x = batch of lines, y = packed
+// array.
 constexpr int FFT_BATCH = 2048;   // complex values per workgroup: 32 KB of LDS
 constexpr int SPEC_FFT_THREADS = 2 * BLOCK;   // three workgroups per CU (24 wavefronts; 20 at 256 threads)
 

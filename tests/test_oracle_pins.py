@@ -875,3 +875,33 @@ def test_psatd_response_to_a_current_mode(longitudinal):
     else:
         np.testing.assert_allclose(F[0:3], -math.sin(w * g.dt) / w * J, atol=1e-14)
         np.testing.assert_allclose(F[3:6], (1 - math.cos(w * g.dt)) / w ** 2 * _curl_h_of(g, J), atol=1e-14)
+
+
+@pytest.mark.parametrize("dims,n", [(2, (16, 8)), (3, (8, 4, 8))])
+def test_psatd_step_keeps_real_fields_real(monkeypatch, dims, n):
+    """The spectral step maps the spectra of real fields to spectra of real
+    fields: each lattice wavenumber k~_a multiplies a half-cell shift along
+    the same axis, so the step at -k of conj A(k) is the conjugate of the
+    step at k for every wavevector, the Nyquist planes (where the sampled
+    -pi/d stands for +pi/d) included.  The inverse transforms of random
+    fields, which carry every wavevector, then have no imaginary part.  (The
+    GPU path steps k and obtains -k by conjugation, so it relies on this.)"""
+    worst = []
+    orig = PS.from_spectrum
+
+    def recording(g, X, comp, ks):
+        z = np.fft.ifftn(X * PS._phase(ks, g, comp, +1.0), axes=(0, 1, 2))
+        worst.append(np.abs(z.imag).max() / np.abs(z.real).max())
+        return orig(g, X, comp, ks)
+
+    monkeypatch.setattr(PS, "from_spectrum", recording)
+    d = (0.1, 0.15, 0.12)[:dims]
+    g = O.Grid(dims, n, d, 0.9 * min(d))
+    rng = np.random.default_rng(5 + dims)
+    F = g.zeros_fields()
+    F[0:6] = rng.standard_normal(F[0:6].shape)
+    F[9:12] = rng.standard_normal(F[9:12].shape)
+    PS.init_fields(F)
+    PS.step_fields(g, F)
+    assert len(worst) == 6
+    assert max(worst) < 1e-13

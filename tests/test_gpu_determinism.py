@@ -193,6 +193,25 @@ def test_checkpoint_resume_is_bitwise_in_deterministic_mode(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32s"])
+def test_spectral_deterministic_twice_and_resume_bitwise(prec):
+    """The spectral field phase uses no atomics, so with the deterministic
+    current a spectral run is bitwise reproducible, and 50 steps, export,
+    re-init and 50 more equal 100 steps bitwise (the state of the spectral
+    solver is E^n and B^n, with Bm^n = B^n)."""
+    say(f"case: spectral deterministic twice and resume {prec}")
+    wl = dataclasses.replace(_lwfa_small(prec), nreg=(1, 1), solver="psatd", name="lwfa256x64_psatd")
+    ref = run_alone(wl, 100)
+    assert_bitwise(run_alone(wl, 100), ref, "second execution")
+    with B.Context([wl], track_ids=True, deterministic=True) as ctx:
+        ctx.step(50)
+        ck = ctx.checkpoint(0)
+    with B.Context([ck], track_ids=True, deterministic=True) as ctx:
+        got = state(ctx, 0, 50)
+    say(f"quantum {ref[2]['det_quantum']} relayouts {ref[2]['n_relayout']}")
+    assert_bitwise(got, ref, "resumed run")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32s"])
 def test_checkpoint_resume_matches_to_round_off(prec):
     say(f"case: 50 + export/re-init + 50 vs 100, plain mode {prec}")
     wl = _lwfa_small(prec)
